@@ -1,0 +1,194 @@
+/*
+ * mcproj — batched projection onto constraint manifolds, collision check and
+ * VJP through the projection, for AMD MI355X (gfx950).
+ *
+ * Method: arXiv 2604.13323 ("Vectorizing Projection in Manifold-Constrained
+ * Motion Planning for Real-Time Whole-Body Control"), Alg. 2 ParallelProject
+ * and getDescentStep with all constraint rows stacked in one block, followed by
+ * the collision check performed after projection (Sec. IV-A). The composite
+ * constraint F: R^d -> R^m and its Jacobian J follow Sec. II; a configuration
+ * satisfies the constraint when ||F(q)|| < tol.
+ *
+ * Conventions for every call:
+ *   - Return value: mc_status; MC_OK (0) on success. No call throws across the ABI.
+ *     Argument errors are reported synchronously, before anything is enqueued;
+ *     mc_last_error() then returns a message (thread-local, valid until the next
+ *     call on the same thread).
+ *   - Configuration arrays are structure-of-arrays: coordinate c of configuration i
+ *     lives at q[c * ld + i], with ld >= n. Element type is given by dtype
+ *     (MC_F32 = float, MC_F64 = double); resid and min_signed_dist use the same type.
+ *   - Every array argument is a caller-owned DEVICE pointer. The library reads and
+ *     writes them asynchronously on `stream` (a hipStream_t; 0 = the null stream);
+ *     they must stay alive until the stream has passed the call. The library never
+ *     keeps them. Input and output arrays must not overlap.
+ *   - n == 0 is a no-op returning MC_OK.
+ *   - A problem handle may be used by one stream at a time (calls on one problem
+ *     share a device work-queue counter).
+ *   - Numerical failure of a configuration is a per-configuration status, never a
+ *     call error.
+ */
+#ifndef MCPROJ_H
+#define MCPROJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MC_OK = 0,
+  MC_ERR_INVALID_ARG = 1, /* null pointer, negative size, ld < n, bad option value */
+  MC_ERR_UNSUPPORTED = 2, /* scene family or structure without a compiled kernel */
+  MC_ERR_HIP = 3,         /* a HIP runtime call failed (message has the HIP error) */
+  MC_ERR_OOM = 4          /* device allocation failed */
+} mc_status;
+
+typedef enum { MC_F32 = 0, MC_F64 = 1 } mc_dtype;
+
+/* Per-configuration outcome of the projection (status array values). */
+typedef enum {
+  MC_CONVERGED = 0, /* ||F(q)|| < tol reached after `iters` steps                         */
+  MC_MAX_ITER = 1,  /* max_iter steps taken without convergence                            */
+  MC_SINGULAR = 2,  /* J J^T not factorable even in FP64 (rank-deficient Jacobian)         */
+  MC_DIVERGED = 3,  /* a step longer than max_step (the paper's MaxDistance exit, Alg. 2)  */
+  MC_NONFINITE = 4  /* NaN or Inf in q, F or the step                                      */
+} mc_cfg_status;
+
+/* Collision verdict values. */
+enum { MC_FREE = 0, MC_COLLIDES = 1, MC_UNCHECKED = 2 };
+
+/* Scene families with compiled kernels (the scene blob's family field). */
+enum {
+  MC_FAMILY_SPHERE = 0,     /* q in R^3, F = q.q - 1, the configuration is a point robot        */
+  MC_FAMILY_LINEAR = 1,     /* F = A q - b, d <= 8, m <= 6, no collision geometry               */
+  MC_FAMILY_PLANAR2 = 2,    /* planar 2R arm, tip position (x, y) pose block                    */
+  MC_FAMILY_ARM7_AXIS = 3,  /* 7-DoF serial arm, end-effector z parallel to world z (2 rows)    */
+  MC_FAMILY_DUAL14_REL = 4, /* two 7-DoF arms, relative end-effector pose of Eq. 2 (6 rows)     */
+  MC_FAMILY_HUMANOID36 = 5  /* 36-DoF humanoid tree: feet poses (12), hands relative pose (6),
+                               centre-of-mass xy (2)                                           */
+};
+
+typedef struct mc_problem mc_problem; /* opaque; device-resident scene */
+
+typedef struct {
+  mc_dtype dtype;             /* element type of q_in/q_out/resid (and of the arithmetic:
+                                 MC_F32 = mixed precision, FP64 residual and iterate with an
+                                 FP32 Jacobian/Gram/Cholesky step and FP64 fallback;
+                                 MC_F64 = FP64 throughout)                                     */
+  double tol;                 /* convergence: ||F|| < tol (2-norm of the stacked rows), > 0      */
+  int32_t max_iter;           /* maximum number of Newton steps, 0..127                          */
+  double alpha;               /* step scale (Alg. 2 alpha), default 1                           */
+  double lambda;              /* damping (Alg. 2 lambda), >= 0, default 0                       */
+  double max_step;            /* > 0: DIVERGED when ||alpha * step|| > max_step; <= 0: off       */
+  double fp64_cond_threshold; /* FP32 mode: redo the step in FP64 when the FP32 Cholesky's
+                                 condition estimate (max L_ii / min L_ii)^2 exceeds this (1e6) */
+  int32_t check_collision;    /* 1: collision-check CONVERGED configurations into `verdict`      */
+  int32_t variant;            /* 0 auto (autotuned), 1 plain (one launch per geodesic),
+                                 2 fused (persistent work-queue kernel over the whole batch)     */
+  int32_t waves_per_block;    /* fused variant: 1, 2 or 4 wavefronts per workgroup (0 = auto)   */
+  int32_t blocks_per_cu;      /* fused variant: resident workgroups per CU for the persistent
+                                 grid (0 = auto)                                                */
+} mc_project_opts;
+
+/* Default options (tol 1e-6, max_iter 50, alpha 1, lambda 0, max_step off, threshold 1e6,
+   check on, variant auto). */
+void mc_default_opts(mc_project_opts* opts);
+
+/* Create a problem from a scene blob (format documented in the design doc; magic 'MCCS', version 1):
+   parses and validates the blob on the host, checks that its kinematic structure matches a
+   compiled family, derives the constants the kernels need (reference poses of blocks flagged
+   ref_from_qref, subtree masses, link bounding spheres, obstacle clusters) and copies them
+   to the current HIP device. The blob is not retained. *out receives the handle.
+   Errors: MC_ERR_INVALID_ARG (null, malformed blob), MC_ERR_UNSUPPORTED (no kernel for this
+   structure), MC_ERR_OOM / MC_ERR_HIP. */
+mc_status mc_problem_create(const void* scene_blob, size_t nbytes, mc_problem** out);
+
+/* Free the problem's device memory. Null is a no-op. The caller must make sure no enqueued
+   call still uses the problem. */
+void mc_problem_destroy(mc_problem* p);
+
+int32_t mc_problem_dof(const mc_problem* p);      /* d, or -1 for null */
+int32_t mc_problem_rows(const mc_problem* p);     /* m, or -1 for null */
+int32_t mc_problem_family(const mc_problem* p);   /* family, or -1 for null */
+
+/* Message of the last error on this thread ("" if none). */
+const char* mc_last_error(void);
+
+/* project_batch — Alg. 2 ParallelProject with per-configuration termination.
+   For each configuration i < n: q <- q_in[:, i]; repeat { F <- F(q); stop if ||F|| < tol or
+   after max_iter steps; dq <- alpha J^T (J J^T + lambda I)^-1 F; DIVERGED if max_step > 0 and
+   ||dq|| > max_step; q <- q - dq }, then (check_collision) the robot spheres at the projected
+   configuration are tested against the obstacle spheres (strict overlap).
+   Outputs (device, caller-owned, length n unless noted):
+     q_out [d][ld_out]  projected configuration (the last iterate for non-converged ones)
+     status int8       mc_cfg_status
+     iters  int8       steps taken
+     resid  dtype      ||F|| at the last evaluation
+     verdict uint8     nullable; MC_FREE / MC_COLLIDES, MC_UNCHECKED when not CONVERGED or
+                       check_collision == 0
+   geo_offsets (nullable, int32[n_geo + 1], device) describes the batch as n_geo geodesics
+   (CSR offsets, geo_offsets[0] = 0, geo_offsets[n_geo] = n). The plain variant needs it on the
+   HOST as well: pass geo_offsets_host (nullable) with the same content. geo_ok (nullable,
+   uint8[n_geo], device) receives 1 when every configuration of the geodesic converged and is
+   collision-free (the early exit of Alg. 2 as a per-geodesic flag).
+   Errors: MC_ERR_INVALID_ARG for null required pointers, n < 0, ld < n, tol <= 0,
+   max_iter outside 0..127, lambda < 0, alpha <= 0, dtype mismatch, plain variant without
+   geo_offsets_host. */
+mc_status project_batch(const mc_problem* p, int64_t n,
+                        const void* q_in, int64_t ld_in, void* q_out, int64_t ld_out,
+                        int8_t* status, int8_t* iters, void* resid, uint8_t* verdict,
+                        const int32_t* geo_offsets, const int32_t* geo_offsets_host, int32_t n_geo,
+                        uint8_t* geo_ok, const mc_project_opts* opts, void* stream);
+
+/* check_batch — collision check of arbitrary configurations (Sec. IV-A: robot spheres vs obstacle
+   spheres, collision when ||c_i - o_j||^2 < (r_i + r_j)^2 for some pair).
+   verdict uint8[n]: MC_FREE or MC_COLLIDES. min_signed_dist (nullable, dtype[n]): minimum over
+   all pairs of ||c_i - o_j|| - (r_i + r_j) (+inf without geometry); requesting it forces the
+   exhaustive pair loop. */
+mc_status check_batch(const mc_problem* p, int64_t n, const void* q, int64_t ld, mc_dtype dtype,
+                      uint8_t* verdict, void* min_signed_dist, void* stream);
+
+/* project_vjp — vector-Jacobian product through the converged projection (implicit
+   differentiation at the converged point): g_in = (I - J^+ J) g_out with J = J(q_proj),
+   computed as g_out - J^T (J J^T)^-1 J g_out. Exact for on-manifold inputs. In MC_F32 mode the
+   Gram solve runs in FP32 and switches to FP64 for configurations whose condition estimate
+   exceeds opts->fp64_cond_threshold. Configurations whose status is not MC_CONVERGED get
+   g_in = 0. Arrays q_proj, g_out, g_in are [d][ld] of opts->dtype. */
+mc_status project_vjp(const mc_problem* p, int64_t n, const void* q_proj, int64_t ld,
+                      const int8_t* status, const void* g_out, void* g_in,
+                      const mc_project_opts* opts, void* stream);
+
+/* interpolate_geodesics — the interpolation step of Alg. 2: geodesic g gets
+   L_g = geo_offsets[g+1] - geo_offsets[g] interior points q_a + t_k (q_b - q_a),
+   t_k = k / (L_g + 1), k = 1..L_g, written to q_out[:, geo_offsets[g] + k - 1].
+   endpoints [d][2 * n_geo] (column 2g = q_a, 2g+1 = q_b), ld_e >= 2 n_geo. */
+mc_status interpolate_geodesics(const mc_problem* p, int32_t n_geo, const int32_t* geo_offsets,
+                                const void* endpoints, int64_t ld_e, void* q_out, int64_t ld_out,
+                                mc_dtype dtype, void* stream);
+
+/* path_length_grad — path-length loss over geodesics and its gradient:
+   L = sum_g sum_i ||q_{i+1} - q_i||, g_out[:, i] = u_{i-1} - u_i with u = delta / max(||delta||, 1e-12)
+   (u taken as 0 outside the geodesic). loss (nullable, device, one dtype scalar) receives L
+   (accumulated atomically; it is zeroed by the call first). */
+mc_status path_length_grad(const mc_problem* p, int64_t n, const void* q, int64_t ld,
+                           const int32_t* geo_offsets, int32_t n_geo, void* g_out, void* loss,
+                           mc_dtype dtype, void* stream);
+
+/* mc_eval_residual_jacobian — diagnostic: the residual F [m][ld] and the Jacobian J [m*d][ld]
+   (row r, column c at (r * d + c) * ld + i) of n configurations, both in dtype, as the
+   projection kernels compute them (FP64 residual; analytic Jacobian columns in the step
+   precision). */
+mc_status mc_eval_residual_jacobian(const mc_problem* p, int64_t n, const void* q, int64_t ld,
+                                    mc_dtype dtype, void* F, void* J, void* stream);
+
+/* mc_fallback_count — number of FP64 step fallbacks taken by the calls enqueued on this problem
+   since it was created or last reset (reset = 1 zeroes it after reading). Synchronises the
+   device. */
+mc_status mc_fallback_count(const mc_problem* p, int reset, uint64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCPROJ_H */

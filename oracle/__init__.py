@@ -50,7 +50,7 @@ def lib():
         L.oracle_residual.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, ctypes.c_int]
         L.oracle_jacobian.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, ctypes.c_int]
         L.oracle_project.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, P, P, P, ctypes.c_double,
-                                     ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int]
+                                     ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, P]
         L.oracle_check.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, P, ctypes.c_int]
         L.oracle_vjp.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, P, P, P, ctypes.c_int]
         L.oracle_path_length.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_int32, P, P]
@@ -103,18 +103,23 @@ class Problem:
         assert lib().oracle_jacobian(*self._args(), q.shape[0], _p(q), _p(J), threads) == 0
         return J
 
-    def project(self, q, tol=1e-6, max_iter=50, alpha=1.0, lam=0.0, max_step=0.0, threads: int = 0):
+    def project(self, q, tol=1e-6, max_iter=50, alpha=1.0, lam=0.0, max_step=0.0, threads: int = 0,
+                path_info: bool = False):
+        """Returns (q_out, status, iters, resid) and, with path_info, an [n, 2] array holding the
+        smallest sigma_min(J) along each path and its longest step."""
         q = np.ascontiguousarray(q, np.float64).reshape(-1, self.d)
         n = q.shape[0]
         qo = np.zeros_like(q)
         st = np.zeros(n, np.int8)
         it = np.zeros(n, np.int32)
         rs = np.zeros(n, np.float64)
+        pi = np.zeros((n, 2)) if path_info else None
         rc = lib().oracle_project(*self._args(), n, _p(q), _p(qo), _p(st), _p(it), _p(rs), float(tol),
-                                  int(max_iter), float(alpha), float(lam), float(max_step), threads)
+                                  int(max_iter), float(alpha), float(lam), float(max_step), threads,
+                                  None if pi is None else _p(pi))
         if rc != 0:
             raise ValueError("oracle_project failed (%d)" % rc)
-        return qo, st, it, rs
+        return (qo, st, it, rs, pi) if path_info else (qo, st, it, rs)
 
     def check(self, q, threads: int = 0):
         q = np.ascontiguousarray(q, np.float64).reshape(-1, self.d)

@@ -399,8 +399,10 @@ bool all_finite(const double* x, int n) { for (int i = 0; i < n; ++i) if (!std::
 struct Opts { double tol; int max_iter; double alpha, lambda, max_step; };
 
 // Descent step delta with J delta ~= F: minimum-norm (lambda = 0) or damped (lambda > 0).
-// J is m x d row-major. Returns false on a singular Jacobian.
-bool descent_step(const Scene& s, const double* J, const double* F, double lambda, double* delta) {
+// J is m x d row-major. Returns false on a singular Jacobian. smin_out (nullable) receives
+// the smallest singular value of J.
+bool descent_step(const Scene& s, const double* J, const double* F, double lambda, double* delta,
+                  double* smin_out = nullptr) {
   const int m = s.m, d = s.d;
   // singularity test on J (= on J^T) by its singular values
   std::vector<double> At(size_t(d) * m);  // J^T, column-major d x m: column i = row i of J
@@ -409,6 +411,7 @@ bool descent_step(const Scene& s, const double* J, const double* F, double lambd
   jacobi_singular_values(d, m, At.data(), sv.data());
   double smax = 0, smin = INFINITY;
   for (double x : sv) { smax = std::max(smax, x); smin = std::min(smin, x); }
+  if (smin_out) *smin_out = smin;
   if (!(smax > 0.0) || smin / smax < 1e-12) return false;
   if (lambda <= 0.0) {
     // J^T = Q R. J delta = F  <=>  R^T (Q^T delta) = F; minimum-norm delta = Q z with R^T z = F.
@@ -445,11 +448,14 @@ bool descent_step(const Scene& s, const double* J, const double* F, double lambd
 double norm2(const double* x, int n) { double a = 0; for (int i = 0; i < n; ++i) a += x[i] * x[i]; return std::sqrt(a); }
 
 // ParallelProject for one configuration (Alg. 2), per-configuration termination.
+// path (nullable) receives {smallest sigma_min(J) over the steps taken, longest step}, used by
+// the parity tests to recognise ill-conditioned projection paths.
 void project_one(const Scene& s, const Targets& tg, const Opts& o, const double* q0, double* q,
-                 int8_t* status, int32_t* iters, double* resid) {
+                 int8_t* status, int32_t* iters, double* resid, double* path = nullptr) {
   const int d = s.d, m = s.m;
   std::vector<double> F(m), J(size_t(m) * d), delta(d);
   for (int j = 0; j < d; ++j) q[j] = q0[j];
+  if (path) { path[0] = INFINITY; path[1] = 0.0; }
   for (int k = 0;; ++k) {
     residual<double>(s, tg, q, F.data());
     double nF = norm2(F.data(), m);
@@ -460,8 +466,12 @@ void project_one(const Scene& s, const Targets& tg, const Opts& o, const double*
     if (k >= o.max_iter) { *status = ST_MAX_ITER; return; }
     jacobian(s, tg, q, J.data());
     if (!all_finite(J.data(), m * d)) { *status = ST_NONFINITE; return; }
-    if (!descent_step(s, J.data(), F.data(), o.lambda, delta.data())) { *status = ST_SINGULAR; return; }
+    double smin = 0.0;
+    const bool ok = descent_step(s, J.data(), F.data(), o.lambda, delta.data(), &smin);
+    if (path) path[0] = std::min(path[0], smin);
+    if (!ok) { *status = ST_SINGULAR; return; }
     for (int j = 0; j < d; ++j) delta[j] *= o.alpha;
+    if (path) path[1] = std::max(path[1], norm2(delta.data(), d));
     if (!all_finite(delta.data(), d)) { *status = ST_NONFINITE; return; }
     if (o.max_step > 0.0 && norm2(delta.data(), d) > o.max_step) { *status = ST_DIVERGED; return; }
     for (int j = 0; j < d; ++j) q[j] -= delta[j];
@@ -570,9 +580,10 @@ int oracle_jacobian(const void* blob, size_t nbytes, int64_t n, const double* q,
 }
 
 // Projection of n configurations (row-major [n][d]).
+// path_info (nullable) [n][2]: smallest sigma_min(J) along the path, longest step.
 int oracle_project(const void* blob, size_t nbytes, int64_t n, const double* q_in, double* q_out,
                    int8_t* status, int32_t* iters, double* resid, double tol, int32_t max_iter,
-                   double alpha, double lambda, double max_step, int nthreads) {
+                   double alpha, double lambda, double max_step, int nthreads, double* path_info) {
   Scene s;
   if (!parse(blob, nbytes, s)) return 1;
   if (n < 0 || !(tol > 0) || max_iter < 0) return 2;
@@ -580,7 +591,8 @@ int oracle_project(const void* blob, size_t nbytes, int64_t n, const double* q_i
   Opts o{tol, max_iter, alpha, lambda, max_step};
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads_or_default(nthreads))
   for (int64_t i = 0; i < n; ++i)
-    project_one(s, tg, o, q_in + i * s.d, q_out + i * s.d, status + i, iters + i, resid + i);
+    project_one(s, tg, o, q_in + i * s.d, q_out + i * s.d, status + i, iters + i, resid + i,
+                path_info ? path_info + 2 * i : nullptr);
   return 0;
 }
 

@@ -1,0 +1,281 @@
+"""ctypes binding of libmcproj (the HIP library); argument marshalling only.
+
+Configuration batches are torch tensors of shape [d, N] (structure of arrays: row c
+holds coordinate c of every configuration), float32 or float64, on the current HIP
+device. Every call is enqueued on torch's current stream. All arithmetic happens in
+the library's kernels; this module never computes on the data.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmcproj.so")
+
+MC_F32, MC_F64 = 0, 1
+CONVERGED, MAX_ITER, SINGULAR, DIVERGED, NONFINITE = range(5)
+FREE, COLLIDES, UNCHECKED = 0, 1, 2
+VARIANTS = {"auto": 0, "plain": 1, "fused": 2}
+
+
+class McError(RuntimeError):
+    pass
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("lambda_", ctypes.c_double), ("max_step", ctypes.c_double),
+                ("fp64_cond_threshold", ctypes.c_double), ("check_collision", ctypes.c_int32),
+                ("variant", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+
+
+_lib = None
+
+EXPORTS = ["mc_default_opts", "mc_problem_create", "mc_problem_destroy", "mc_problem_dof", "mc_problem_rows",
+           "mc_problem_family", "mc_last_error", "project_batch", "check_batch", "project_vjp",
+           "interpolate_geodesics", "path_length_grad", "mc_eval_residual_jacobian", "mc_fallback_count"]
+
+
+def lib():
+    """Load libmcproj.so. Raises when it has not been built: there is no fallback path."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise McError(f"HIP library {LIB_PATH} is missing: build it first (python -m paper_2604_13323_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    L.mc_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    L.mc_default_opts.restype = None
+    L.mc_problem_create.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(P)]
+    L.mc_problem_destroy.argtypes = [P]
+    L.mc_problem_destroy.restype = None
+    for f in ("mc_problem_dof", "mc_problem_rows", "mc_problem_family"):
+        getattr(L, f).argtypes = [P]
+        getattr(L, f).restype = I32
+    L.mc_last_error.argtypes = []
+    L.mc_last_error.restype = ctypes.c_char_p
+    L.project_batch.argtypes = [P, I64, P, I64, P, I64, P, P, P, P, P, P, I32, P, ctypes.POINTER(Opts), P]
+    L.check_batch.argtypes = [P, I64, P, I64, ctypes.c_int, P, P, P]
+    L.project_vjp.argtypes = [P, I64, P, I64, P, P, P, ctypes.POINTER(Opts), P]
+    L.interpolate_geodesics.argtypes = [P, I32, P, P, I64, P, I64, ctypes.c_int, P]
+    L.path_length_grad.argtypes = [P, I64, P, I64, P, I32, P, P, ctypes.c_int, P]
+    L.mc_eval_residual_jacobian.argtypes = [P, I64, P, I64, ctypes.c_int, P, P, P]
+    L.mc_fallback_count.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
+    for f in EXPORTS:
+        if f not in ("mc_default_opts", "mc_problem_destroy", "mc_problem_dof", "mc_problem_rows",
+                     "mc_problem_family", "mc_last_error"):
+            getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise McError(f"{what} failed ({rc}): {lib().mc_last_error().decode()}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return MC_F32
+    if t.dtype == torch.float64:
+        return MC_F64
+    raise McError(f"unsupported dtype {t.dtype}")
+
+
+def _soa(q: torch.Tensor, d: int, name: str):
+    if q.dim() != 2 or q.shape[0] != d:
+        raise McError(f"{name}: expected shape [{d}, N], got {tuple(q.shape)}")
+    if not q.is_cuda:
+        raise McError(f"{name}: expected a device tensor")
+    if q.stride(1) != 1:
+        raise McError(f"{name}: rows must be contiguous")
+    return q.shape[1], q.stride(0)
+
+
+def make_opts(dtype=MC_F32, tol=1e-6, max_iter=50, alpha=1.0, lam=0.0, max_step=0.0, cond=1e6, check=True,
+              variant="auto", waves_per_block=0, blocks_per_cu=0) -> Opts:
+    o = Opts()
+    lib().mc_default_opts(ctypes.byref(o))
+    o.dtype = dtype
+    o.tol = tol
+    o.max_iter = max_iter
+    o.alpha = alpha
+    o.lambda_ = lam
+    o.max_step = max_step
+    o.fp64_cond_threshold = cond
+    o.check_collision = 1 if check else 0
+    o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    o.waves_per_block = waves_per_block
+    o.blocks_per_cu = blocks_per_cu
+    return o
+
+
+@dataclass
+class ProjectResult:
+    q: torch.Tensor
+    status: torch.Tensor
+    iters: torch.Tensor
+    resid: torch.Tensor
+    verdict: torch.Tensor | None
+    geo_ok: torch.Tensor | None
+
+
+class Problem:
+    """A scene on the current HIP device (wraps mc_problem)."""
+
+    def __init__(self, blob: bytes):
+        self._blob = ctypes.create_string_buffer(bytes(blob), len(blob))
+        h = ctypes.c_void_p()
+        _check(lib().mc_problem_create(self._blob, len(blob), ctypes.byref(h)), "mc_problem_create")
+        self._h = h
+        self.d = int(lib().mc_problem_dof(h))
+        self.m = int(lib().mc_problem_rows(h))
+        self.family = int(lib().mc_problem_family(h))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            try:
+                torch.cuda.synchronize()
+            except Exception:
+                pass
+            _lib.mc_problem_destroy(h)
+            self._h = None
+
+    # -- projection -------------------------------------------------------
+    def project(self, q: torch.Tensor, tol=1e-6, max_iter=50, alpha=1.0, lam=0.0, max_step=0.0, cond=1e6,
+                check=True, variant="auto", geo_offsets=None, geo_ok=False, waves_per_block=0, blocks_per_cu=0,
+                out: ProjectResult | None = None) -> ProjectResult:
+        n, ld = _soa(q, self.d, "project")
+        dt = _dtype_code(q)
+        dev = q.device
+        if out is None:
+            out = ProjectResult(q=torch.empty((self.d, n), dtype=q.dtype, device=dev),
+                                status=torch.empty(n, dtype=torch.int8, device=dev),
+                                iters=torch.empty(n, dtype=torch.int8, device=dev),
+                                resid=torch.empty(n, dtype=q.dtype, device=dev),
+                                verdict=torch.empty(n, dtype=torch.uint8, device=dev),
+                                geo_ok=None)
+        offs_dev, offs_host, n_geo = None, None, 0
+        if geo_offsets is not None:
+            offs_np = np.ascontiguousarray(np.asarray(geo_offsets, dtype=np.int32))
+            n_geo = len(offs_np) - 1
+            offs_host = offs_np
+            offs_dev = geo_offsets if isinstance(geo_offsets, torch.Tensor) and geo_offsets.is_cuda else \
+                torch.from_numpy(offs_np).to(dev)
+            out._offs = offs_dev  # keep alive while the stream runs
+            if geo_ok and out.geo_ok is None:
+                out.geo_ok = torch.empty(n_geo, dtype=torch.uint8, device=dev)
+        o = make_opts(dt, tol, max_iter, alpha, lam, max_step, cond, check, variant, waves_per_block, blocks_per_cu)
+        rc = lib().project_batch(self._h, n, _ptr(q), ld, _ptr(out.q), out.q.stride(0), _ptr(out.status),
+                                 _ptr(out.iters), _ptr(out.resid), _ptr(out.verdict), _ptr(offs_dev),
+                                 None if offs_host is None else offs_host.ctypes.data_as(ctypes.c_void_p),
+                                 n_geo, _ptr(out.geo_ok) if geo_ok else None, ctypes.byref(o), _stream())
+        _check(rc, "project_batch")
+        return out
+
+    def check(self, q: torch.Tensor, min_signed_dist=False):
+        n, ld = _soa(q, self.d, "check")
+        v = torch.empty(n, dtype=torch.uint8, device=q.device)
+        sd = torch.empty(n, dtype=q.dtype, device=q.device) if min_signed_dist else None
+        _check(lib().check_batch(self._h, n, _ptr(q), ld, _dtype_code(q), _ptr(v), _ptr(sd), _stream()), "check_batch")
+        return (v, sd) if min_signed_dist else v
+
+    def vjp(self, q_proj: torch.Tensor, status: torch.Tensor, g_out: torch.Tensor, cond=1e6):
+        n, ld = _soa(q_proj, self.d, "vjp")
+        if g_out.shape != q_proj.shape or g_out.stride() != q_proj.stride() or g_out.dtype != q_proj.dtype:
+            g_out = g_out.to(q_proj.dtype).contiguous()
+            q_proj = q_proj.contiguous()
+            ld = q_proj.stride(0)
+        g_in = torch.empty_like(q_proj)
+        o = make_opts(_dtype_code(q_proj), cond=cond)
+        _check(lib().project_vjp(self._h, n, _ptr(q_proj), ld, _ptr(status), _ptr(g_out), _ptr(g_in),
+                                 ctypes.byref(o), _stream()), "project_vjp")
+        return g_in
+
+    def interpolate(self, endpoints: torch.Tensor, geo_offsets: torch.Tensor, total: int):
+        """endpoints [d, 2 n_geo] (columns 2g, 2g+1 = the two ends); geo_offsets int32 device [n_geo + 1]."""
+        n_geo = geo_offsets.numel() - 1
+        out = torch.empty((self.d, total), dtype=endpoints.dtype, device=endpoints.device)
+        _check(lib().interpolate_geodesics(self._h, n_geo, _ptr(geo_offsets), _ptr(endpoints), endpoints.stride(0),
+                                           _ptr(out), out.stride(0), _dtype_code(endpoints), _stream()),
+               "interpolate_geodesics")
+        return out
+
+    def path_length_grad(self, q: torch.Tensor, geo_offsets: torch.Tensor, with_loss=True):
+        n, ld = _soa(q, self.d, "path_length_grad")
+        g = torch.empty_like(q)
+        loss = torch.empty(1, dtype=q.dtype, device=q.device) if with_loss else None
+        _check(lib().path_length_grad(self._h, n, _ptr(q), ld, _ptr(geo_offsets), geo_offsets.numel() - 1, _ptr(g),
+                                      _ptr(loss), _dtype_code(q), _stream()), "path_length_grad")
+        return g, loss
+
+    def eval_fj(self, q: torch.Tensor):
+        n, ld = _soa(q, self.d, "eval_fj")
+        F = torch.empty((self.m, n), dtype=q.dtype, device=q.device)
+        J = torch.empty((self.m * self.d, n), dtype=q.dtype, device=q.device)
+        if ld != n:
+            q = q.contiguous()
+        _check(lib().mc_eval_residual_jacobian(self._h, n, _ptr(q), n, _dtype_code(q), _ptr(F), _ptr(J), _stream()),
+               "mc_eval_residual_jacobian")
+        return F, J
+
+    def fallback_count(self, reset=False) -> int:
+        c = ctypes.c_uint64()
+        _check(lib().mc_fallback_count(self._h, 1 if reset else 0, ctypes.byref(c)), "mc_fallback_count")
+        return int(c.value)
+
+
+class ProjectFn(torch.autograd.Function):
+    """q_proj = P(q_in); backward gives (I - J^+ J) g at q_proj (implicit differentiation at
+    convergence). Only q_proj and status are saved: the backward kernel recomputes the
+    kinematics and the Jacobian."""
+
+    @staticmethod
+    def forward(ctx, q_in: torch.Tensor, problem: Problem, kwargs: dict):
+        r = problem.project(q_in.detach(), **kwargs)
+        ctx.problem = problem
+        ctx.cond = kwargs.get("cond", 1e6)
+        ctx.save_for_backward(r.q, r.status)
+        ctx.mark_non_differentiable(r.status)
+        return r.q, r.status
+
+    @staticmethod
+    def backward(ctx, g_q, g_status):
+        q, status = ctx.saved_tensors
+        g_in = ctx.problem.vjp(q, status, g_q.contiguous(), cond=ctx.cond)
+        return g_in, None, None
+
+
+def project(q_in: torch.Tensor, problem: Problem, **kwargs):
+    """Differentiable projection: returns (q_proj, status)."""
+    return ProjectFn.apply(q_in, problem, kwargs)
+
+
+class PathLengthFn(torch.autograd.Function):
+    """Path length summed over geodesics (CSR offsets); gradient from the library kernel."""
+
+    @staticmethod
+    def forward(ctx, q: torch.Tensor, problem: Problem, geo_offsets: torch.Tensor):
+        g, loss = problem.path_length_grad(q.detach(), geo_offsets)
+        ctx.save_for_backward(g)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, gl):
+        (g,) = ctx.saved_tensors
+        return g * gl, None, None

@@ -1,0 +1,792 @@
+// C-ABI of the mcproj library: problem lifecycle, argument validation, dispatch of the
+// per-family kernels, and the small utility kernels (work-queue reset, geodesic
+// interpolation, path-length gradient, per-geodesic success flags).
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mcproj.h"
+#include "kin.hpp"
+#include "ops.hpp"
+
+using namespace mc;
+
+namespace {
+
+thread_local std::string g_err;
+
+mc_status fail(mc_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+mc_status hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? MC_ERR_OOM : MC_ERR_HIP;
+}
+
+// ------------------------------------------------------------------ host scene
+struct HJoint { int parent, type, axis; double R[9], p[3]; };
+struct HFrame { int link; double R[9], p[3]; };
+struct HBlock { int type, fa, fb, mask, ref_from_qref; double R[9], p[3], target[3]; };
+struct HSphere { int link; double c[3], r; };
+struct HScene {
+  int family = 0, d = 0, m = 0;
+  std::vector<HJoint> joints;
+  std::vector<double> mass;
+  std::vector<std::array<double, 3>> com;
+  std::vector<HFrame> frames;
+  std::vector<HBlock> blocks;
+  std::vector<HSphere> spheres;
+  std::vector<std::array<double, 4>> obs;
+  std::vector<double> qref, A, b;
+};
+
+struct Cursor {
+  const unsigned char* p;
+  size_t n, off = 0;
+  bool ok = true;
+  template <class T> T get() {
+    T v{};
+    if (off + sizeof(T) > n) { ok = false; return v; }
+    std::memcpy(&v, p + off, sizeof(T));
+    off += sizeof(T);
+    return v;
+  }
+  void getd(double* d, int k) { for (int i = 0; i < k; ++i) d[i] = get<double>(); }
+};
+
+bool parse_blob(const void* blob, size_t nbytes, HScene& s, std::string& err) {
+  Cursor c{static_cast<const unsigned char*>(blob), nbytes};
+  int32_t h[16];
+  for (int i = 0; i < 16; ++i) h[i] = c.get<int32_t>();
+  if (!c.ok || h[0] != 0x5343434D) { err = "scene blob: bad magic or truncated header"; return false; }
+  if (h[1] != 1) { err = "scene blob: unsupported version"; return false; }
+  s.family = h[2]; s.d = h[3]; s.m = h[4];
+  const int nj = h[5], nf = h[6], nb = h[7], ns = h[8], no = h[9], has_qref = h[10], has_lin = h[11];
+  if (s.d <= 0 || s.m <= 0 || nj < 0 || nf < 0 || nb <= 0 || ns < 0 || no < 0 || nj > 4096 || nf > 4096 ||
+      nb > 4096 || ns > 1 << 20 || no > 1 << 24 || s.d > 4096 || s.m > 4096) {
+    err = "scene blob: bad counts"; return false;
+  }
+  s.joints.resize(nj);
+  for (auto& j : s.joints) {
+    j.parent = c.get<int32_t>(); j.type = c.get<int32_t>(); j.axis = c.get<int32_t>(); c.get<int32_t>();
+    c.getd(j.R, 9); c.getd(j.p, 3);
+  }
+  s.mass.resize(nj); s.com.resize(nj);
+  for (int k = 0; k < nj; ++k) { s.mass[k] = c.get<double>(); c.getd(s.com[k].data(), 3); }
+  s.frames.resize(nf);
+  for (auto& f : s.frames) { f.link = c.get<int32_t>(); c.get<int32_t>(); c.getd(f.R, 9); c.getd(f.p, 3); }
+  s.blocks.resize(nb);
+  for (auto& b : s.blocks) {
+    b.type = c.get<int32_t>(); b.fa = c.get<int32_t>(); b.fb = c.get<int32_t>(); b.mask = c.get<int32_t>();
+    b.ref_from_qref = c.get<int32_t>(); c.get<int32_t>();
+    c.getd(b.R, 9); c.getd(b.p, 3); c.getd(b.target, 3);
+  }
+  s.spheres.resize(ns);
+  for (auto& sp : s.spheres) { sp.link = c.get<int32_t>(); c.get<int32_t>(); c.getd(sp.c, 3); sp.r = c.get<double>(); }
+  s.obs.resize(no);
+  for (auto& o : s.obs) c.getd(o.data(), 4);
+  if (has_qref) { s.qref.resize(s.d); c.getd(s.qref.data(), s.d); }
+  if (has_lin) { s.A.resize(size_t(s.m) * s.d); c.getd(s.A.data(), s.m * s.d); s.b.resize(s.m); c.getd(s.b.data(), s.m); }
+  if (!c.ok) { err = "scene blob: truncated"; return false; }
+  for (int j = 0; j < nj; ++j) {
+    const auto& J = s.joints[j];
+    if (J.parent < -1 || J.parent >= j || (J.type != 0 && J.type != 1) || J.axis < 0 || J.axis > 2) {
+      err = "scene blob: bad joint " + std::to_string(j); return false;
+    }
+  }
+  for (const auto& f : s.frames) if (f.link < 0 || f.link >= nj) { err = "scene blob: bad frame link"; return false; }
+  for (const auto& sp : s.spheres) if (sp.link < -1 || sp.link >= nj || !(sp.r >= 0)) { err = "scene blob: bad sphere"; return false; }
+  for (const auto& o : s.obs) if (!(o[3] >= 0) || !std::isfinite(o[0] + o[1] + o[2])) { err = "scene blob: bad obstacle"; return false; }
+  for (const auto& b : s.blocks) if (b.ref_from_qref && !has_qref) { err = "scene blob: block needs q_ref"; return false; }
+  return true;
+}
+
+// ---- host forward kinematics (reference poses at q_ref, at create time only)
+struct HT { double R[9], p[3]; };
+HT ht_mul(const HT& a, const HT& b) {
+  HT c;
+  for (int i = 0; i < 3; ++i) {
+    for (int k = 0; k < 3; ++k) c.R[3 * i + k] = a.R[3 * i] * b.R[k] + a.R[3 * i + 1] * b.R[3 + k] + a.R[3 * i + 2] * b.R[6 + k];
+    c.p[i] = a.R[3 * i] * b.p[0] + a.R[3 * i + 1] * b.p[1] + a.R[3 * i + 2] * b.p[2] + a.p[i];
+  }
+  return c;
+}
+HT ht_inv(const HT& a) {
+  HT c;
+  for (int i = 0; i < 3; ++i) for (int k = 0; k < 3; ++k) c.R[3 * i + k] = a.R[3 * k + i];
+  for (int i = 0; i < 3; ++i) c.p[i] = -(c.R[3 * i] * a.p[0] + c.R[3 * i + 1] * a.p[1] + c.R[3 * i + 2] * a.p[2]);
+  return c;
+}
+HT ht_make(const double* R, const double* p) {
+  HT t;
+  std::memcpy(t.R, R, sizeof t.R);
+  std::memcpy(t.p, p, sizeof t.p);
+  return t;
+}
+std::vector<HT> host_fk(const HScene& s, const double* q) {
+  std::vector<HT> L(s.joints.size());
+  for (size_t j = 0; j < s.joints.size(); ++j) {
+    const auto& J = s.joints[j];
+    HT base;
+    if (J.parent < 0) {
+      for (int k = 0; k < 9; ++k) base.R[k] = (k % 4 == 0) ? 1.0 : 0.0;
+      base.p[0] = base.p[1] = base.p[2] = 0.0;
+    } else {
+      base = L[J.parent];
+    }
+    HT t = ht_mul(base, ht_make(J.R, J.p));
+    HT m;
+    for (int k = 0; k < 9; ++k) m.R[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    m.p[0] = m.p[1] = m.p[2] = 0.0;
+    if (J.type == 1) {
+      m.p[J.axis] = q[j];
+    } else {
+      const double c = std::cos(q[j]), sn = std::sin(q[j]);
+      const int i = (J.axis + 1) % 3, k = (J.axis + 2) % 3;
+      m.R[3 * i + i] = c; m.R[3 * i + k] = -sn; m.R[3 * k + i] = sn; m.R[3 * k + k] = c;
+    }
+    L[j] = ht_mul(t, m);
+  }
+  return L;
+}
+
+// ---- compiled-structure check
+bool is_identity(const double* R) {
+  for (int k = 0; k < 9; ++k)
+    if (std::fabs(R[k] - ((k % 4 == 0) ? 1.0 : 0.0)) > 1e-12) return false;
+  return true;
+}
+
+template <class Topo>
+bool matches_topology(const HScene& s, std::string& err) {
+  using KI = KInfo<Topo>;
+  if ((int)s.joints.size() != Topo::NJ || s.d != Topo::NJ) { err = "joint count does not match the compiled family"; return false; }
+  if (s.m != Topo::M) { err = "row count does not match the compiled family"; return false; }
+  for (int j = 0; j < Topo::NJ; ++j) {
+    if (s.joints[j].parent != Topo::parent[j] || s.joints[j].type != Topo::jtype[j] || s.joints[j].axis != Topo::axis[j]) {
+      err = "joint " + std::to_string(j) + " does not match the compiled family"; return false;
+    }
+    if (!Topo::origin_rot && !is_identity(s.joints[j].R)) { err = "family expects pure-translation joint origins"; return false; }
+    if (Topo::has_com && Topo::massless(j) && (s.mass[j] != 0.0)) {
+      err = "family expects massless link " + std::to_string(j);
+      return false;
+    }
+  }
+  if ((int)s.frames.size() != Topo::NF) { err = "frame count does not match the compiled family"; return false; }
+  for (int f = 0; f < Topo::NF; ++f) {
+    if (s.frames[f].link != Topo::frame_link[f]) { err = "frame link does not match the compiled family"; return false; }
+    if (!Topo::frame_rot && !is_identity(s.frames[f].R)) { err = "family expects pure-translation frame offsets"; return false; }
+  }
+  if ((int)s.blocks.size() != Topo::NB) { err = "block count does not match the compiled family"; return false; }
+  for (int b = 0; b < Topo::NB; ++b) {
+    const auto& B = s.blocks[b];
+    if (B.type != Topo::btype[b]) { err = "block type does not match the compiled family"; return false; }
+    if ((B.type == B_POSE || B.type == B_REL || B.type == B_AXIS) && B.fa != Topo::bfa[b]) { err = "block frame mismatch"; return false; }
+    if (B.type == B_REL && B.fb != Topo::bfb[b]) { err = "block frame mismatch"; return false; }
+    if ((B.type == B_POSE || B.type == B_REL) && B.mask != Topo::bmask[b]) { err = "block row mask mismatch"; return false; }
+    if (B.type == B_COM && !Topo::has_com) { err = "unexpected CoM block"; return false; }
+  }
+  for (const auto& sp : s.spheres)
+    if (sp.link < 0 || !Topo::may_have_spheres(sp.link)) { err = "sphere on a link without geometry slot"; return false; }
+  (void)sizeof(KI);
+  return true;
+}
+
+const FamilyOps* ops_for(int family, int f64) {
+  switch (family) {
+    case MC_FAMILY_SPHERE: return f64 ? &ops_sphere3_f64 : &ops_sphere3_f32;
+    case MC_FAMILY_LINEAR: return f64 ? &ops_linear_f64 : &ops_linear_f32;
+    case MC_FAMILY_PLANAR2: return f64 ? &ops_planar2_f64 : &ops_planar2_f32;
+    case MC_FAMILY_ARM7_AXIS: return f64 ? &ops_arm7_axis_f64 : &ops_arm7_axis_f32;
+    case MC_FAMILY_DUAL14_REL: return f64 ? &ops_dual14_rel_f64 : &ops_dual14_rel_f32;
+    case MC_FAMILY_HUMANOID36: return f64 ? &ops_humanoid36_f64 : &ops_humanoid36_f32;
+  }
+  return nullptr;
+}
+
+bool validate_family(const HScene& s, std::string& err) {
+  switch (s.family) {
+    case MC_FAMILY_SPHERE:
+      if (s.d != 3 || s.m != 1 || !s.joints.empty() || s.blocks.size() != 1 || s.blocks[0].type != B_SPHERE) {
+        err = "sphere family: expects d = 3, m = 1, one SPHERE block, no joints"; return false;
+      }
+      if (s.spheres.size() > 1 || (s.spheres.size() == 1 && s.spheres[0].link != -1)) {
+        err = "sphere family: at most one point-robot sphere (link -1)"; return false;
+      }
+      return true;
+    case MC_FAMILY_LINEAR:
+      if (s.d > LIN_D || s.m > LIN_M || s.m > s.d || !s.joints.empty() || s.blocks.size() != 1 ||
+          s.blocks[0].type != B_LINEAR || s.A.empty() || !s.spheres.empty()) {
+        err = "linear family: expects d <= 8, m <= min(6, d), one LINEAR block, no joints or spheres"; return false;
+      }
+      return true;
+    case MC_FAMILY_PLANAR2: return matches_topology<TopoPlanar2>(s, err);
+    case MC_FAMILY_ARM7_AXIS: return matches_topology<TopoArm7Axis>(s, err);
+    case MC_FAMILY_DUAL14_REL: return matches_topology<TopoDual14Rel>(s, err);
+    case MC_FAMILY_HUMANOID36: return matches_topology<TopoHumanoid36>(s, err);
+  }
+  err = "unknown scene family " + std::to_string(s.family);
+  return false;
+}
+
+// ---- obstacle clusters: recursive median split on the widest axis, <= kClusterSize each
+constexpr int kClusterSize = 16;
+constexpr double kBoundMargin = 1e-4;  // metres added to every bounding radius (covers FP32 rounding)
+
+void build_clusters(std::vector<std::array<double, 4>>& obs, int lo, int hi,
+                    std::vector<std::array<double, 4>>& cl, std::vector<std::array<int, 2>>& rg) {
+  if (hi - lo <= kClusterSize) {
+    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+    for (int i = lo; i < hi; ++i)
+      for (int a = 0; a < 3; ++a) { mn[a] = std::min(mn[a], obs[i][a]); mx[a] = std::max(mx[a], obs[i][a]); }
+    std::array<double, 4> c{0.5 * (mn[0] + mx[0]), 0.5 * (mn[1] + mx[1]), 0.5 * (mn[2] + mx[2]), 0.0};
+    for (int i = lo; i < hi; ++i) {
+      const double dx = obs[i][0] - c[0], dy = obs[i][1] - c[1], dz = obs[i][2] - c[2];
+      c[3] = std::max(c[3], std::sqrt(dx * dx + dy * dy + dz * dz) + obs[i][3]);
+    }
+    c[3] += kBoundMargin;
+    cl.push_back(c);
+    rg.push_back({lo, hi});
+    return;
+  }
+  double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+  for (int i = lo; i < hi; ++i)
+    for (int a = 0; a < 3; ++a) { mn[a] = std::min(mn[a], obs[i][a]); mx[a] = std::max(mx[a], obs[i][a]); }
+  int ax = 0;
+  for (int a = 1; a < 3; ++a) if (mx[a] - mn[a] > mx[ax] - mn[ax]) ax = a;
+  const int mid = (lo + hi) / 2;
+  std::nth_element(obs.begin() + lo, obs.begin() + mid, obs.begin() + hi,
+                   [ax](const std::array<double, 4>& x, const std::array<double, 4>& y) { return x[ax] < y[ax]; });
+  build_clusters(obs, lo, mid, cl, rg);
+  build_clusters(obs, mid, hi, cl, rg);
+}
+
+template <class T>
+void fill_tp(TP<T>& t, const HScene& s, const std::vector<HT>& tref, const std::vector<double>& submass, double Mtot) {
+  std::memset(&t, 0, sizeof(TP<T>));
+  for (size_t j = 0; j < s.joints.size() && j < MAXJ; ++j) {
+    for (int k = 0; k < 9; ++k) t.jR[j][k] = T(s.joints[j].R[k]);
+    for (int k = 0; k < 3; ++k) t.jp[j][k] = T(s.joints[j].p[k]);
+    t.mass[j] = T(s.mass[j]);
+    for (int k = 0; k < 3; ++k) t.mcom[j][k] = T(s.mass[j] * s.com[j][k]);
+    t.submass[j] = T(submass[j]);
+  }
+  for (size_t f = 0; f < s.frames.size() && f < MAXF; ++f) {
+    for (int k = 0; k < 9; ++k) t.fR[f][k] = T(s.frames[f].R[k]);
+    for (int k = 0; k < 3; ++k) t.fp[f][k] = T(s.frames[f].p[k]);
+  }
+  for (size_t b = 0; b < s.blocks.size() && b < MAXB; ++b) {
+    const HT& r = tref[b];
+    for (int i = 0; i < 3; ++i) for (int k = 0; k < 3; ++k) t.refRt[b][3 * i + k] = T(r.R[3 * k + i]);
+    for (int k = 0; k < 3; ++k) t.refp[b][k] = T(r.p[k]);
+    for (int k = 0; k < 3; ++k) t.target[b][k] = T(s.blocks[b].target[k]);
+  }
+  t.inv_total_mass = Mtot > 0 ? T(1.0 / Mtot) : T(0);
+  if (s.family == MC_FAMILY_LINEAR) {
+    for (int r = 0; r < s.m; ++r) {
+      for (int c = 0; c < s.d; ++c) t.A[r][c] = T(s.A[size_t(r) * s.d + c]);
+      t.b[r] = T(s.b[r]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ utility kernels
+__global__ void k_reset_u32(unsigned int* p) { *p = 0u; }
+
+__global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <class IO>
+__global__ void k_zero1(IO* p) { *p = IO(0); }
+
+__device__ __forceinline__ int find_geo(const int32_t* offs, int n_geo, int64_t i) {
+  int lo = 0, hi = n_geo;  // offs[lo] <= i < offs[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (offs[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <class IO>
+__global__ void k_interpolate(int n_geo, const int32_t* offs, const IO* e, int64_t ld_e, IO* q, int64_t ld, int d) {
+  const int64_t total = offs[n_geo];
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int g = find_geo(offs, n_geo, i);
+  const int L = offs[g + 1] - offs[g];
+  if (L <= 0) return;
+  const double t = double(i - offs[g] + 1) / double(L + 1);
+  for (int c = 0; c < d; ++c) {
+    const double a = double(e[c * ld_e + 2 * g]), b = double(e[c * ld_e + 2 * g + 1]);
+    q[c * ld + i] = IO(a + t * (b - a));
+  }
+}
+
+template <class IO>
+__global__ void k_path_grad(int64_t n, const IO* q, int64_t ld, const int32_t* offs, int n_geo, IO* g, IO* loss, int d) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  double seg = 0.0;
+  if (i < n) {
+    const int gi = find_geo(offs, n_geo, i);
+    const bool has_prev = i > offs[gi], has_next = i + 1 < offs[gi + 1] && i + 1 < n;
+    double np = 0.0, nn = 0.0;
+    for (int c = 0; c < d; ++c) {
+      const double x = double(q[c * ld + i]);
+      if (has_prev) { const double t = x - double(q[c * ld + i - 1]); np += t * t; }
+      if (has_next) { const double t = double(q[c * ld + i + 1]) - x; nn += t * t; }
+    }
+    np = sqrt(np);
+    nn = sqrt(nn);
+    const double ip = 1.0 / fmax(np, 1e-12), in = 1.0 / fmax(nn, 1e-12);
+    for (int c = 0; c < d; ++c) {
+      const double x = double(q[c * ld + i]);
+      double gr = 0.0;
+      if (has_prev) gr += (x - double(q[c * ld + i - 1])) * ip;  // u_{i-1}
+      if (has_next) gr -= (double(q[c * ld + i + 1]) - x) * in;  // -u_i
+      g[c * ld + i] = IO(gr);
+    }
+    if (has_next) seg = nn;
+  }
+  // wave reduction, one atomic per wave
+  for (int off = 32; off > 0; off >>= 1) seg += __shfl_xor(seg, off);
+  if (loss && (threadIdx.x & 63) == 0 && seg != 0.0) atomicAdd(loss, IO(seg));
+}
+
+__global__ void k_geo_ok(int n_geo, const int32_t* offs, int64_t n, const int8_t* status, const uint8_t* verdict, uint8_t* ok) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_geo) return;
+  uint8_t r = 1;
+  const int64_t lo = offs[g] < 0 ? 0 : offs[g];
+  const int64_t hi = offs[g + 1] < n ? offs[g + 1] : n;
+  for (int64_t i = lo; i < hi; ++i) {
+    if (status[i] != ST_CONVERGED) r = 0;
+    if (verdict && verdict[i] != V_FREE) r = 0;
+  }
+  ok[g] = r;
+}
+
+}  // namespace
+
+struct mc_problem {
+  int family = 0, d = 0, m = 0, device = 0, n_cu = 0;
+  size_t max_lds_per_block = 0;
+  DevProblem* dev = nullptr;
+  float4* obs = nullptr;
+  float4* clus = nullptr;
+  int2* clus_range = nullptr;
+  unsigned int* counter = nullptr;
+  unsigned long long* fallback = nullptr;
+};
+
+extern "C" {
+
+const char* mc_last_error(void) { return g_err.c_str(); }
+
+void mc_default_opts(mc_project_opts* o) {
+  if (!o) return;
+  o->dtype = MC_F32;
+  o->tol = 1e-6;
+  o->max_iter = 50;
+  o->alpha = 1.0;
+  o->lambda = 0.0;
+  o->max_step = 0.0;
+  o->fp64_cond_threshold = 1e6;
+  o->check_collision = 1;
+  o->variant = 0;
+  o->waves_per_block = 0;
+  o->blocks_per_cu = 0;
+}
+
+int32_t mc_problem_dof(const mc_problem* p) { return p ? p->d : -1; }
+int32_t mc_problem_rows(const mc_problem* p) { return p ? p->m : -1; }
+int32_t mc_problem_family(const mc_problem* p) { return p ? p->family : -1; }
+
+void mc_problem_destroy(mc_problem* p) {
+  if (!p) return;
+  hipFree(p->dev);
+  hipFree(p->obs);
+  hipFree(p->clus);
+  hipFree(p->clus_range);
+  hipFree(p->counter);
+  hipFree(p->fallback);
+  delete p;
+}
+
+mc_status mc_problem_create(const void* blob, size_t nbytes, mc_problem** out) {
+  g_err.clear();
+  if (!blob || !out) return fail(MC_ERR_INVALID_ARG, "mc_problem_create: null argument");
+  *out = nullptr;
+  HScene s;
+  std::string err;
+  if (!parse_blob(blob, nbytes, s, err)) return fail(MC_ERR_INVALID_ARG, err);
+  if (!validate_family(s, err)) return fail(MC_ERR_UNSUPPORTED, err);
+  if (s.spheres.size() > size_t(MAXS)) return fail(MC_ERR_UNSUPPORTED, "too many robot spheres");
+
+  // reference poses of blocks
+  std::vector<HT> tref(s.blocks.size());
+  std::vector<HT> Lref;
+  if (!s.qref.empty() && !s.joints.empty()) Lref = host_fk(s, s.qref.data());
+  auto frame_at = [&](int f) { return ht_mul(Lref[s.frames[f].link], ht_make(s.frames[f].R, s.frames[f].p)); };
+  for (size_t b = 0; b < s.blocks.size(); ++b) {
+    const auto& B = s.blocks[b];
+    if (B.ref_from_qref && B.type == B_POSE) tref[b] = frame_at(B.fa);
+    else if (B.ref_from_qref && B.type == B_REL) tref[b] = ht_mul(ht_inv(frame_at(B.fa)), frame_at(B.fb));
+    else tref[b] = ht_make(B.R, B.p);
+  }
+  // subtree masses (joints are in depth-first preorder; parent < child)
+  std::vector<double> submass(s.joints.size(), 0.0);
+  double Mtot = 0.0;
+  for (int j = int(s.joints.size()) - 1; j >= 0; --j) {
+    submass[j] += s.mass[j];
+    if (s.joints[j].parent >= 0) submass[s.joints[j].parent] += submass[j];
+    Mtot += s.mass[j];
+  }
+
+  DevProblem* hp = new DevProblem;
+  std::memset(hp, 0, sizeof(DevProblem));
+  fill_tp<double>(hp->d, s, tref, submass, Mtot);
+  fill_tp<float>(hp->f, s, tref, submass, Mtot);
+  hp->dof = s.d;
+  hp->rows = s.m;
+  hp->family = s.family;
+  hp->lin_d = s.family == MC_FAMILY_LINEAR ? s.d : 0;
+  hp->lin_m = s.family == MC_FAMILY_LINEAR ? s.m : 0;
+
+  // robot spheres grouped by link, link bounding spheres
+  std::vector<HSphere> sph = s.spheres;
+  std::stable_sort(sph.begin(), sph.end(), [](const HSphere& a, const HSphere& b) { return a.link < b.link; });
+  hp->n_sph = int(sph.size());
+  hp->point_sph = make_float4(0.f, 0.f, 0.f, -1.f);
+  int idx = 0;
+  for (int l = 0; l <= MAXJ; ++l) hp->sph_begin[l] = 0;
+  std::vector<HSphere> linked;
+  for (const auto& sp : sph) {
+    if (sp.link < 0) hp->point_sph = make_float4(float(sp.c[0]), float(sp.c[1]), float(sp.c[2]), float(sp.r));
+    else linked.push_back(sp);
+  }
+  if (s.family == MC_FAMILY_SPHERE && sph.empty()) hp->point_sph = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int l = 0; l < MAXJ; ++l) {
+    hp->sph_begin[l] = idx;
+    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+    const int first = idx;
+    for (const auto& sp : linked) {
+      if (sp.link != l) continue;
+      hp->sph[idx++] = make_float4(float(sp.c[0]), float(sp.c[1]), float(sp.c[2]), float(sp.r));
+      for (int a = 0; a < 3; ++a) { mn[a] = std::min(mn[a], sp.c[a]); mx[a] = std::max(mx[a], sp.c[a]); }
+    }
+    if (idx > first) {
+      const double c[3] = {0.5 * (mn[0] + mx[0]), 0.5 * (mn[1] + mx[1]), 0.5 * (mn[2] + mx[2])};
+      double r = 0.0;
+      for (const auto& sp : linked) {
+        if (sp.link != l) continue;
+        const double dx = sp.c[0] - c[0], dy = sp.c[1] - c[1], dz = sp.c[2] - c[2];
+        r = std::max(r, std::sqrt(dx * dx + dy * dy + dz * dz) + sp.r);
+      }
+      hp->link_bs[l] = make_float4(float(c[0]), float(c[1]), float(c[2]), float(r + kBoundMargin));
+    } else {
+      hp->link_bs[l] = make_float4(0.f, 0.f, 0.f, -1.f);
+    }
+  }
+  hp->sph_begin[MAXJ] = idx;
+
+  // obstacle clusters
+  std::vector<std::array<double, 4>> obs = s.obs;
+  std::vector<std::array<double, 4>> cl;
+  std::vector<std::array<int, 2>> rg;
+  if (!obs.empty()) build_clusters(obs, 0, int(obs.size()), cl, rg);
+  hp->n_obs = int(obs.size());
+  hp->n_clus = int(cl.size());
+  std::vector<float4> obs_f(obs.size()), cl_f(cl.size());
+  std::vector<int2> rg_i(rg.size());
+  for (size_t i = 0; i < obs.size(); ++i) obs_f[i] = make_float4(float(obs[i][0]), float(obs[i][1]), float(obs[i][2]), float(obs[i][3]));
+  for (size_t i = 0; i < cl.size(); ++i) {
+    cl_f[i] = make_float4(float(cl[i][0]), float(cl[i][1]), float(cl[i][2]), float(cl[i][3]));
+    rg_i[i] = make_int2(rg[i][0], rg[i][1]);
+  }
+
+  mc_problem* p = new mc_problem;
+  p->family = s.family;
+  p->d = s.d;
+  p->m = s.m;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) { delete p; delete hp; return hip_fail(e, "hipGetDevice"); }
+  hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device);
+  int lds = 0;
+  hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
+  p->max_lds_per_block = size_t(lds);
+  auto alloc = [&](void** ptr, size_t bytes) -> hipError_t { return hipMalloc(ptr, bytes > 0 ? bytes : 16); };
+  if ((e = alloc((void**)&p->dev, sizeof(DevProblem))) != hipSuccess ||
+      (e = alloc((void**)&p->obs, obs_f.size() * sizeof(float4))) != hipSuccess ||
+      (e = alloc((void**)&p->clus, cl_f.size() * sizeof(float4))) != hipSuccess ||
+      (e = alloc((void**)&p->clus_range, rg_i.size() * sizeof(int2))) != hipSuccess ||
+      (e = alloc((void**)&p->counter, sizeof(unsigned int))) != hipSuccess ||
+      (e = alloc((void**)&p->fallback, sizeof(unsigned long long))) != hipSuccess) {
+    mc_problem_destroy(p);
+    delete hp;
+    return hip_fail(e, "mc_problem_create: hipMalloc");
+  }
+  hp->obs = p->obs;
+  hp->clus = p->clus;
+  hp->clus_range = p->clus_range;
+  hp->fallback_counter = p->fallback;
+  const unsigned long long zero64 = 0;
+  const unsigned int zero32 = 0;
+  if ((e = hipMemcpy(p->dev, hp, sizeof(DevProblem), hipMemcpyHostToDevice)) != hipSuccess ||
+      (!obs_f.empty() && (e = hipMemcpy(p->obs, obs_f.data(), obs_f.size() * sizeof(float4), hipMemcpyHostToDevice)) != hipSuccess) ||
+      (!cl_f.empty() && (e = hipMemcpy(p->clus, cl_f.data(), cl_f.size() * sizeof(float4), hipMemcpyHostToDevice)) != hipSuccess) ||
+      (!rg_i.empty() && (e = hipMemcpy(p->clus_range, rg_i.data(), rg_i.size() * sizeof(int2), hipMemcpyHostToDevice)) != hipSuccess) ||
+      (e = hipMemcpy(p->counter, &zero32, sizeof zero32, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p->fallback, &zero64, sizeof zero64, hipMemcpyHostToDevice)) != hipSuccess) {
+    mc_problem_destroy(p);
+    delete hp;
+    return hip_fail(e, "mc_problem_create: hipMemcpy");
+  }
+  delete hp;
+  *out = p;
+  return MC_OK;
+}
+
+static mc_status check_opts(const mc_problem* p, const mc_project_opts* o) {
+  if (!o) return fail(MC_ERR_INVALID_ARG, "null opts");
+  if (o->dtype != MC_F32 && o->dtype != MC_F64) return fail(MC_ERR_INVALID_ARG, "bad dtype");
+  if (!(o->tol > 0) || !std::isfinite(o->tol)) return fail(MC_ERR_INVALID_ARG, "tol must be > 0");
+  if (o->max_iter < 0 || o->max_iter > 127) return fail(MC_ERR_INVALID_ARG, "max_iter must be in 0..127");
+  if (!(o->alpha > 0) || !std::isfinite(o->alpha)) return fail(MC_ERR_INVALID_ARG, "alpha must be > 0");
+  if (!(o->lambda >= 0) || !std::isfinite(o->lambda)) return fail(MC_ERR_INVALID_ARG, "lambda must be >= 0");
+  if (std::isnan(o->max_step)) return fail(MC_ERR_INVALID_ARG, "max_step is NaN");
+  if (!(o->fp64_cond_threshold > 0)) return fail(MC_ERR_INVALID_ARG, "fp64_cond_threshold must be > 0");
+  if (o->variant < 0 || o->variant > 2) return fail(MC_ERR_INVALID_ARG, "variant must be 0, 1 or 2");
+  if (o->waves_per_block != 0 && o->waves_per_block != 1 && o->waves_per_block != 2 && o->waves_per_block != 4)
+    return fail(MC_ERR_INVALID_ARG, "waves_per_block must be 0, 1, 2 or 4");
+  if (o->blocks_per_cu < 0 || o->blocks_per_cu > 64) return fail(MC_ERR_INVALID_ARG, "blocks_per_cu must be 0..64");
+  (void)p;
+  return MC_OK;
+}
+
+mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_t ld_in, void* q_out, int64_t ld_out,
+                        int8_t* status, int8_t* iters, void* resid, uint8_t* verdict, const int32_t* geo_offsets,
+                        const int32_t* geo_offsets_host, int32_t n_geo, uint8_t* geo_ok, const mc_project_opts* opts,
+                        void* stream) {
+  g_err.clear();
+  if (!p) return fail(MC_ERR_INVALID_ARG, "project_batch: null problem");
+  if (n < 0) return fail(MC_ERR_INVALID_ARG, "project_batch: n < 0");
+  mc_status st = check_opts(p, opts);
+  if (st != MC_OK) return st;
+  if (n == 0) return MC_OK;
+  if (!q_in || !q_out || !status || !iters || !resid) return fail(MC_ERR_INVALID_ARG, "project_batch: null array");
+  if (ld_in < n || ld_out < n) return fail(MC_ERR_INVALID_ARG, "project_batch: ld < n");
+  if (n > (int64_t(1) << 31) - 1) return fail(MC_ERR_INVALID_ARG, "project_batch: n too large");
+  if (geo_ok && (!geo_offsets || n_geo <= 0)) return fail(MC_ERR_INVALID_ARG, "project_batch: geo_ok needs geo_offsets");
+  int variant = opts->variant == 0 ? 2 : opts->variant;
+  if (variant == 1) {
+    if (!geo_offsets_host || n_geo <= 0) return fail(MC_ERR_INVALID_ARG, "project_batch: plain variant needs geo_offsets_host");
+    if (geo_offsets_host[0] != 0 || geo_offsets_host[n_geo] != n) return fail(MC_ERR_INVALID_ARG, "project_batch: geo_offsets must span [0, n]");
+    for (int g = 0; g < n_geo; ++g)
+      if (geo_offsets_host[g + 1] < geo_offsets_host[g]) return fail(MC_ERR_INVALID_ARG, "project_batch: geo_offsets not monotone");
+  }
+  const FamilyOps* ops = ops_for(p->family, opts->dtype == MC_F64);
+  if (!ops) return fail(MC_ERR_UNSUPPORTED, "project_batch: family without kernels");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  ProjArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.P = p->dev;
+  a.q_in = q_in;
+  a.ld_in = ld_in;
+  a.q_out = q_out;
+  a.ld_out = ld_out;
+  a.status = status;
+  a.iters = iters;
+  a.resid = resid;
+  a.tol2 = opts->tol * opts->tol;
+  a.alpha = opts->alpha;
+  a.lambda = opts->lambda;
+  a.max_step = opts->max_step;
+  a.cond_thr = opts->fp64_cond_threshold;
+  a.max_iter = opts->max_iter;
+  a.check = opts->check_collision;
+  a.counter = p->counter;
+  hipError_t e;
+  if (variant == 1) {
+    a.verdict = verdict;
+    for (int g = 0; g < n_geo; ++g) {
+      a.base = geo_offsets_host[g];
+      a.n = geo_offsets_host[g + 1] - geo_offsets_host[g];
+      if (a.n == 0) continue;
+      if ((e = ops->project_plain(a, s)) != hipSuccess) return hip_fail(e, "project_batch: plain launch");
+    }
+  } else {
+    int wpb = opts->waves_per_block > 0 ? opts->waves_per_block : 1;
+    while (wpb > 1 && ops->lds_bytes(64 * wpb) > p->max_lds_per_block) wpb >>= 1;
+    const int block = 64 * wpb;
+    int bpc = opts->blocks_per_cu > 0 ? opts->blocks_per_cu : ops->persistent_blocks_per_cu(block);
+    int64_t grid = int64_t(p->n_cu) * bpc;
+    grid = std::min<int64_t>(grid, (n + block - 1) / block);
+    a.base = 0;
+    a.n = n;
+    a.n_static = std::min<int64_t>(n, grid * block);
+    hipLaunchKernelGGL(k_reset_u32, dim3(1), dim3(1), 0, s, p->counter);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "project_batch: reset");
+    if ((e = ops->project_persistent(a, int(grid), block, s)) != hipSuccess) return hip_fail(e, "project_batch: persistent launch");
+    if (verdict) {
+      CheckArgs c;
+      c.P = p->dev;
+      c.n = n;
+      c.q = q_out;
+      c.ld = ld_out;
+      c.status = status;
+      c.verdict = verdict;
+      c.minsd = nullptr;
+      if (opts->check_collision) {
+        if ((e = ops->check(c, 0, s)) != hipSuccess) return hip_fail(e, "project_batch: check launch");
+      } else {
+        hipLaunchKernelGGL(k_fill_u8, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, verdict, n, uint8_t(V_UNCHECKED));
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "project_batch: verdict fill");
+      }
+    }
+  }
+  if (geo_ok) {
+    hipLaunchKernelGGL(k_geo_ok, dim3((n_geo + 255) / 256), dim3(256), 0, s, n_geo, geo_offsets, n, status, verdict, geo_ok);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "project_batch: geo_ok");
+  }
+  return MC_OK;
+}
+
+mc_status check_batch(const mc_problem* p, int64_t n, const void* q, int64_t ld, mc_dtype dtype, uint8_t* verdict,
+                      void* min_signed_dist, void* stream) {
+  g_err.clear();
+  if (!p) return fail(MC_ERR_INVALID_ARG, "check_batch: null problem");
+  if (n < 0) return fail(MC_ERR_INVALID_ARG, "check_batch: n < 0");
+  if (dtype != MC_F32 && dtype != MC_F64) return fail(MC_ERR_INVALID_ARG, "check_batch: bad dtype");
+  if (n == 0) return MC_OK;
+  if (!q || !verdict) return fail(MC_ERR_INVALID_ARG, "check_batch: null array");
+  if (ld < n) return fail(MC_ERR_INVALID_ARG, "check_batch: ld < n");
+  const FamilyOps* ops = ops_for(p->family, dtype == MC_F64);
+  CheckArgs c;
+  c.P = p->dev;
+  c.n = n;
+  c.q = q;
+  c.ld = ld;
+  c.status = nullptr;
+  c.verdict = verdict;
+  c.minsd = min_signed_dist;
+  hipError_t e = ops->check(c, min_signed_dist != nullptr, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "check_batch: launch");
+  return MC_OK;
+}
+
+mc_status project_vjp(const mc_problem* p, int64_t n, const void* q_proj, int64_t ld, const int8_t* status,
+                      const void* g_out, void* g_in, const mc_project_opts* opts, void* stream) {
+  g_err.clear();
+  if (!p) return fail(MC_ERR_INVALID_ARG, "project_vjp: null problem");
+  if (n < 0) return fail(MC_ERR_INVALID_ARG, "project_vjp: n < 0");
+  mc_status st = check_opts(p, opts);
+  if (st != MC_OK) return st;
+  if (n == 0) return MC_OK;
+  if (!q_proj || !status || !g_out || !g_in) return fail(MC_ERR_INVALID_ARG, "project_vjp: null array");
+  if (ld < n) return fail(MC_ERR_INVALID_ARG, "project_vjp: ld < n");
+  const FamilyOps* ops = ops_for(p->family, opts->dtype == MC_F64);
+  VjpArgs a;
+  a.P = p->dev;
+  a.n = n;
+  a.q = q_proj;
+  a.ld = ld;
+  a.status = status;
+  a.g = g_out;
+  a.g_in = g_in;
+  a.cond_thr = opts->fp64_cond_threshold;
+  hipError_t e = ops->vjp(a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "project_vjp: launch");
+  return MC_OK;
+}
+
+mc_status interpolate_geodesics(const mc_problem* p, int32_t n_geo, const int32_t* geo_offsets, const void* endpoints,
+                                int64_t ld_e, void* q_out, int64_t ld_out, mc_dtype dtype, void* stream) {
+  g_err.clear();
+  if (!p) return fail(MC_ERR_INVALID_ARG, "interpolate_geodesics: null problem");
+  if (n_geo < 0) return fail(MC_ERR_INVALID_ARG, "interpolate_geodesics: n_geo < 0");
+  if (n_geo == 0) return MC_OK;
+  if (!geo_offsets || !endpoints || !q_out) return fail(MC_ERR_INVALID_ARG, "interpolate_geodesics: null array");
+  if (ld_e < 2 * int64_t(n_geo)) return fail(MC_ERR_INVALID_ARG, "interpolate_geodesics: ld_e < 2 n_geo");
+  if (dtype != MC_F32 && dtype != MC_F64) return fail(MC_ERR_INVALID_ARG, "interpolate_geodesics: bad dtype");
+  int32_t total = 0;
+  hipError_t e = hipMemcpy(&total, geo_offsets + n_geo, sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "interpolate_geodesics: read total");
+  if (total < 0 || ld_out < total) return fail(MC_ERR_INVALID_ARG, "interpolate_geodesics: ld_out < total");
+  if (total == 0) return MC_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const dim3 g((total + 255) / 256), b(256);
+  if (dtype == MC_F64)
+    hipLaunchKernelGGL(k_interpolate<double>, g, b, 0, s, n_geo, geo_offsets, static_cast<const double*>(endpoints), ld_e,
+                       static_cast<double*>(q_out), ld_out, p->d);
+  else
+    hipLaunchKernelGGL(k_interpolate<float>, g, b, 0, s, n_geo, geo_offsets, static_cast<const float*>(endpoints), ld_e,
+                       static_cast<float*>(q_out), ld_out, p->d);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "interpolate_geodesics: launch");
+  return MC_OK;
+}
+
+mc_status path_length_grad(const mc_problem* p, int64_t n, const void* q, int64_t ld, const int32_t* geo_offsets,
+                           int32_t n_geo, void* g_out, void* loss, mc_dtype dtype, void* stream) {
+  g_err.clear();
+  if (!p) return fail(MC_ERR_INVALID_ARG, "path_length_grad: null problem");
+  if (n < 0 || n_geo < 0) return fail(MC_ERR_INVALID_ARG, "path_length_grad: negative size");
+  if (dtype != MC_F32 && dtype != MC_F64) return fail(MC_ERR_INVALID_ARG, "path_length_grad: bad dtype");
+  if (n == 0) return MC_OK;
+  if (!q || !geo_offsets || !g_out || n_geo == 0) return fail(MC_ERR_INVALID_ARG, "path_length_grad: null array");
+  if (ld < n) return fail(MC_ERR_INVALID_ARG, "path_length_grad: ld < n");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  const dim3 g((n + 255) / 256), b(256);
+  if (dtype == MC_F64) {
+    if (loss) hipLaunchKernelGGL(k_zero1<double>, dim3(1), dim3(1), 0, s, static_cast<double*>(loss));
+    hipLaunchKernelGGL(k_path_grad<double>, g, b, 0, s, n, static_cast<const double*>(q), ld, geo_offsets, n_geo,
+                       static_cast<double*>(g_out), static_cast<double*>(loss), p->d);
+  } else {
+    if (loss) hipLaunchKernelGGL(k_zero1<float>, dim3(1), dim3(1), 0, s, static_cast<float*>(loss));
+    hipLaunchKernelGGL(k_path_grad<float>, g, b, 0, s, n, static_cast<const float*>(q), ld, geo_offsets, n_geo,
+                       static_cast<float*>(g_out), static_cast<float*>(loss), p->d);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "path_length_grad: launch");
+  return MC_OK;
+}
+
+mc_status mc_eval_residual_jacobian(const mc_problem* p, int64_t n, const void* q, int64_t ld, mc_dtype dtype, void* F,
+                                    void* J, void* stream) {
+  g_err.clear();
+  if (!p) return fail(MC_ERR_INVALID_ARG, "mc_eval_residual_jacobian: null problem");
+  if (n < 0) return fail(MC_ERR_INVALID_ARG, "mc_eval_residual_jacobian: n < 0");
+  if (dtype != MC_F32 && dtype != MC_F64) return fail(MC_ERR_INVALID_ARG, "mc_eval_residual_jacobian: bad dtype");
+  if (n == 0) return MC_OK;
+  if (!q || !F || !J) return fail(MC_ERR_INVALID_ARG, "mc_eval_residual_jacobian: null array");
+  if (ld < n) return fail(MC_ERR_INVALID_ARG, "mc_eval_residual_jacobian: ld < n");
+  const FamilyOps* ops = ops_for(p->family, dtype == MC_F64);
+  hipError_t e = ops->eval_fj(p->dev, n, q, ld, F, J, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "mc_eval_residual_jacobian: launch");
+  return MC_OK;
+}
+
+mc_status mc_fallback_count(const mc_problem* p, int reset, uint64_t* count) {
+  g_err.clear();
+  if (!p || !count) return fail(MC_ERR_INVALID_ARG, "mc_fallback_count: null argument");
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "mc_fallback_count: sync");
+  unsigned long long v = 0;
+  if ((e = hipMemcpy(&v, p->fallback, sizeof v, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "mc_fallback_count: read");
+  *count = v;
+  if (reset) {
+    const unsigned long long z = 0;
+    if ((e = hipMemcpy(p->fallback, &z, sizeof z, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "mc_fallback_count: reset");
+  }
+  return MC_OK;
+}
+
+}  // extern "C"

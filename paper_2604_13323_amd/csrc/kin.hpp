@@ -1,0 +1,610 @@
+// Kinematic-tree constraint models with compile-time topology.
+//
+// The paper generates branch-free, loop-unrolled code for each robot with a
+// tracing compiler (Sec. IV-A, "Tracing Compiler for Constraints"). Here the
+// same effect comes from C++ templates: a robot's joint tree, joint types and
+// axes, end-effector frames and constraint blocks are constexpr data, and every
+// loop over joints, rows and Gram entries is unrolled at compile time with the
+// structural zeros of the Jacobian, the Gram matrix and its Cholesky factor
+// removed. Numeric parameters (origins, masses, targets) stay runtime data read
+// with wave-uniform (scalar) loads.
+//
+// Conventions: joint j has parent p(j) (-1 = world), fixed origin O_j and axis
+// a_j of its own frame; the link frame is T_j = T_p(j) O_j Q_j(q_j). Joints are
+// in depth-first preorder, so the subtree of j is the index range [j, end_j).
+// A revolute joint's world axis is z_j = R_j e_{a_j} and its origin o_j = p_j.
+//
+// Residual blocks (rows stacked in block order):
+//   POSE  (Eq. 1)  T_err = T_ref^-1 T_f, rows [t; log(R)^v] selected by a mask.
+//   REL   (Eq. 2)  T_err = T_ref^-1 (T_a^-1 T_b), rows [t; log(R)^v].
+//   AXIS           (R_f e_z)_x, (R_f e_z)_y  (frame z-axis parallel to world z).
+//   COM   (Digit constraint figure, equality form) sum_l m_l c_l / M |_xy - target.
+//
+// Analytic Jacobian columns (for a revolute joint j; prismatic in brackets):
+//   POSE  [W (z_j x (p_f - o_j)); A z_j]    [W z_j; 0],   W = R_ref^T, A = J_l^-1(w) W
+//   REL   s_j [W (z_j x (p_b - o_j)); A z_j] with W = (R_a R_ref)^T, s_j = +1 when j moves
+//         only frame b, -1 when it moves only frame a, 0 when it moves both
+//   AXIS  (z_j x u)_xy with u = R_f e_z         [0]
+//   COM   (z_j x (S_j - M_j o_j))_xy / M        [(M_j / M) z_j,xy]
+//         S_j = sum of m_l c_l over the subtree of j, M_j its mass.
+#pragma once
+
+#include "common.hpp"
+
+namespace mc {
+
+// ------------------------------------------------------------------ topologies
+struct TopoPlanar2 {
+  static constexpr int family = 2;
+  static constexpr int NJ = 2, NF = 1, NB = 1, M = 2;
+  static constexpr int parent[NJ] = {-1, 0};
+  static constexpr int jtype[NJ] = {REV, REV};
+  static constexpr int axis[NJ] = {2, 2};
+  static constexpr bool origin_rot = false, frame_rot = false;
+  static constexpr int frame_link[NF] = {1};
+  static constexpr int btype[NB] = {B_POSE};
+  static constexpr int bfa[NB] = {0};
+  static constexpr int bfb[NB] = {-1};
+  static constexpr int bmask[NB] = {0x3};
+  static constexpr bool has_com = false;
+  static constexpr bool massless(int) { return true; }
+  static constexpr bool may_have_spheres(int) { return true; }
+};
+
+struct TopoArm7Axis {
+  static constexpr int family = 3;
+  static constexpr int NJ = 7, NF = 1, NB = 1, M = 2;
+  static constexpr int parent[NJ] = {-1, 0, 1, 2, 3, 4, 5};
+  static constexpr int jtype[NJ] = {REV, REV, REV, REV, REV, REV, REV};
+  static constexpr int axis[NJ] = {2, 2, 2, 2, 2, 2, 2};
+  static constexpr bool origin_rot = true, frame_rot = true;
+  static constexpr int frame_link[NF] = {6};
+  static constexpr int btype[NB] = {B_AXIS};
+  static constexpr int bfa[NB] = {0};
+  static constexpr int bfb[NB] = {-1};
+  static constexpr int bmask[NB] = {0};
+  static constexpr bool has_com = false;
+  static constexpr bool massless(int) { return true; }
+  static constexpr bool may_have_spheres(int) { return true; }
+};
+
+struct TopoDual14Rel {
+  static constexpr int family = 4;
+  static constexpr int NJ = 14, NF = 2, NB = 1, M = 6;
+  static constexpr int parent[NJ] = {-1, 0, 1, 2, 3, 4, 5, -1, 7, 8, 9, 10, 11, 12};
+  static constexpr int jtype[NJ] = {REV, REV, REV, REV, REV, REV, REV, REV, REV, REV, REV, REV, REV, REV};
+  static constexpr int axis[NJ] = {2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2};
+  static constexpr bool origin_rot = true, frame_rot = true;
+  static constexpr int frame_link[NF] = {6, 13};
+  static constexpr int btype[NB] = {B_REL};
+  static constexpr int bfa[NB] = {0};
+  static constexpr int bfb[NB] = {1};
+  static constexpr int bmask[NB] = {0x3F};
+  static constexpr bool has_com = false;
+  static constexpr bool massless(int) { return true; }
+  static constexpr bool may_have_spheres(int) { return true; }
+};
+
+// 6-DoF floating base (Px Py Pz Rz Ry Rx -> pelvis = link 5), legs 2 x 6, torso 2,
+// arms 2 x 7, head 2.
+struct TopoHumanoid36 {
+  static constexpr int family = 5;
+  static constexpr int NJ = 36, NF = 4, NB = 4, M = 20;
+  static constexpr int parent[NJ] = {-1, 0, 1, 2, 3, 4,
+                                     5, 6, 7, 8, 9, 10,
+                                     5, 12, 13, 14, 15, 16,
+                                     5, 18,
+                                     19, 20, 21, 22, 23, 24, 25,
+                                     19, 27, 28, 29, 30, 31, 32,
+                                     19, 34};
+  static constexpr int jtype[NJ] = {PRI, PRI, PRI, REV, REV, REV,
+                                    REV, REV, REV, REV, REV, REV,
+                                    REV, REV, REV, REV, REV, REV,
+                                    REV, REV,
+                                    REV, REV, REV, REV, REV, REV, REV,
+                                    REV, REV, REV, REV, REV, REV, REV,
+                                    REV, REV};
+  static constexpr int axis[NJ] = {0, 1, 2, 2, 1, 0,
+                                   2, 0, 1, 1, 1, 0,
+                                   2, 0, 1, 1, 1, 0,
+                                   2, 1,
+                                   1, 0, 2, 1, 2, 1, 0,
+                                   1, 0, 2, 1, 2, 1, 0,
+                                   2, 1};
+  static constexpr bool origin_rot = false, frame_rot = false;
+  static constexpr int frame_link[NF] = {11, 17, 26, 33};   // left sole, right sole, left palm, right palm
+  static constexpr int btype[NB] = {B_POSE, B_POSE, B_REL, B_COM};
+  static constexpr int bfa[NB] = {0, 1, 2, -1};
+  static constexpr int bfb[NB] = {-1, -1, 3, -1};
+  static constexpr int bmask[NB] = {0x3F, 0x3F, 0x3F, 0};
+  static constexpr bool has_com = true;
+  static constexpr bool massless(int j) { return j < 5; }     // the base's intermediate links
+  static constexpr bool may_have_spheres(int j) { return j >= 5; }
+};
+
+// ------------------------------------------------------------------ structure
+template <class Topo>
+struct KInfo {
+  static constexpr int NJ = Topo::NJ, NB = Topo::NB, M = Topo::M;
+  static constexpr bool anc(int j, int l) {
+    for (int k = l; k >= 0; k = Topo::parent[k])
+      if (k == j) return true;
+    return false;
+  }
+  static constexpr int popc6(int x) {
+    int c = 0;
+    for (int i = 0; i < 6; ++i) c += (x >> i) & 1;
+    return c;
+  }
+  static constexpr int brows(int b) {
+    return (Topo::btype[b] == B_POSE || Topo::btype[b] == B_REL) ? popc6(Topo::bmask[b]) : 2;
+  }
+  static constexpr int brow0(int b) {
+    int r = 0;
+    for (int k = 0; k < b; ++k) r += brows(k);
+    return r;
+  }
+  static constexpr int flink(int f) { return Topo::frame_link[f]; }
+  // 0: block b does not depend on joint j; +-1: it does (sign for REL).
+  static constexpr int dep(int b, int j) {
+    const int t = Topo::btype[b];
+    if (t == B_POSE) return anc(j, flink(Topo::bfa[b])) ? 1 : 0;
+    if (t == B_AXIS) return (anc(j, flink(Topo::bfa[b])) && Topo::jtype[j] == REV) ? 1 : 0;
+    if (t == B_REL) {
+      const bool a = anc(j, flink(Topo::bfa[b])), bb = anc(j, flink(Topo::bfb[b]));
+      return a == bb ? 0 : (bb ? 1 : -1);
+    }
+    if (t == B_COM) return 1;
+    return 0;
+  }
+  static constexpr int row_block(int r) {
+    for (int b = 0; b < NB; ++b)
+      if (r < brow0(b) + brows(b)) return b;
+    return -1;
+  }
+  // component (0..5 of [t; w] for pose blocks, 0..1 otherwise) of row r
+  static constexpr int row_comp(int r) {
+    const int b = row_block(r);
+    const int k = r - brow0(b);
+    if (Topo::btype[b] == B_POSE || Topo::btype[b] == B_REL) {
+      int seen = 0;
+      for (int c = 0; c < 6; ++c)
+        if ((Topo::bmask[b] >> c) & 1) {
+          if (seen == k) return c;
+          ++seen;
+        }
+      return -1;
+    }
+    return k;
+  }
+  // row r is structurally nonzero in column j
+  static constexpr bool rdep(int r, int j) {
+    const int b = row_block(r);
+    if (dep(b, j) == 0) return false;
+    const int t = Topo::btype[b];
+    if ((t == B_POSE || t == B_REL) && row_comp(r) >= 3 && Topo::jtype[j] == PRI) return false;
+    return true;
+  }
+  static constexpr bool gnz(int r1, int r2) {
+    for (int j = 0; j < NJ; ++j)
+      if (rdep(r1, j) && rdep(r2, j)) return true;
+    return false;
+  }
+  struct Pat { bool nz[MAXM][MAXM]; };
+  static constexpr Pat lpattern() {
+    Pat P{};
+    for (int i = 0; i < M; ++i)
+      for (int k = 0; k <= i; ++k) P.nz[i][k] = gnz(i, k);
+    for (int k = 0; k < M; ++k)
+      for (int i = k + 1; i < M; ++i)
+        for (int j = k + 1; j <= i; ++j)
+          if (P.nz[i][k] && P.nz[j][k]) P.nz[i][j] = true;
+    return P;
+  }
+  static constexpr Pat LP = lpattern();
+  static constexpr int sub_end(int j) {
+    int e = j + 1;
+    while (e < NJ && anc(j, e)) ++e;
+    return e;
+  }
+  static constexpr bool end_needed(int e) {
+    for (int j = 0; j < NJ; ++j)
+      if (sub_end(j) == e) return true;
+    return false;
+  }
+  static constexpr int complete_link(int b) {
+    const int t = Topo::btype[b];
+    if (t == B_POSE || t == B_AXIS) return flink(Topo::bfa[b]);
+    if (t == B_REL) return flink(Topo::bfa[b]) > flink(Topo::bfb[b]) ? flink(Topo::bfa[b]) : flink(Topo::bfb[b]);
+    return NJ - 1;
+  }
+};
+
+
+// ------------------------------------------------------------------ model
+template <class Topo>
+struct Kin {
+  using KI = KInfo<Topo>;
+  static constexpr int NJ = Topo::NJ, NB = Topo::NB, NF = Topo::NF, M = Topo::M, D = Topo::NJ;
+  static constexpr int family = Topo::family;
+  static constexpr bool lnz(int i, int k) { return KI::LP.nz[i][k]; }
+
+  // Per-iteration data from the residual pass used by the Jacobian passes.
+  template <class S>
+  struct SD {
+    S pend[NB][3];    // end point of pose / relative-pose blocks
+    S W[NB][9];       // REL: (R_a R_ref)^T
+    S A[NB][9];       // J_l^-1(w) W
+    S u[NB][3];       // AXIS: frame z axis
+    S Qe[NJ + 1][3];  // prefix sums of m_l c_l at the subtree ends
+  };
+
+  // Joint coordinate in the pass precision. FP32 passes take revolute angles reduced to
+  // [-pi, pi] in FP64 first, so large angles keep full FP32 accuracy in sine and cosine.
+  template <class T, int type>
+  static __device__ __forceinline__ T joint_value(double x) {
+    if constexpr (std::is_same<T, float>::value && type == REV) {
+      const double k = __builtin_rint(x * 0.15915494309189535);  // 1 / (2 pi)
+      x = __builtin_fma(-k, 6.283185307179586, x);
+      x = __builtin_fma(-k, 2.4492935982947064e-16, x);
+    }
+    return T(x);
+  }
+
+  // Forward kinematics, streaming each link frame to visit(ic<j>, frame) in joint order.
+  template <class T, class Q, class V>
+  static __device__ __forceinline__ void fk(const Q& q, const TP<T>& P, V&& visit) {
+    Rig<T> L[NJ];
+    sfor<0, NJ>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      constexpr int par = Topo::parent[j];
+      constexpr int ax = Topo::axis[j];
+      Rig<T>& X = L[j];
+      T qj;
+      if constexpr (par < 0) {
+        qj = joint_value<T, Topo::jtype[j]>(q.at(j));
+        const TP<T>& Pj = P;
+        if constexpr (Topo::origin_rot) {
+          for (int k = 0; k < 9; ++k) X.R[k] = Pj.jR[j][k];
+        } else {
+          for (int k = 0; k < 9; ++k) X.R[k] = (k % 4 == 0) ? T(1) : T(0);
+        }
+        for (int k = 0; k < 3; ++k) X.p[k] = Pj.jp[j][k];
+      } else {
+        const Rig<T>& B = L[par];
+        // joint j's angle and origin are consumed only once its parent frame and the previous
+        // frame in depth-first order exist: the walk stays one chain at a time
+        const T dep = after2(B.p[2], B.p[2], L[j - 1].p[2]);
+        qj = joint_value<T, Topo::jtype[j]>(q.at(j, dep));
+        const TP<T>& Pj = after_params(P, dep);
+        if constexpr (Topo::origin_rot) {
+          matmul3(B.R, Pj.jR[j], X.R);
+        } else {
+          for (int k = 0; k < 9; ++k) X.R[k] = B.R[k];
+        }
+        T t[3];
+        matvec3(B.R, Pj.jp[j], t);
+        for (int k = 0; k < 3; ++k) X.p[k] = B.p[k] + t[k];
+      }
+      if constexpr (Topo::jtype[j] == PRI) {
+        for (int r = 0; r < 3; ++r) X.p[r] += X.R[3 * r + ax] * qj;
+      } else {
+        T s, c;
+        sincos_t(qj, &s, &c);
+        constexpr int i = (ax + 1) % 3, k = (ax + 2) % 3;
+        for (int r = 0; r < 3; ++r) {
+          const T a = X.R[3 * r + i], b = X.R[3 * r + k];
+          X.R[3 * r + i] = a * c + b * s;
+          X.R[3 * r + k] = b * c - a * s;
+        }
+      }
+      visit(J, X);
+    });
+  }
+
+  template <class T>
+  static __device__ __forceinline__ void frame_pose(const Rig<T>& X, const TP<T>& P, int f, Rig<T>& out) {
+    if constexpr (Topo::frame_rot) {
+      matmul3(X.R, P.fR[f], out.R);
+    } else {
+      for (int k = 0; k < 9; ++k) out.R[k] = X.R[k];
+    }
+    T t[3];
+    matvec3(X.R, P.fp[f], t);
+    for (int k = 0; k < 3; ++k) out.p[k] = X.p[k] + t[k];
+  }
+
+  // rows of a pose error (t, log R) selected by the block mask
+  template <int b, class S>
+  static __device__ __forceinline__ void put_pose_rows(const double* t, const double* w, S* F, double& n2) {
+    constexpr int r0 = KI::brow0(b);
+    sfor<0, KI::brows(b)>([&](auto K) {
+      constexpr int c = KI::row_comp(r0 + decltype(K)::value);
+      const double v = c < 3 ? t[c] : w[c - 3];
+      F[r0 + decltype(K)::value] = S(v);
+      n2 += v * v;
+    });
+  }
+
+  template <class S, int b>
+  static __device__ __forceinline__ void block_rows(const Rig<double>* Fr, const DevProblem& P, S* F, double& n2, SD<S>& sd) {
+    constexpr int t = Topo::btype[b];
+    constexpr int r0 = KI::brow0(b);
+    if constexpr (t == B_POSE) {
+      constexpr int fa = Topo::bfa[b];
+      const double* Rt = P.d.refRt[b];
+      double dp[3] = {Fr[fa].p[0] - P.d.refp[b][0], Fr[fa].p[1] - P.d.refp[b][1], Fr[fa].p[2] - P.d.refp[b][2]};
+      double tt[3], Re[9], w[3], Jl[9], A[9];
+      matvec3(Rt, dp, tt);
+      matmul3(Rt, Fr[fa].R, Re);
+      so3_log_jlinv(Re, w, Jl);
+      put_pose_rows<b>(tt, w, F, n2);
+      matmul3(Jl, Rt, A);
+      for (int k = 0; k < 3; ++k) sd.pend[b][k] = S(Fr[fa].p[k]);
+      for (int k = 0; k < 9; ++k) sd.A[b][k] = S(A[k]);
+    } else if constexpr (t == B_REL) {
+      constexpr int fa = Topo::bfa[b], fb = Topo::bfb[b];
+      const double* Rt = P.d.refRt[b];
+      double W[9];  // W = R_ref^T R_a^T
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k)
+          W[3 * i + k] = Rt[3 * i] * Fr[fa].R[3 * k] + Rt[3 * i + 1] * Fr[fa].R[3 * k + 1] + Rt[3 * i + 2] * Fr[fa].R[3 * k + 2];
+      double dp[3] = {Fr[fb].p[0] - Fr[fa].p[0], Fr[fb].p[1] - Fr[fa].p[1], Fr[fb].p[2] - Fr[fa].p[2]};
+      double tt[3], pr[3], Re[9], w[3], Jl[9], A[9];
+      matvec3(W, dp, tt);
+      matvec3(Rt, P.d.refp[b], pr);
+      for (int k = 0; k < 3; ++k) tt[k] -= pr[k];
+      matmul3(W, Fr[fb].R, Re);
+      so3_log_jlinv(Re, w, Jl);
+      put_pose_rows<b>(tt, w, F, n2);
+      matmul3(Jl, W, A);
+      for (int k = 0; k < 3; ++k) sd.pend[b][k] = S(Fr[fb].p[k]);
+      for (int k = 0; k < 9; ++k) sd.W[b][k] = S(W[k]);
+      for (int k = 0; k < 9; ++k) sd.A[b][k] = S(A[k]);
+    } else if constexpr (t == B_AXIS) {
+      constexpr int fa = Topo::bfa[b];
+      F[r0] = S(Fr[fa].R[2]);
+      F[r0 + 1] = S(Fr[fa].R[5]);
+      n2 += Fr[fa].R[2] * Fr[fa].R[2] + Fr[fa].R[5] * Fr[fa].R[5];
+      sd.u[b][0] = S(Fr[fa].R[2]);
+      sd.u[b][1] = S(Fr[fa].R[5]);
+      sd.u[b][2] = S(Fr[fa].R[8]);
+    }
+  }
+
+  // Residual pass in FP64: returns ||F(q)||^2 (FP64); F in the step precision S and the
+  // step data for the Jacobian passes.
+  template <class S, class Q>
+  static __device__ __forceinline__ double residual(const Q& q, const DevProblem& P, S* F, SD<S>& sd) {
+    Rig<double> Fr[NF];
+    double cm[3] = {0.0, 0.0, 0.0};
+    double n2 = 0.0;
+    fk<double>(q, P.d, [&](auto J, const Rig<double>& X) {
+      constexpr int j = decltype(J)::value;
+      sfor<0, NF>([&](auto FI) {
+        constexpr int f = decltype(FI)::value;
+        if constexpr (Topo::frame_link[f] == j) frame_pose<double>(X, P.d, f, Fr[f]);
+      });
+      if constexpr (Topo::has_com) {
+        if constexpr (!Topo::massless(j)) {
+          double t[3];
+          matvec3(X.R, P.d.mcom[j], t);
+          const double mj = P.d.mass[j];
+          for (int k = 0; k < 3; ++k) cm[k] += t[k] + mj * X.p[k];
+        }
+        if constexpr (KI::end_needed(j + 1)) {
+          for (int k = 0; k < 3; ++k) sd.Qe[j + 1][k] = S(cm[k]);
+        }
+      }
+      sfor<0, NB>([&](auto BI) {
+        constexpr int b = decltype(BI)::value;
+        if constexpr (KI::complete_link(b) == j) block_rows<S, b>(Fr, P, F, n2, sd);
+      });
+    });
+    sfor<0, NB>([&](auto BI) {
+      constexpr int b = decltype(BI)::value;
+      if constexpr (Topo::btype[b] == B_COM) {
+        constexpr int r0 = KI::brow0(b);
+        const double e0 = cm[0] * P.d.inv_total_mass - P.d.target[b][0];
+        const double e1 = cm[1] * P.d.inv_total_mass - P.d.target[b][1];
+        F[r0] = S(e0);
+        F[r0 + 1] = S(e1);
+        n2 += e0 * e0 + e1 * e1;
+      }
+    });
+    return n2;
+  }
+
+  // Structurally nonzero entries of Jacobian column j (other rows untouched). Qr is the running
+  // prefix sum of m_l c_l over the links before j and is advanced past link j.
+  template <class S, int j>
+  static __device__ __forceinline__ void column(const Rig<S>& X, const TP<S>& T, const SD<S>& sd, S* Qr, S* col) {
+    constexpr int ax = Topo::axis[j];
+    constexpr bool rev = Topo::jtype[j] == REV;
+    const S z[3] = {X.R[ax], X.R[3 + ax], X.R[6 + ax]};
+    const S* o = X.p;
+    sfor<0, NB>([&](auto BI) {
+      constexpr int b = decltype(BI)::value;
+      constexpr int sg = KI::dep(b, j);
+      constexpr int t = Topo::btype[b];
+      constexpr int r0 = KI::brow0(b);
+      if constexpr (sg != 0 && (t == B_POSE || t == B_REL)) {
+        S tv[3];
+        if constexpr (rev) {
+          const S r[3] = {sd.pend[b][0] - o[0], sd.pend[b][1] - o[1], sd.pend[b][2] - o[2]};
+          cross3(z, r, tv);
+        } else {
+          tv[0] = z[0]; tv[1] = z[1]; tv[2] = z[2];
+        }
+        S lin[3], ang[3] = {S(0), S(0), S(0)};
+        if constexpr (t == B_POSE) matvec3(T.refRt[b], tv, lin); else matvec3(sd.W[b], tv, lin);
+        if constexpr (rev) matvec3(sd.A[b], z, ang);
+        sfor<0, KI::brows(b)>([&](auto K) {
+          constexpr int r = r0 + decltype(K)::value;
+          constexpr int c = KI::row_comp(r);
+          if constexpr (KI::rdep(r, j)) {
+            const S v = c < 3 ? lin[c] : ang[c - 3];
+            col[r] = sg > 0 ? v : -v;
+          }
+        });
+      } else if constexpr (sg != 0 && t == B_AXIS) {
+        col[r0] = z[1] * sd.u[b][2] - z[2] * sd.u[b][1];
+        col[r0 + 1] = z[2] * sd.u[b][0] - z[0] * sd.u[b][2];
+      } else if constexpr (sg != 0 && t == B_COM) {
+        constexpr int e = KI::sub_end(j);
+        const S iM = T.inv_total_mass;
+        if constexpr (rev) {
+          const S Mj = T.submass[j];
+          S Sp[3];
+          for (int k = 0; k < 3; ++k) Sp[k] = sd.Qe[e][k] - Qr[k] - Mj * o[k];
+          col[r0] = (z[1] * Sp[2] - z[2] * Sp[1]) * iM;
+          col[r0 + 1] = (z[2] * Sp[0] - z[0] * Sp[2]) * iM;
+        } else {
+          const S f = T.submass[j] * iM;
+          col[r0] = z[0] * f;
+          col[r0 + 1] = z[1] * f;
+        }
+      }
+    });
+    if constexpr (Topo::has_com && !Topo::massless(j)) {
+      S t[3];
+      matvec3(X.R, T.mcom[j], t);
+      const S mj = T.mass[j];
+      for (int k = 0; k < 3; ++k) Qr[k] += t[k] + mj * X.p[k];
+    }
+  }
+
+  // Gram pass: G += J_j J_j^T over all columns (packed lower triangle), optionally v = J g.
+  template <class S, bool WITH_V, class Q>
+  static __device__ __forceinline__ void gram(const Q& q, const DevProblem& P, const SD<S>& sd, S* G, const S* g, S* v) {
+    const TP<S>& T = tp<S>(P);
+    sfor<0, M>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      sfor<0, i + 1>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        if constexpr (lnz(i, k)) G[pidx(i, k)] = S(0);
+      });
+      if constexpr (WITH_V) v[i] = S(0);
+    });
+    S Qr[3] = {S(0), S(0), S(0)};
+    fk<S>(q, T, [&](auto J, const Rig<S>& X) {
+      constexpr int j = decltype(J)::value;
+      S col[M];
+      column<S, j>(X, T, sd, Qr, col);
+      sfor<0, M>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (KI::rdep(i, j)) {
+          sfor<0, i + 1>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            if constexpr (KI::rdep(k, j)) G[pidx(i, k)] += col[i] * col[k];
+          });
+          if constexpr (WITH_V) v[i] += col[i] * g[j];
+        }
+      });
+    });
+  }
+
+  // J^T y pass.
+  template <class S, class Q>
+  static __device__ __forceinline__ void jty(const Q& q, const DevProblem& P, const SD<S>& sd, const S* y, S* out) {
+    const TP<S>& T = tp<S>(P);
+    S Qr[3] = {S(0), S(0), S(0)};
+    fk<S>(q, T, [&](auto J, const Rig<S>& X) {
+      constexpr int j = decltype(J)::value;
+      S col[M];
+      column<S, j>(X, T, sd, Qr, col);
+      S acc = S(0);
+      sfor<0, M>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (KI::rdep(i, j)) acc += col[i] * y[i];
+      });
+      out[j] = acc;
+    });
+  }
+
+  // Dense Jacobian (diagnostic): J[r * D + c].
+  template <class S, class Q>
+  static __device__ __forceinline__ void jacobian(const Q& q, const DevProblem& P, const SD<S>& sd, S* Jd) {
+    const TP<S>& T = tp<S>(P);
+    S Qr[3] = {S(0), S(0), S(0)};
+    for (int k = 0; k < M * D; ++k) Jd[k] = S(0);
+    fk<S>(q, T, [&](auto J, const Rig<S>& X) {
+      constexpr int j = decltype(J)::value;
+      S col[M];
+      column<S, j>(X, T, sd, Qr, col);
+      sfor<0, M>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (KI::rdep(i, j)) Jd[i * D + j] = col[i];
+      });
+    });
+  }
+
+  // World-space collision test of the robot spheres of one link against the obstacles.
+  // Broad phase: link bounding sphere vs obstacle-cluster bounding spheres (both inflated so that
+  // no overlapping pair is ever culled); narrow phase: every sphere of the link vs every obstacle
+  // of an overlapping cluster.
+  template <bool MINSD>
+  static __device__ __forceinline__ void check_link(const Rig<float>& X, const DevProblem& P, int l, bool& hit, float& minsd) {
+    const int s0 = P.sph_begin[l], s1 = P.sph_begin[l + 1];
+    if (s0 >= s1) return;
+    if constexpr (MINSD) {
+      for (int s = s0; s < s1; ++s) {
+        const float4 sp = P.sph[s];
+        float c[3];
+        const float lc[3] = {sp.x, sp.y, sp.z};
+        matvec3(X.R, lc, c);
+        for (int k = 0; k < 3; ++k) c[k] += X.p[k];
+        for (int o = 0; o < P.n_obs; ++o) {
+          const float4 ob = P.obs[o];
+          const float dx = c[0] - ob.x, dy = c[1] - ob.y, dz = c[2] - ob.z;
+          const float d2 = dx * dx + dy * dy + dz * dz;
+          const float rr = sp.w + ob.w;
+          hit = hit || (d2 < rr * rr);
+          minsd = fminf(minsd, __fsqrt_rn(d2) - rr);
+        }
+      }
+    } else {
+      const float4 bs = P.link_bs[l];
+      const float lc[3] = {bs.x, bs.y, bs.z};
+      float cb[3];
+      matvec3(X.R, lc, cb);
+      for (int k = 0; k < 3; ++k) cb[k] += X.p[k];
+      for (int c = 0; c < P.n_clus; ++c) {
+        const float4 cl = P.clus[c];
+        const float dx = cb[0] - cl.x, dy = cb[1] - cl.y, dz = cb[2] - cl.z;
+        const float rr = bs.w + cl.w;
+        const bool ov = !hit && (dx * dx + dy * dy + dz * dz < rr * rr);
+        if (ov) {
+          const int2 rg = P.clus_range[c];
+          for (int s = s0; s < s1; ++s) {
+            const float4 sp = P.sph[s];
+            float cs[3];
+            const float sl[3] = {sp.x, sp.y, sp.z};
+            matvec3(X.R, sl, cs);
+            for (int k = 0; k < 3; ++k) cs[k] += X.p[k];
+            for (int o = rg.x; o < rg.y; ++o) {
+              const float4 ob = P.obs[o];
+              const float ex = cs[0] - ob.x, ey = cs[1] - ob.y, ez = cs[2] - ob.z;
+              const float r2 = sp.w + ob.w;
+              hit = hit || (ex * ex + ey * ey + ez * ez < r2 * r2);
+            }
+          }
+        }
+      }
+    }
+  }
+
+  template <bool MINSD, class Q>
+  static __device__ __forceinline__ void check(const Q& q, const DevProblem& P, bool& hit, float& minsd) {
+    hit = false;
+    minsd = __builtin_huge_valf();
+    fk<float>(q, P.f, [&](auto J, const Rig<float>& X) {
+      constexpr int l = decltype(J)::value;
+      if constexpr (Topo::may_have_spheres(l)) {
+        if (MINSD || !hit) check_link<MINSD>(X, P, l, hit, minsd);
+      }
+    });
+  }
+};
+
+}  // namespace mc

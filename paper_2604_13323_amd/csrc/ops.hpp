@@ -1,0 +1,84 @@
+// Per-family, per-precision kernel launchers. Each translation unit instantiates the
+// generic kernels for one model in one precision mode and exports one FamilyOps table;
+// the C-ABI layer dispatches on (family, dtype).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace mc {
+
+struct FamilyOps {
+  int family;
+  int f64;      // 1: FP64 mode tables (IO = double, S = double)
+  int dof_max;  // compiled D (padded for the linear family)
+  hipError_t (*project_persistent)(const ProjArgs& a, int grid, int block, hipStream_t s);
+  hipError_t (*project_plain)(const ProjArgs& a, hipStream_t s);
+  hipError_t (*check)(const CheckArgs& a, int minsd, hipStream_t s);
+  hipError_t (*vjp)(const VjpArgs& a, hipStream_t s);
+  hipError_t (*eval_fj)(const DevProblem* P, int64_t n, const void* q, int64_t ld, void* F, void* J, hipStream_t s);
+  int (*persistent_blocks_per_cu)(int block);
+  size_t (*lds_bytes)(int block);
+};
+
+inline unsigned blocks_for(int64_t n, int block) { return unsigned((n + block - 1) / block); }
+
+template <class Model, class IO, class S>
+struct OpsImpl {
+  static size_t lds_bytes(int block) { return size_t(Model::D) * sizeof(double) * size_t(block); }
+  static hipError_t project_persistent(const ProjArgs& a, int grid, int block, hipStream_t s) {
+    hipLaunchKernelGGL((k_project_persistent<Model, IO, S>), dim3(grid), dim3(block), lds_bytes(block), s, a);
+    return hipGetLastError();
+  }
+  static hipError_t project_plain(const ProjArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_project_plain<Model, IO, S>), dim3(blocks_for(a.n, 64)), dim3(64), lds_bytes(64), s, a);
+    return hipGetLastError();
+  }
+  static hipError_t check(const CheckArgs& a, int minsd, hipStream_t s) {
+    const dim3 g(blocks_for(a.n, 256)), b(256);
+    if (minsd) hipLaunchKernelGGL((k_check<Model, IO, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_check<Model, IO, false>), g, b, 0, s, a);
+    return hipGetLastError();
+  }
+  static hipError_t vjp(const VjpArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_vjp<Model, IO, S>), dim3(blocks_for(a.n, 64)), dim3(64), lds_bytes(64), s, a);
+    return hipGetLastError();
+  }
+  static hipError_t eval_fj(const DevProblem* P, int64_t n, const void* q, int64_t ld, void* F, void* J, hipStream_t s) {
+    hipLaunchKernelGGL((k_eval_fj<Model, IO, S>), dim3(blocks_for(n, 64)), dim3(64), 0, s, P, n, q, ld, F, J);
+    return hipGetLastError();
+  }
+  static int persistent_blocks_per_cu(int block) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_project_persistent<Model, IO, S>),
+                                                     block, lds_bytes(block)) != hipSuccess)
+      return 1;
+    return nb > 0 ? nb : 1;
+  }
+  static FamilyOps make() {
+    FamilyOps o;
+    o.family = Model::family;
+    o.f64 = std::is_same<S, double>::value ? 1 : 0;
+    o.dof_max = Model::D;
+    o.project_persistent = &project_persistent;
+    o.project_plain = &project_plain;
+    o.check = &check;
+    o.vjp = &vjp;
+    o.eval_fj = &eval_fj;
+    o.persistent_blocks_per_cu = &persistent_blocks_per_cu;
+    o.lds_bytes = &lds_bytes;
+    return o;
+  }
+};
+
+#define MC_FAMILY_TABLE(name) \
+  extern const FamilyOps ops_##name##_f32; \
+  extern const FamilyOps ops_##name##_f64;
+MC_FAMILY_TABLE(sphere3)
+MC_FAMILY_TABLE(linear)
+MC_FAMILY_TABLE(planar2)
+MC_FAMILY_TABLE(arm7_axis)
+MC_FAMILY_TABLE(dual14_rel)
+MC_FAMILY_TABLE(humanoid36)
+#undef MC_FAMILY_TABLE
+
+}  // namespace mc
