@@ -43,7 +43,7 @@ def compare(P, q, r, tol, max_iter, qtol, require_iters=True, min_agree=0.98, ma
     # statuses agree outside the band
     bad = out & (gst != st)
     assert bad.sum() == 0, f"status mismatch on {bad.sum()} configs, e.g. idx {np.where(bad)[0][:5]}: gpu {gst[bad][:5]} oracle {st[bad][:5]}"
-    both = (gst == CONV) & (st == CONV)
+    both = (gst == CONV) & (st == CONV) & out
     err = np.abs(gq[both] - qo[both]).max(axis=1) if both.any() else np.zeros(0)
     assert (err <= qtol).all(), f"q mismatch: max {err.max():.3e} on {np.sum(err > qtol)} configs"
     agree = (git == it)[out & both]
@@ -161,7 +161,9 @@ def test_residual_and_jacobian_match_oracle(mc, name):
 # ---------------------------------------------------------------- projection parity
 # C1's specified inputs (uniform random joint vectors, far from the manifold) send most min-norm
 # Newton paths through near-singular Jacobians; those configurations are band (property-checked).
-MAX_BAND = {"c0": 0.05, "c1": 0.85, "c2": 0.05, "c3": 0.05}
+# C0 chords pass near the origin, where the first radial (Heron) step is longer than 1: not
+# chaotic, but band by the step rule; the closed-form test covers those radii exactly.
+MAX_BAND = {"c0": 0.10, "c1": 0.85, "c2": 0.05, "c3": 0.05}
 
 
 @pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3"])
