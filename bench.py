@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched manifold projection on one MI355X.
+
+Headline: converged projections/s on the 36-DoF humanoid batch (65,536 configurations =
+2,048 geodesics x 32 interior interpolants between projected endpoints, tol 1e-6, at most
+40 Newton steps, collision check against 500 shelf spheres fused into the step), with the
+fused persistent work-queue kernel. Also measured: the plain per-geodesic launch on the same
+batch, and fwd+VJP/s on the differentiation batch (2,048 geodesics of 8..64 interpolants:
+projection + path-length gradient + VJP).
+
+A "step" is one pass of the whole hot path over the batch, inputs resident in HBM. Timing:
+HIP events on the stream the kernels run on, W untimed warm-up steps, then K timed steps.
+Prints one JSON line (last line of stdout).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import glob
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_VALU_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz (non-packed FP32 and FP64)
+PEAK_FP32_PACKED_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2604_13323_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def timed(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps  # ms per step
+
+
+def build_batch(G, cfg, torch):
+    """Project the geodesic endpoints (library, untimed) and interpolate the interior points."""
+    sc = cfg["scene"]
+    E = cfg["endpoints"].reshape(-1, sc.d)  # rows 2g, 2g+1 = the two ends of geodesic g
+    e = torch.from_numpy(np.ascontiguousarray(E.T)).to("cuda", torch.float32)
+    re = G.project(e, tol=1e-9, max_iter=100, check=False)
+    offs = torch.from_numpy(np.asarray(cfg["geo_offsets"], np.int32)).cuda()
+    n = int(cfg["geo_offsets"][-1])
+    q = G.interpolate(re.q, offs, n)
+    torch.cuda.synchronize()
+    return q, offs, re
+
+
+def cpu_baseline(cfg, max_configs: int):
+    """The FP64 oracle on the same workload recipe (its own endpoint projection and interpolation)."""
+    import oracle
+    sc = cfg["scene"]
+    P = oracle.Problem(sc.to_blob())
+    offs = np.asarray(cfg["geo_offsets"], np.int32)
+    n_geo = len(offs) - 1
+    per = int(offs[1] - offs[0])
+    g_take = max(1, min(n_geo, max_configs // max(per, 1)))
+    offs = offs[:g_take + 1]
+    e = cfg["endpoints"][:g_take].reshape(-1, sc.d)
+    qe = P.project(e, tol=1e-9, max_iter=100)[0]
+    q = oracle.interpolate_interior(qe.reshape(-1, 2, sc.d), offs)
+    t0 = time.perf_counter()
+    qo, st, it, rs = P.project(q, tol=cfg["tol"], max_iter=cfg["max_iter"])
+    conv = st == 0
+    v, _ = P.check(qo[conv])
+    dt = time.perf_counter() - t0
+    return dict(value=float(conv.sum() / dt), unit="converged projections/s", cores=oracle.max_threads(),
+                kind="oracle",
+                sample=f"{len(q)} configurations ({g_take} geodesics x {per}) of the humanoid batch, "
+                       f"projection + brute-force collision check, FP64, {dt:.2f} s",
+                seconds=dt, n=int(len(q)))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-vjp", action="store_true")
+    ap.add_argument("--cpu-max-configs", type=int, default=65536)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration for profiling runs)")
+    ap.add_argument("--waves-per-block", type=int, default=0)
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the projection shards by whole "
+              "geodesics with no collective in the hot loop, see DESIGN.md.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2604_13323_amd as M
+    from paper_2604_13323_amd import flops as FL
+    from paper_2604_13323_amd import scenes as S
+
+    M.lib()  # the HIP library must be present: there is no fallback
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a HIP device")
+    torch.cuda.set_device(0)
+
+    cfg = S.make_config("c3")
+    sc = cfg["scene"]
+    G = M.Problem(sc.to_blob())
+    q_in, offs, _ = build_batch(G, cfg, torch)
+    n = q_in.shape[1]
+    tol, mi = cfg["tol"], cfg["max_iter"]
+    kw = dict(tol=tol, max_iter=mi, waves_per_block=args.waves_per_block, blocks_per_cu=args.blocks_per_cu)
+    out = G.project(q_in, variant="fused", **kw)
+    torch.cuda.synchronize()
+    log(f"humanoid batch: {n} configurations built; first projection done")
+
+    # --- headline: fused persistent projection + collision check
+    G.fallback_count(reset=True)
+    ms = timed(lambda: G.project(q_in, variant="fused", out=out, **kw), args.steps, args.warmup, torch)
+    status = out.status.cpu().numpy()
+    iters = out.iters.cpu().numpy().astype(np.int64)
+    verdict = out.verdict.cpu().numpy()
+    n_conv = int((status == 0).sum())
+    fallbacks = G.fallback_count(reset=True)
+    value = n_conv / (ms * 1e-3)
+    log(f"fused: {ms:.3f} ms/step, {value:.4g} converged projections/s, converged {n_conv}/{n}")
+
+    # --- the dominant kernel alone (projection without the check): its launch duration
+    out_nc = M.ProjectResult(q=torch.empty_like(out.q), status=torch.empty_like(out.status),
+                             iters=torch.empty_like(out.iters), resid=torch.empty_like(out.resid),
+                             verdict=None, geo_ok=None)
+    ms_proj = timed(lambda: G.project(q_in, variant="fused", out=out_nc, check=False, **kw), args.steps,
+                    args.warmup, torch)
+    ms_check = timed(lambda: G.check(out.q), args.steps, args.warmup, torch)
+    flop = FL.batch_flops(sc, iters)
+    achieved_tflops = flop / (ms_proj * 1e-3) / 1e12
+    log(f"projection kernel alone: {ms_proj:.3f} ms, {achieved_tflops:.2f} TFLOP/s algorithmic; "
+        f"check alone {ms_check:.3f} ms")
+
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic_projection_humanoid36.json")
+    if os.path.exists(tpath):
+        with open(tpath) as f:
+            t = json.load(f)
+        if t.get("source_hash") == source_hash():
+            traffic = t.get("bytes_per_launch")
+
+    # --- plain per-geodesic launches on the same batch
+    plain = None
+    if not args.no_plain:
+        offs_host = np.asarray(cfg["geo_offsets"], np.int32)
+        outp = G.project(q_in, variant="plain", geo_offsets=offs_host, **kw)
+        ms_plain = timed(lambda: G.project(q_in, variant="plain", geo_offsets=offs_host, out=outp, **kw),
+                         args.plain_steps, 1, torch)
+        same = bool(torch.equal(outp.q, out.q) and torch.equal(outp.status, out.status))
+        plain = dict(ms_per_step=ms_plain, value=n_conv / (ms_plain * 1e-3), launches=len(offs_host) - 1,
+                     identical_outputs=same)
+        log(f"plain: {ms_plain:.3f} ms/step ({plain['value']:.4g}/s), outputs identical to fused: {same}")
+
+    # --- fwd + VJP on the differentiation batch
+    fv = None
+    if not args.no_vjp:
+        cfg4 = S.make_config("c4")
+        q4, offs4, _ = build_batch(G, cfg4, torch)
+        n4 = q4.shape[1]
+        o4 = G.project(q4, variant="fused", **kw)
+
+        def fwd_vjp():
+            G.project(q4, variant="fused", out=o4, **kw)
+            g, _ = G.path_length_grad(o4.q, offs4)
+            G.vjp(o4.q, o4.status, g)
+
+        ms4 = timed(fwd_vjp, args.steps, args.warmup, torch)
+        fv = dict(value=n4 / (ms4 * 1e-3), unit="configurations/s", ms_per_step=ms4, configs=n4,
+                  geodesics=len(cfg4["geo_offsets"]) - 1)
+        log(f"fwd+vjp: {ms4:.3f} ms/step, {fv['value']:.4g} configurations/s")
+
+    if args.copy_calibration:
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(cfg, args.cpu_max_configs)
+        log(f"cpu baseline: {cpu['value']:.4g} converged projections/s on {cpu['cores']} threads")
+
+    result = {
+        "metric": "converged projections/s at 36-DoF + fwd+VJP/s, fused-batched vs plain, tol 1e-6",
+        "value": value,
+        "unit": "converged projections/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "humanoid36: 65,536 configurations (2,048 geodesics x 32 interior points between "
+                               "projected endpoints), 36 DoF, 20 rows, 248 robot spheres vs 500 obstacle spheres, "
+                               "tol 1e-6, max 40 steps, fused persistent kernel + collision check",
+                   "configs": n, "geodesics": len(cfg["geo_offsets"]) - 1},
+        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tflops / PEAK_VALU_TFLOPS, "traffic": traffic,
+                     "kernel": "k_project_persistent<humanoid36, FP32 mode>", "kernel_ms": ms_proj,
+                     "flop_per_launch": flop, "frac_vs_packed_fp32_peak": achieved_tflops / PEAK_FP32_PACKED_TFLOPS},
+        "cpu_baseline": cpu,
+        "plain": plain,
+        "fused_vs_plain": (value / plain["value"]) if plain else None,
+        "fwd_vjp": fv,
+        "stats": {"converged_frac": n_conv / n, "iters_mean": float(iters.mean()),
+                  "iters_p99": float(np.percentile(iters, 99)), "iters_max": int(iters.max()),
+                  "collision_free_frac_of_converged": float((verdict[status == 0] == 0).mean()) if n_conv else None,
+                  "fp64_fallbacks_per_step": fallbacks / max(1, args.steps + args.warmup),
+                  "check_ms": ms_check, "projection_ms": ms_proj,
+                  "gpu": torch.cuda.get_device_name(0)},
+    }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,149 @@
+"""Algorithmic FLOP counts of one Newton iteration and of the final residual evaluation.
+
+These are the operations the method has to perform per configuration (FMA = 2 FLOP),
+counted from the scene's structure: forward kinematics once per iteration, the residual,
+the Jacobian columns once, the Gram matrix J J^T over structural nonzeros, the Cholesky
+factorisation and two triangular solves over the nonzeros of the factor, J^T y and the
+update. Recomputations an implementation makes (the library re-runs the kinematics in its
+Gram and J^T y passes to save registers) are not counted; sine/cosine, square roots and
+reciprocals count as one FLOP each.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import scenes as S
+
+
+def _ancestor(parents, j, l):
+    k = l
+    while k >= 0:
+        if k == j:
+            return True
+        k = parents[k]
+    return False
+
+
+def _block_rows(b, m_total):
+    if b.btype in (S.BLK_POSE, S.BLK_REL):
+        return bin(b.mask & 0x3F).count("1")
+    if b.btype in (S.BLK_AXIS, S.BLK_COM):
+        return 2
+    if b.btype == S.BLK_SPHERE:
+        return 1
+    return m_total
+
+
+def jacobian_pattern(sc: S.Scene) -> np.ndarray:
+    """Structural nonzero pattern of J (m x d) for kinematic scenes."""
+    parents = [j.parent for j in sc.joints]
+    rows = []
+    for b in sc.blocks:
+        nr = _block_rows(b, sc.m)
+        comps = [c for c in range(6) if (b.mask >> c) & 1] if b.btype in (S.BLK_POSE, S.BLK_REL) else list(range(nr))
+        for c in comps:
+            row = np.zeros(sc.d, bool)
+            for j in range(sc.d):
+                jt = sc.joints[j].jtype
+                if b.btype == S.BLK_POSE:
+                    dep = _ancestor(parents, j, sc.frames[b.fa].link)
+                elif b.btype == S.BLK_REL:
+                    dep = _ancestor(parents, j, sc.frames[b.fa].link) != _ancestor(parents, j, sc.frames[b.fb].link)
+                elif b.btype == S.BLK_AXIS:
+                    dep = _ancestor(parents, j, sc.frames[b.fa].link) and jt == S.JOINT_REV
+                else:  # COM
+                    dep = True
+                if b.btype in (S.BLK_POSE, S.BLK_REL) and c >= 3 and jt == S.JOINT_PRI:
+                    dep = False
+                row[j] = dep
+            rows.append(row)
+    return np.array(rows)
+
+
+def _chol_counts(Gnz: np.ndarray):
+    m = Gnz.shape[0]
+    L = np.tril(Gnz).copy()
+    for k in range(m):
+        for i in range(k + 1, m):
+            for j in range(k + 1, i + 1):
+                if L[i, k] and L[j, k]:
+                    L[i, j] = True
+    chol = 0
+    for k in range(m):
+        chol += 2  # square root and reciprocal
+        below = [i for i in range(k + 1, m) if L[i, k]]
+        chol += len(below)
+        for i in below:
+            chol += 2 * sum(1 for j in range(k + 1, i + 1) if L[j, k])
+    offdiag = int(np.tril(L, -1).sum())
+    solves = 2 * (2 * offdiag + m)
+    return chol, solves
+
+
+def iteration_flops(sc: S.Scene) -> dict:
+    """Per-iteration FLOP components and the final-evaluation FLOPs for one configuration."""
+    d, m = sc.d, sc.m
+    if sc.family == S.FAMILY_SPHERE:
+        res = 6
+        it = dict(fk=0, residual=res, jacobian=3, gram=6, cholesky=2, solve=2, jty=6, update=4 * d)
+        return dict(per_iter=sum(it.values()), final=res, parts=it)
+    if sc.family == S.FAMILY_LINEAR:
+        res = 2 * m * d + 2 * m
+        gram = m * (m + 1) * d
+        chol, solves = _chol_counts(np.ones((m, m), bool))
+        it = dict(fk=0, residual=res, jacobian=0, gram=gram, cholesky=chol, solve=solves, jty=2 * m * d, update=4 * d)
+        return dict(per_iter=sum(it.values()), final=res, parts=it)
+
+    fk = 0
+    for j, J in enumerate(sc.joints):
+        rot = not np.allclose(J.R, np.eye(3))
+        if J.parent >= 0:
+            fk += 18 + (45 if rot else 0)
+        fk += 18 if J.jtype == S.JOINT_REV else 6
+        fk += 1 if J.jtype == S.JOINT_REV else 0  # sine and cosine
+    frames = sum(18 + (0 if np.allclose(f.R, np.eye(3)) else 45) for f in sc.frames)
+    massive = int(np.count_nonzero(sc.masses)) if sc.masses is not None else 0
+    res = 0
+    cols = 0
+    Jp = jacobian_pattern(sc)
+    for b in sc.blocks:
+        if b.btype == S.BLK_POSE:
+            res += 3 + 15 + 45 + 25
+            cols += 45 + 20  # A = J_l^-1 W and J_l^-1
+        elif b.btype == S.BLK_REL:
+            res += 45 + 3 + 15 + 3 + 45 + 25
+            cols += 45 + 20
+        elif b.btype == S.BLK_COM:
+            res += 24 * massive + 4
+            cols += 6 * massive
+    res += 2 * m  # norm
+    r = 0
+    for b in sc.blocks:
+        nr = _block_rows(b, m)
+        for j in range(d):
+            dep = Jp[r:r + nr, j].any()
+            if not dep:
+                continue
+            rev = sc.joints[j].jtype == S.JOINT_REV
+            if b.btype in (S.BLK_POSE, S.BLK_REL):
+                cols += 42 if rev else 15
+            elif b.btype == S.BLK_AXIS:
+                cols += 6
+            elif b.btype == S.BLK_COM:
+                cols += 17 if rev else 3
+        r += nr
+    nnz_col = Jp.sum(axis=0)
+    gram = int(sum(2 * k * (k + 1) // 2 for k in nnz_col))
+    Gnz = (Jp.astype(int) @ Jp.T.astype(int)) > 0
+    chol, solves = _chol_counts(Gnz)
+    jty = 2 * int(Jp.sum())
+    it = dict(fk=fk + frames, residual=res, jacobian=cols, gram=gram, cholesky=chol, solve=solves, jty=jty,
+              update=4 * d)
+    return dict(per_iter=sum(it.values()), final=fk + frames + res, parts=it)
+
+
+def batch_flops(sc: S.Scene, iters: np.ndarray) -> float:
+    """Algorithmic FLOPs of projecting a batch whose per-configuration step counts are `iters`."""
+    f = iteration_flops(sc)
+    iters = np.asarray(iters, np.int64)
+    return float(f["per_iter"] * iters.sum() + f["final"] * iters.size)
