@@ -112,7 +112,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the projection shards by whole "
-              "geodesics with no collective in the hot loop, see DESIGN.md.", file=sys.stderr)
+              "geodesics with no collective in the hot loop.", file=sys.stderr)
         sys.exit(2)
 
     import torch

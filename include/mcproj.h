@@ -82,8 +82,10 @@ typedef struct {
   double alpha;               /* step scale (Alg. 2 alpha), default 1                           */
   double lambda;              /* damping (Alg. 2 lambda), >= 0, default 0                       */
   double max_step;            /* > 0: DIVERGED when ||alpha * step|| > max_step; <= 0: off       */
-  double fp64_cond_threshold; /* FP32 mode: redo the step in FP64 when the FP32 Cholesky's
-                                 condition estimate (max L_ii / min L_ii)^2 exceeds this (1e6) */
+  double fp64_cond_threshold; /* FP32 mode: when the FP32 Cholesky of J J^T fails or its
+                                 condition estimate (max L_ii / min L_ii)^2 exceeds this (1e6),
+                                 the step is redone in FP64 and that configuration takes FP64
+                                 steps until it terminates                                     */
   int32_t check_collision;    /* 1: collision-check CONVERGED configurations into `verdict`      */
   int32_t variant;            /* 0 auto (autotuned), 1 plain (one launch per geodesic),
                                  2 fused (persistent work-queue kernel over the whole batch)     */
@@ -96,7 +98,9 @@ typedef struct {
    check on, variant auto). */
 void mc_default_opts(mc_project_opts* opts);
 
-/* Create a problem from a scene blob (format documented in the design doc; magic 'MCCS', version 1):
+/* Create a problem from a scene blob (magic 'MCCS', version 1: the little-endian layout written
+   by Scene.to_blob in paper_2604_13323_amd/scenes.py, a 16-int header followed by joints, links,
+   frames, constraint blocks, robot spheres, obstacles and the optional q_ref, A, b):
    parses and validates the blob on the host, checks that its kinematic structure matches a
    compiled family, derives the constants the kernels need (reference poses of blocks flagged
    ref_from_qref, subtree masses, link bounding spheres, obstacle clusters) and copies them
@@ -133,6 +137,10 @@ const char* mc_last_error(void);
    HOST as well: pass geo_offsets_host (nullable) with the same content. geo_ok (nullable,
    uint8[n_geo], device) receives 1 when every configuration of the geodesic converged and is
    collision-free (the early exit of Alg. 2 as a per-geodesic flag).
+   Workspace: in MC_F32 mode the fused variant hands configurations that need FP64 steps to a
+   second kernel through a queue owned by the problem; a call with a larger n than any before
+   grows it (hipFree + hipMalloc, which synchronise the device). Calls on one problem must not
+   overlap (one stream at a time).
    Errors: MC_ERR_INVALID_ARG for null required pointers, n < 0, ld < n, tol <= 0,
    max_iter outside 0..127, lambda < 0, alpha <= 0, dtype mismatch, plain variant without
    geo_offsets_host. */
@@ -153,8 +161,9 @@ mc_status check_batch(const mc_problem* p, int64_t n, const void* q, int64_t ld,
 /* project_vjp — vector-Jacobian product through the converged projection (implicit
    differentiation at the converged point): g_in = (I - J^+ J) g_out with J = J(q_proj),
    computed as g_out - J^T (J J^T)^-1 J g_out. Exact for on-manifold inputs. In MC_F32 mode the
-   Gram solve runs in FP32 and switches to FP64 for configurations whose condition estimate
-   exceeds opts->fp64_cond_threshold. Configurations whose status is not MC_CONVERGED get
+   Gram solve runs in FP32; configurations whose FP32 factorisation fails or whose condition
+   estimate exceeds opts->fp64_cond_threshold are redone in FP64 by a second kernel (queue
+   grown like project_batch's). Configurations whose status is not MC_CONVERGED get
    g_in = 0. Arrays q_proj, g_out, g_in are [d][ld] of opts->dtype. */
 mc_status project_vjp(const mc_problem* p, int64_t n, const void* q_proj, int64_t ld,
                       const int8_t* status, const void* g_out, void* g_in,
@@ -183,9 +192,9 @@ mc_status path_length_grad(const mc_problem* p, int64_t n, const void* q, int64_
 mc_status mc_eval_residual_jacobian(const mc_problem* p, int64_t n, const void* q, int64_t ld,
                                     mc_dtype dtype, void* F, void* J, void* stream);
 
-/* mc_fallback_count — number of FP64 step fallbacks taken by the calls enqueued on this problem
-   since it was created or last reset (reset = 1 zeroes it after reading). Synchronises the
-   device. */
+/* mc_fallback_count — number of configurations moved to FP64 (projections that switched to FP64
+   steps, VJPs redone in FP64) by the calls enqueued on this problem since it was created or last
+   reset (reset = 1 zeroes it after reading). Synchronises the device. */
 mc_status mc_fallback_count(const mc_problem* p, int reset, uint64_t* count);
 
 #ifdef __cplusplus

@@ -296,7 +296,9 @@ void fill_tp(TP<T>& t, const HScene& s, const std::vector<HT>& tref, const std::
 }
 
 // ------------------------------------------------------------------ utility kernels
-__global__ void k_reset_u32(unsigned int* p) { *p = 0u; }
+__global__ void k_reset_u32(unsigned int* p, int n) {
+  if (int(threadIdx.x) < n) p[threadIdx.x] = 0u;
+}
 
 __global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -380,11 +382,42 @@ struct mc_problem {
   size_t max_lds_per_block = 0;
   DevProblem* dev = nullptr;
   float4* obs = nullptr;
-  float4* clus = nullptr;
-  int2* clus_range = nullptr;
-  unsigned int* counter = nullptr;
+  int n_obs = 0;
+  unsigned int* counter = nullptr;  // [0] work-queue head, [1] projection FP64 queue, [2] VJP FP64 queue
   unsigned long long* fallback = nullptr;
+  // FP64 tail queues (FP32 mode), grown to the largest batch seen; calls on one handle must not
+  // overlap (one stream at a time).
+  mutable double* defer_q = nullptr;
+  mutable int32_t* defer_ik = nullptr;
+  mutable int64_t defer_cap = 0;
+  mutable int32_t* vjp_idx = nullptr;
+  mutable int64_t vjp_cap = 0;
 };
+
+// Grow a tail queue to hold n entries (synchronises the device when it reallocates).
+static hipError_t grow_defer(const mc_problem* p, int64_t n, int dmax) {
+  if (n <= p->defer_cap) return hipSuccess;
+  hipError_t e;
+  if (p->defer_q && (e = hipFree(p->defer_q)) != hipSuccess) return e;
+  if (p->defer_ik && (e = hipFree(p->defer_ik)) != hipSuccess) return e;
+  p->defer_q = nullptr;
+  p->defer_ik = nullptr;
+  p->defer_cap = 0;
+  if ((e = hipMalloc((void**)&p->defer_q, size_t(n) * size_t(dmax) * sizeof(double))) != hipSuccess) return e;
+  if ((e = hipMalloc((void**)&p->defer_ik, size_t(n) * 2 * sizeof(int32_t))) != hipSuccess) return e;
+  p->defer_cap = n;
+  return hipSuccess;
+}
+static hipError_t grow_vjp(const mc_problem* p, int64_t n) {
+  if (n <= p->vjp_cap) return hipSuccess;
+  hipError_t e;
+  if (p->vjp_idx && (e = hipFree(p->vjp_idx)) != hipSuccess) return e;
+  p->vjp_idx = nullptr;
+  p->vjp_cap = 0;
+  if ((e = hipMalloc((void**)&p->vjp_idx, size_t(n) * sizeof(int32_t))) != hipSuccess) return e;
+  p->vjp_cap = n;
+  return hipSuccess;
+}
 
 extern "C" {
 
@@ -413,10 +446,11 @@ void mc_problem_destroy(mc_problem* p) {
   if (!p) return;
   hipFree(p->dev);
   hipFree(p->obs);
-  hipFree(p->clus);
-  hipFree(p->clus_range);
   hipFree(p->counter);
   hipFree(p->fallback);
+  hipFree(p->defer_q);
+  hipFree(p->defer_ik);
+  hipFree(p->vjp_idx);
   delete p;
 }
 
@@ -452,34 +486,33 @@ mc_status mc_problem_create(const void* blob, size_t nbytes, mc_problem** out) {
 
   DevProblem* hp = new DevProblem;
   std::memset(hp, 0, sizeof(DevProblem));
-  fill_tp<double>(hp->d, s, tref, submass, Mtot);
-  fill_tp<float>(hp->f, s, tref, submass, Mtot);
-  hp->dof = s.d;
-  hp->rows = s.m;
-  hp->family = s.family;
-  hp->lin_d = s.family == MC_FAMILY_LINEAR ? s.d : 0;
-  hp->lin_m = s.family == MC_FAMILY_LINEAR ? s.m : 0;
+  fill_tp<double>(hp->c.d, s, tref, submass, Mtot);
+  fill_tp<float>(hp->c.f, s, tref, submass, Mtot);
+  hp->c.dof = s.d;
+  hp->c.rows = s.m;
+  hp->c.lin_m = s.family == MC_FAMILY_LINEAR ? s.m : 0;
+  CollConsts& K = hp->k;
 
   // robot spheres grouped by link, link bounding spheres
   std::vector<HSphere> sph = s.spheres;
   std::stable_sort(sph.begin(), sph.end(), [](const HSphere& a, const HSphere& b) { return a.link < b.link; });
-  hp->n_sph = int(sph.size());
-  hp->point_sph = make_float4(0.f, 0.f, 0.f, -1.f);
+  K.n_sph = int(sph.size());
+  K.point_sph = make_float4(0.f, 0.f, 0.f, -1.f);
   int idx = 0;
-  for (int l = 0; l <= MAXJ; ++l) hp->sph_begin[l] = 0;
+  for (int l = 0; l <= MAXJ; ++l) K.sph_begin[l] = 0;
   std::vector<HSphere> linked;
   for (const auto& sp : sph) {
-    if (sp.link < 0) hp->point_sph = make_float4(float(sp.c[0]), float(sp.c[1]), float(sp.c[2]), float(sp.r));
+    if (sp.link < 0) K.point_sph = make_float4(float(sp.c[0]), float(sp.c[1]), float(sp.c[2]), float(sp.r));
     else linked.push_back(sp);
   }
-  if (s.family == MC_FAMILY_SPHERE && sph.empty()) hp->point_sph = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (s.family == MC_FAMILY_SPHERE && sph.empty()) K.point_sph = make_float4(0.f, 0.f, 0.f, 0.f);
   for (int l = 0; l < MAXJ; ++l) {
-    hp->sph_begin[l] = idx;
+    K.sph_begin[l] = idx;
     double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
     const int first = idx;
     for (const auto& sp : linked) {
       if (sp.link != l) continue;
-      hp->sph[idx++] = make_float4(float(sp.c[0]), float(sp.c[1]), float(sp.c[2]), float(sp.r));
+      K.sph[idx++] = make_float4(float(sp.c[0]), float(sp.c[1]), float(sp.c[2]), float(sp.r));
       for (int a = 0; a < 3; ++a) { mn[a] = std::min(mn[a], sp.c[a]); mx[a] = std::max(mx[a], sp.c[a]); }
     }
     if (idx > first) {
@@ -490,26 +523,33 @@ mc_status mc_problem_create(const void* blob, size_t nbytes, mc_problem** out) {
         const double dx = sp.c[0] - c[0], dy = sp.c[1] - c[1], dz = sp.c[2] - c[2];
         r = std::max(r, std::sqrt(dx * dx + dy * dy + dz * dz) + sp.r);
       }
-      hp->link_bs[l] = make_float4(float(c[0]), float(c[1]), float(c[2]), float(r + kBoundMargin));
+      K.link_bs[l] = make_float4(float(c[0]), float(c[1]), float(c[2]), float(r + kBoundMargin));
     } else {
-      hp->link_bs[l] = make_float4(0.f, 0.f, 0.f, -1.f);
+      K.link_bs[l] = make_float4(0.f, 0.f, 0.f, -1.f);
     }
   }
-  hp->sph_begin[MAXJ] = idx;
+  for (int l = MAXJ; l < MAXJ + 4; ++l) K.sph_begin[l] = idx;
 
   // obstacle clusters
   std::vector<std::array<double, 4>> obs = s.obs;
   std::vector<std::array<double, 4>> cl;
   std::vector<std::array<int, 2>> rg;
+  if (obs.size() > size_t(MAXO)) {
+    delete hp;
+    return fail(MC_ERR_UNSUPPORTED, "more than 2048 obstacle spheres");
+  }
   if (!obs.empty()) build_clusters(obs, 0, int(obs.size()), cl, rg);
-  hp->n_obs = int(obs.size());
-  hp->n_clus = int(cl.size());
-  std::vector<float4> obs_f(obs.size()), cl_f(cl.size());
-  std::vector<int2> rg_i(rg.size());
+  if (cl.size() > size_t(MAXC)) {
+    delete hp;
+    return fail(MC_ERR_UNSUPPORTED, "too many obstacle clusters");
+  }
+  K.n_obs = int(obs.size());
+  K.n_clus = int(cl.size());
+  std::vector<float4> obs_f(obs.size());
   for (size_t i = 0; i < obs.size(); ++i) obs_f[i] = make_float4(float(obs[i][0]), float(obs[i][1]), float(obs[i][2]), float(obs[i][3]));
   for (size_t i = 0; i < cl.size(); ++i) {
-    cl_f[i] = make_float4(float(cl[i][0]), float(cl[i][1]), float(cl[i][2]), float(cl[i][3]));
-    rg_i[i] = make_int2(rg[i][0], rg[i][1]);
+    K.clus[i] = make_float4(float(cl[i][0]), float(cl[i][1]), float(cl[i][2]), float(cl[i][3]));
+    K.clus_range[i] = make_int2(rg[i][0], rg[i][1]);
   }
 
   mc_problem* p = new mc_problem;
@@ -525,25 +565,21 @@ mc_status mc_problem_create(const void* blob, size_t nbytes, mc_problem** out) {
   auto alloc = [&](void** ptr, size_t bytes) -> hipError_t { return hipMalloc(ptr, bytes > 0 ? bytes : 16); };
   if ((e = alloc((void**)&p->dev, sizeof(DevProblem))) != hipSuccess ||
       (e = alloc((void**)&p->obs, obs_f.size() * sizeof(float4))) != hipSuccess ||
-      (e = alloc((void**)&p->clus, cl_f.size() * sizeof(float4))) != hipSuccess ||
-      (e = alloc((void**)&p->clus_range, rg_i.size() * sizeof(int2))) != hipSuccess ||
-      (e = alloc((void**)&p->counter, sizeof(unsigned int))) != hipSuccess ||
+      (e = alloc((void**)&p->counter, 4 * sizeof(unsigned int))) != hipSuccess ||
       (e = alloc((void**)&p->fallback, sizeof(unsigned long long))) != hipSuccess) {
     mc_problem_destroy(p);
     delete hp;
     return hip_fail(e, "mc_problem_create: hipMalloc");
   }
   hp->obs = p->obs;
-  hp->clus = p->clus;
-  hp->clus_range = p->clus_range;
   hp->fallback_counter = p->fallback;
+  p->n_obs = K.n_obs;
   const unsigned long long zero64 = 0;
-  const unsigned int zero32 = 0;
+  const unsigned int zero32[4] = {0, 0, 0, 0};
   if ((e = hipMemcpy(p->dev, hp, sizeof(DevProblem), hipMemcpyHostToDevice)) != hipSuccess ||
       (!obs_f.empty() && (e = hipMemcpy(p->obs, obs_f.data(), obs_f.size() * sizeof(float4), hipMemcpyHostToDevice)) != hipSuccess) ||
-      (!cl_f.empty() && (e = hipMemcpy(p->clus, cl_f.data(), cl_f.size() * sizeof(float4), hipMemcpyHostToDevice)) != hipSuccess) ||
-      (!rg_i.empty() && (e = hipMemcpy(p->clus_range, rg_i.data(), rg_i.size() * sizeof(int2), hipMemcpyHostToDevice)) != hipSuccess) ||
-      (e = hipMemcpy(p->counter, &zero32, sizeof zero32, hipMemcpyHostToDevice)) != hipSuccess ||
+
+      (e = hipMemcpy(p->counter, zero32, sizeof zero32, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p->fallback, &zero64, sizeof zero64, hipMemcpyHostToDevice)) != hipSuccess) {
     mc_problem_destroy(p);
     delete hp;
@@ -614,6 +650,7 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
   a.max_iter = opts->max_iter;
   a.check = opts->check_collision;
   a.counter = p->counter;
+  a.n_obs = p->n_obs;
   hipError_t e;
   if (variant == 1) {
     a.verdict = verdict;
@@ -625,7 +662,7 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
     }
   } else {
     int wpb = opts->waves_per_block > 0 ? opts->waves_per_block : 1;
-    while (wpb > 1 && ops->lds_bytes(64 * wpb) > p->max_lds_per_block) wpb >>= 1;
+    while (wpb > 1 && ops->lds_bytes(64 * wpb) + sizeof(Consts) > p->max_lds_per_block) wpb >>= 1;
     const int block = 64 * wpb;
     int bpc = opts->blocks_per_cu > 0 ? opts->blocks_per_cu : ops->persistent_blocks_per_cu(block);
     int64_t grid = int64_t(p->n_cu) * bpc;
@@ -633,9 +670,18 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
     a.base = 0;
     a.n = n;
     a.n_static = std::min<int64_t>(n, grid * block);
-    hipLaunchKernelGGL(k_reset_u32, dim3(1), dim3(1), 0, s, p->counter);
+    const bool tail = ops->project_tail != nullptr;
+    if (tail) {
+      if ((e = grow_defer(p, n, ops->dof_max)) != hipSuccess) return hip_fail(e, "project_batch: FP64 queue allocation");
+      a.defer_count = p->counter + 1;
+      a.defer_ik = p->defer_ik;
+      a.defer_q = p->defer_q;
+      a.defer_cap = p->defer_cap;
+    }
+    hipLaunchKernelGGL(k_reset_u32, dim3(1), dim3(64), 0, s, p->counter, 2);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "project_batch: reset");
     if ((e = ops->project_persistent(a, int(grid), block, s)) != hipSuccess) return hip_fail(e, "project_batch: persistent launch");
+    if (tail && (e = ops->project_tail(a, p->n_cu, s)) != hipSuccess) return hip_fail(e, "project_batch: FP64 tail launch");
     if (verdict) {
       CheckArgs c;
       c.P = p->dev;
@@ -645,6 +691,7 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
       c.status = status;
       c.verdict = verdict;
       c.minsd = nullptr;
+      c.n_obs = p->n_obs;
       if (opts->check_collision) {
         if ((e = ops->check(c, 0, s)) != hipSuccess) return hip_fail(e, "project_batch: check launch");
       } else {
@@ -678,6 +725,7 @@ mc_status check_batch(const mc_problem* p, int64_t n, const void* q, int64_t ld,
   c.status = nullptr;
   c.verdict = verdict;
   c.minsd = min_signed_dist;
+  c.n_obs = p->n_obs;
   hipError_t e = ops->check(c, min_signed_dist != nullptr, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "check_batch: launch");
   return MC_OK;
@@ -703,8 +751,20 @@ mc_status project_vjp(const mc_problem* p, int64_t n, const void* q_proj, int64_
   a.g = g_out;
   a.g_in = g_in;
   a.cond_thr = opts->fp64_cond_threshold;
-  hipError_t e = ops->vjp(a, static_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return hip_fail(e, "project_vjp: launch");
+  a.defer_count = nullptr;
+  a.defer_idx = nullptr;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  const bool tail = ops->vjp_tail != nullptr;
+  if (tail) {
+    if ((e = grow_vjp(p, n)) != hipSuccess) return hip_fail(e, "project_vjp: FP64 queue allocation");
+    a.defer_count = p->counter + 2;
+    a.defer_idx = p->vjp_idx;
+    hipLaunchKernelGGL(k_reset_u32, dim3(1), dim3(64), 0, s, p->counter + 2, 1);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "project_vjp: reset");
+  }
+  if ((e = ops->vjp(a, s)) != hipSuccess) return hip_fail(e, "project_vjp: launch");
+  if (tail && (e = ops->vjp_tail(a, p->n_cu, s)) != hipSuccess) return hip_fail(e, "project_vjp: FP64 tail launch");
   return MC_OK;
 }
 

@@ -1,9 +1,12 @@
 // Shared device-side definitions of the mcproj HIP library (gfx950).
 //
-// Layout of a problem on the device (DevProblem): one struct in global memory
-// holding every per-scene constant in FP64 (residual precision) and FP32 (step
-// precision). All kernel accesses to it use wave-uniform addresses, so they
-// compile to scalar loads that stay in the scalar cache.
+// Data layout. A problem lives in global memory as one DevProblem. Its kinematic and
+// constraint constants (Consts: FP64 copy for the residual pass, FP32 copy for the step
+// passes) and its collision constants (CollConsts; obstacles follow in a separate array)
+// are copied into LDS by every workgroup when a kernel starts. All later reads are LDS
+// broadcasts (every lane reads the same address), which are short-latency and prefetched
+// one joint ahead along the kinematic walk; nothing on the hot path waits on the scalar
+// cache or on global memory. A lane's FP64 iterate is a column of a [D][blockDim] LDS array.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,6 +20,8 @@ constexpr int MAXF = 4;     // end-effector frames
 constexpr int MAXB = 4;     // constraint blocks
 constexpr int MAXM = 20;    // stacked rows
 constexpr int MAXS = 320;   // robot collision spheres
+constexpr int MAXC = 128;   // obstacle clusters
+constexpr int MAXO = 2048;  // obstacle spheres
 constexpr int LIN_D = 8;    // linear family: padded d
 constexpr int LIN_M = 6;    // linear family: padded m
 
@@ -42,24 +47,42 @@ struct TP {
   T b[LIN_M];
 };
 
-struct DevProblem {
+// Kinematic and constraint constants (copied to LDS by the projection kernels).
+struct alignas(16) Consts {
   TP<double> d;
   TP<float> f;
-  int32_t dof, rows, family, lin_d, lin_m;
-  int32_t n_sph, n_obs, n_clus;
-  int32_t sph_begin[MAXJ + 1];   // spheres of link l: [sph_begin[l], sph_begin[l+1])
+  int32_t dof, rows, lin_m, pad;
+};
+
+// Collision constants (copied to LDS by the kernels that check collisions); the
+// obstacles themselves follow as a dynamic LDS array of n_obs float4.
+struct alignas(16) CollConsts {
+  int32_t n_sph, n_obs, n_clus, pad;
+  int32_t sph_begin[MAXJ + 4];   // spheres of link l: [sph_begin[l], sph_begin[l+1])
   float4 sph[MAXS];              // local centre, radius
-  float4 link_bs[MAXJ];          // link bounding sphere: local centre, radius (inflated), w<0: none
+  float4 link_bs[MAXJ];          // link bounding sphere: local centre, radius (inflated); w < 0: none
   float4 point_sph;              // sphere family: offset and radius of the point robot
-  const float4* obs;             // obstacles (x, y, z, r), grouped by cluster
-  const float4* clus;            // cluster bounding spheres (centre, inflated radius)
-  const int2* clus_range;        // obstacle index range of each cluster
+  float4 clus[MAXC];             // cluster bounding spheres (centre, inflated radius)
+  int2 clus_range[MAXC];         // obstacle index range of each cluster
+};
+
+struct DevProblem {
+  Consts c;
+  CollConsts k;
+  const float4* obs;             // obstacles (x, y, z, r), grouped by cluster, n_obs of them
   unsigned long long* fallback_counter;
 };
 
-template <class T> __device__ __forceinline__ const TP<T>& tp(const DevProblem& P);
-template <> __device__ __forceinline__ const TP<double>& tp<double>(const DevProblem& P) { return P.d; }
-template <> __device__ __forceinline__ const TP<float>& tp<float>(const DevProblem& P) { return P.f; }
+template <class T> __device__ __forceinline__ const TP<T>& tp(const Consts& P);
+template <> __device__ __forceinline__ const TP<double>& tp<double>(const Consts& P) { return P.d; }
+template <> __device__ __forceinline__ const TP<float>& tp<float>(const Consts& P) { return P.f; }
+
+// Cooperative copy of `bytes` (multiple of 16) from global memory into LDS by the whole block.
+__device__ __forceinline__ void block_copy16(void* dst_lds, const void* src, int bytes) {
+  const uint4* s = static_cast<const uint4*>(src);
+  uint4* d = static_cast<uint4*>(dst_lds);
+  for (int i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
+}
 
 // ---------------------------------------------------------------- compile-time loops
 template <int N> using ic = std::integral_constant<int, N>;
@@ -75,6 +98,80 @@ __host__ __device__ __forceinline__ void sfor(F&& f) {
 // ---------------------------------------------------------------- small math
 template <class T> struct Rig { T R[9]; T p[3]; };
 
+// Opaque copy: stops the compiler from proving two recomputations equal (and merging
+// them, which would keep every intermediate live across the solve).
+__device__ __forceinline__ float opaque(float x) { asm volatile("" : "+v"(x)); return x; }
+__device__ __forceinline__ double opaque(double x) { asm volatile("" : "+v"(x)); return x; }
+
+// Ordering helper for the unrolled walks: an empty asm that claims to read `dep` and rewrite
+// `x`, so x (and everything computed from it) cannot be scheduled before dep exists. Costs no
+// instruction; bounds how far ahead loads and transcendental work are hoisted.
+template <class T, class U>
+__device__ __forceinline__ T after(T x, U dep) {
+  asm volatile("" : "+v"(x) : "v"(dep));
+  return x;
+}
+// Wave-uniform pointer, stated with readfirstlane so it can live in scalar registers.
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
+  return reinterpret_cast<T*>((uint64_t(hi) << 32) | lo);
+}
+// A reference into read-only global memory whose reads become scalar loads (constant address
+// space), issued only after dep exists.
+template <class T, class U>
+__device__ __forceinline__ const T& after_const(const T& r, U dep) {
+  using CT = const __attribute__((address_space(4))) T;
+  CT* c = (CT*)uniform_ptr(&r);
+  asm volatile("" : "+s"(c) : "v"(dep));
+  return *(const T*)c;
+}
+// The problem's constants as scalar-load memory.
+__device__ __forceinline__ const Consts& consts_of(const DevProblem* P) {
+  using CT = const __attribute__((address_space(4))) Consts;
+  CT* c = (CT*)uniform_ptr(&P->c);
+  asm volatile("" : "+s"(c));
+  return *(const Consts*)c;
+}
+// Same for a reference into LDS: its reads happen after dep.
+template <class T, class U>
+__device__ __forceinline__ const T& after_lds(const T& r, U dep) {
+  using LT = const __attribute__((address_space(3))) T;
+  LT* p = (LT*)&r;
+  asm volatile("" : "+v"(p) : "v"(dep));
+  return *(const T*)p;
+}
+
+// a * b + c with c wave-uniform (a scalar register pair), as one v_fma_f64. Written out because
+// the compiler otherwise prefers v_fmac_f64, whose addend must first be copied into a vector
+// register pair (two extra moves per Horner step).
+__device__ __forceinline__ double fma_su(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+}
+
+// Polynomial coefficients of the FP64 elementary functions below, read with scalar loads at the
+// point of use: as literals the compiler materialises them once outside the Newton loop and
+// keeps them live (and spilled) across it.
+struct alignas(16) MathTab {
+  double sin_c[7];   // (-1)^k / (2k+1)!, k = 7 .. 1 (Horner order)
+  double cos_c[8];   // (-1)^k / (2k)!, k = 8 .. 1
+  double atan_c[14]; // (-1)^k / (2k+1), k = 14 .. 1
+  double beta_c[5];  // series of 1/theta^2 - cot(theta/2)/(2 theta) in theta^2, highest first
+};
+static __constant__ MathTab kMathTab = {
+    {-1.0 / 1307674368000.0, 1.0 / 6227020800.0, -1.0 / 39916800.0, 1.0 / 362880.0, -1.0 / 5040.0, 1.0 / 120.0,
+     -1.0 / 6.0},
+    {1.0 / 20922789888000.0, -1.0 / 87178291200.0, 1.0 / 479001600.0, -1.0 / 3628800.0, 1.0 / 40320.0, -1.0 / 720.0,
+     1.0 / 24.0, -0.5},
+    {-1.0 / 29.0, 1.0 / 27.0, -1.0 / 25.0, 1.0 / 23.0, -1.0 / 21.0, 1.0 / 19.0, -1.0 / 17.0, 1.0 / 15.0, -1.0 / 13.0,
+     1.0 / 11.0, -1.0 / 9.0, 1.0 / 7.0, -1.0 / 5.0, 1.0 / 3.0},
+    {1.0 / 47900160.0, 1.0 / 1209600.0, 1.0 / 30240.0, 1.0 / 720.0, 1.0 / 12.0},
+};
+
 // FP64 sine and cosine for moderate arguments (|x| < 1e5, joint angles), a few ulp accurate:
 // Cody-Waite reduction x = k pi/2 + r with pi/2 split into three doubles (hi + mid + lo),
 // then the Taylor series of sin (to r^15) and cos (to r^16) on |r| <= pi/4, whose
@@ -85,22 +182,12 @@ __device__ __forceinline__ void sincos_t(double x, double* s, double* c) {
   r = __builtin_fma(-k, 6.123233995736766e-17, r);
   r = __builtin_fma(-k, -1.4973849048591698e-33, r);
   const double r2 = r * r;
-  double ps = -1.0 / 1307674368000.0;
-  ps = __builtin_fma(ps, r2, 1.0 / 6227020800.0);
-  ps = __builtin_fma(ps, r2, -1.0 / 39916800.0);
-  ps = __builtin_fma(ps, r2, 1.0 / 362880.0);
-  ps = __builtin_fma(ps, r2, -1.0 / 5040.0);
-  ps = __builtin_fma(ps, r2, 1.0 / 120.0);
-  ps = __builtin_fma(ps, r2, -1.0 / 6.0);
+  const MathTab& T = after_const(kMathTab, r2);
+  double ps = T.sin_c[0];
+  for (int i = 1; i < 7; ++i) ps = fma_su(ps, r2, T.sin_c[i]);
   const double sn = __builtin_fma(ps * r2, r, r);
-  double pc = 1.0 / 20922789888000.0;
-  pc = __builtin_fma(pc, r2, -1.0 / 87178291200.0);
-  pc = __builtin_fma(pc, r2, 1.0 / 479001600.0);
-  pc = __builtin_fma(pc, r2, -1.0 / 3628800.0);
-  pc = __builtin_fma(pc, r2, 1.0 / 40320.0);
-  pc = __builtin_fma(pc, r2, -1.0 / 720.0);
-  pc = __builtin_fma(pc, r2, 1.0 / 24.0);
-  pc = __builtin_fma(pc, r2, -0.5);
+  double pc = T.cos_c[0];
+  for (int i = 1; i < 8; ++i) pc = fma_su(pc, r2, T.cos_c[i]);
   const double cs = __builtin_fma(pc, r2, 1.0);
   const int qd = int(k) & 3;  // quadrant
   const double s0 = (qd & 1) ? cs : sn;
@@ -111,67 +198,32 @@ __device__ __forceinline__ void sincos_t(double x, double* s, double* c) {
 __device__ __forceinline__ void sincos_t(float x, float* s, float* c) { __sincosf(x, s, c); }
 __device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
 __device__ __forceinline__ float rsqrt_t(float x) { return __frsqrt_rn(x); }
-__device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
-__device__ __forceinline__ float sqrt_t(float x) { return __fsqrt_rn(x); }
 __device__ __forceinline__ bool finite_t(double x) { return __builtin_isfinite(x); }
 __device__ __forceinline__ bool finite_t(float x) { return __builtin_isfinite(x); }
 
-// Opaque copy: stops the compiler from proving two recomputations equal (and
-// merging them, which would keep every intermediate live across the solve).
-__device__ __forceinline__ float opaque(float x) { asm volatile("" : "+v"(x)); return x; }
-__device__ __forceinline__ double opaque(double x) { asm volatile("" : "+v"(x)); return x; }
-
-// Problem constants for one pass: the pointer is moved to the constant address space, so
-// the loads become scalar (s_load) reads, and passed through an opaque barrier, so they are
-// re-issued per pass instead of being hoisted out of the Newton loop into registers.
-// The pointer is wave-uniform by construction; readfirstlane states it (out-of-line
-// functions cannot prove it) so it can live in scalar registers.
-template <class T>
-__device__ __forceinline__ T* uniform_ptr(T* p) {
-  const uint64_t v = reinterpret_cast<uint64_t>(p);
-  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
-  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
-  return reinterpret_cast<T*>((uint64_t(hi) << 32) | lo);
-}
-using cDevProblem = const __attribute__((address_space(4))) DevProblem;
-__device__ __forceinline__ const DevProblem& cparams(const DevProblem* p) {
-  cDevProblem* c = (cDevProblem*)uniform_ptr(p);
-  asm volatile("" : "+s"(c));
-  return *(const DevProblem*)c;
-}
-
-// Ordering helpers for the unrolled kinematic chains: an empty asm that claims to read `dep`
-// and rewrite `x`, so x (and everything computed from it, e.g. a joint's sine and cosine or
-// the loads of its origin) cannot be scheduled before dep exists. Costs no instruction; keeps
-// the register footprint of a tree walk to the frames actually in flight.
-template <class T, class U>
-__device__ __forceinline__ T after(T x, U dep) {
-  asm volatile("" : "+v"(x) : "v"(dep));
-  return x;
-}
-template <class TPT, class U>
-__device__ __forceinline__ const TPT& after_params(const TPT& P, U dep) {
-  using cT = const __attribute__((address_space(4))) TPT;
-  cT* c = (cT*)uniform_ptr(&P);
-  asm volatile("" : "+s"(c) : "v"(dep));
-  return *(const TPT*)c;
-}
-template <class T, class U, class V>
-__device__ __forceinline__ T after2(T x, U d0, V d1) {
-  asm volatile("" : "+v"(x) : "v"(d0), "v"(d1));
-  return x;
-}
-
-// Accessors for the FP64 iterate. at(j) returns coordinate j; at(j, dep) issues the read only
-// after dep exists. Reads go through an opaque copy so separate passes never share them.
-struct QLds {  // per-lane column in LDS: q[j] at base[j * stride]
-  double* base;
-  int stride;
-  __device__ __forceinline__ double at(int j) const { return opaque(base[j * stride]); }
+// Accessors for the FP64 iterate. at(j) returns coordinate j; at(j, dep) reads it only after
+// dep exists. Reads go through an opaque copy so separate passes never share them.
+// Per-lane column of a wave's [D][64] FP64 tile in LDS: coordinate j at base[64 j], so every
+// access is one ds_read/ds_write with an immediate offset (no per-coordinate address registers)
+// and the 64 lanes of a wave hit 64 consecutive doubles.
+struct QLds {
+  using LP = __attribute__((address_space(3))) double*;
+  LP base;
+  __device__ __forceinline__ double at(int j) const { return opaque(base[j * 64]); }
   template <class U>
-  __device__ __forceinline__ double at(int j, U dep) const { return opaque(base[after(j * stride, dep)]); }
-  __device__ __forceinline__ void set(int j, double v) const { base[j * stride] = v; }
+  __device__ __forceinline__ double at(int j, U dep) const {
+    LP b = base;
+    asm volatile("" : "+v"(b) : "v"(dep));
+    return opaque(b[j * 64]);
+  }
+  __device__ __forceinline__ void set(int j, double v) const { base[j * 64] = v; }
 };
+// The calling lane's column; smem holds blockDim.x / 64 tiles of D x 64 doubles.
+template <int D>
+__device__ __forceinline__ QLds q_lds(double* smem) {
+  const int w = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
+  return QLds{(QLds::LP)(smem + w * (D * 64) + l)};
+}
 template <class T>
 struct QArr {  // registers
   const T* q;
@@ -194,68 +246,58 @@ __device__ __forceinline__ void matvec3(const T* M, const T* v, T* o) {
   o[1] = M[3] * v[0] + M[4] * v[1] + M[5] * v[2];
   o[2] = M[6] * v[0] + M[7] * v[1] + M[8] * v[2];
 }
-// o = M^T v
-template <class T>
-__device__ __forceinline__ void matTvec3(const T* M, const T* v, T* o) {
-  o[0] = M[0] * v[0] + M[3] * v[1] + M[6] * v[2];
-  o[1] = M[1] * v[0] + M[4] * v[1] + M[7] * v[2];
-  o[2] = M[2] * v[0] + M[5] * v[1] + M[8] * v[2];
-}
 // C = A B
 template <class T>
 __device__ __forceinline__ void matmul3(const T* A, const T* B, T* C) {
   for (int i = 0; i < 3; ++i)
     for (int k = 0; k < 3; ++k) C[3 * i + k] = A[3 * i] * B[k] + A[3 * i + 1] * B[3 + k] + A[3 * i + 2] * B[6 + k];
 }
-// C = A^T B
-template <class T>
-__device__ __forceinline__ void matTmul3(const T* A, const T* B, T* C) {
-  for (int i = 0; i < 3; ++i)
-    for (int k = 0; k < 3; ++k) C[3 * i + k] = A[i] * B[k] + A[3 + i] * B[3 + k] + A[6 + i] * B[6 + k];
+
+// atan2(y, x) on [0, pi] for y >= 0 (the rotation angle from sin and cos). Octant reduction to
+// u = min/max in [0, 1], then u > tan(pi/12) is mapped to (u sqrt3 - 1) / (u + sqrt3) =
+// tan(atan(u) - pi/6), so the Maclaurin series of atan runs on |u| <= tan(pi/12) = 0.268 and
+// is truncated after u^29 / 29 (remainder below 1e-19).
+__device__ __forceinline__ double angle_from_sincos(double y, double x) {
+  const double ax = fabs(x);
+  const double lo = fmin(y, ax), hi = fmax(y, ax);
+  double u = lo / hi;
+  const bool shift = u > 0.2679491924311228;
+  u = shift ? (u * 1.7320508075688772 - 1.0) / (u + 1.7320508075688772) : u;
+  const double u2 = u * u;
+  const MathTab& T = after_const(kMathTab, u2);
+  double p = T.atan_c[0];
+  for (int i = 1; i < 14; ++i) p = fma_su(p, u2, T.atan_c[i]);
+  double t = __builtin_fma(-p * u2, u, u);
+  t = shift ? t + 0.5235987755982989 : t;          // + pi/6
+  t = y > ax ? 1.5707963267948966 - t : t;        // pi/2 - t
+  t = x < 0.0 ? 3.141592653589793 - t : t;        // pi - t
+  return hi > 0.0 ? t : 0.0;
 }
 
 // SO(3) log (vee form) of R plus the left-Jacobian inverse J_l^-1(w), used for the angular
-// rows of the pose errors: v = vee(R - R^T)/2 = sin(theta) * axis, c = cos(theta),
-// w = (theta / sin theta) v, with the first-order Taylor form 1 + s^2/6 of theta/sin(theta)
-// near theta = 0 (Sec. IV-A). For a left perturbation R' = exp([e]x) R,
-// d log(R') / d e = J_l^-1(w) = I - [w]x / 2 + beta [w]x^2, beta = 1/theta^2 - (1 + c)/(2 theta s).
+// rows of the pose errors (Eq. 1, Eq. 2): v = vee(R - R^T)/2 = sin(theta) * axis,
+// c = cos(theta), w = (theta / sin theta) v, with the first-order Taylor form 1 + s^2/6 of
+// theta / sin(theta) when sin^2(theta) < 1e-8 and theta < pi/2 (Sec. IV-A). For a left
+// perturbation R' = exp([e]x) R, d log(R') / d e = J_l^-1(w) = I - [w]x / 2 + beta [w]x^2 with
+// beta = 1/theta^2 - (1 + c) / (2 theta s), taken from its series when theta^2 < 0.1. Both
+// forms of each factor are computed and selected, so lanes do not diverge.
 __device__ __forceinline__ void so3_log_jlinv(const double* R, double* w, double* Jinv) {
   const double v0 = 0.5 * (R[7] - R[5]), v1 = 0.5 * (R[2] - R[6]), v2 = 0.5 * (R[3] - R[1]);
   const double s2 = v0 * v0 + v1 * v1 + v2 * v2;
   const double c = 0.5 * (R[0] + R[4] + R[8] - 1.0);
-  double f;
-  if (c > 0.0 && s2 < 1e-8) {
-    f = 1.0 + s2 * (1.0 / 6.0);
-  } else if (c > 0.0 && s2 < 1e-2) {
-    // theta < pi/2: theta / sin(theta) = asin(s) / s = sum_n C(2n, n) s^2n / (4^n (2n + 1))
-    f = 6435.0 / 557056.0;
-    f = __builtin_fma(f, s2, 143.0 / 10240.0);
-    f = __builtin_fma(f, s2, 231.0 / 13312.0);
-    f = __builtin_fma(f, s2, 63.0 / 2816.0);
-    f = __builtin_fma(f, s2, 35.0 / 1152.0);
-    f = __builtin_fma(f, s2, 5.0 / 112.0);
-    f = __builtin_fma(f, s2, 3.0 / 40.0);
-    f = __builtin_fma(f, s2, 1.0 / 6.0);
-    f = __builtin_fma(f, s2, 1.0);
-  } else {
-    const double sn = sqrt(s2);
-    f = atan2(sn, c) / sn;
-  }
+  const double sn = sqrt(s2);
+  const double th = angle_from_sincos(sn, c);
+  const bool small = c > 0.0 && s2 < 1e-8;
+  const double f = small ? __builtin_fma(s2, 1.0 / 6.0, 1.0) : th / sn;
   w[0] = f * v0; w[1] = f * v1; w[2] = f * v2;
   if (Jinv) {
     const double th2 = f * f * s2;
-    double beta;
-    if (th2 < 0.1) {
-      // 1/theta^2 - cot(theta/2) / (2 theta) = 1/12 + th^2/720 + th^4/30240 + th^6/1209600 + th^8/47900160 + ...
-      beta = 1.0 / 47900160.0;
-      beta = __builtin_fma(beta, th2, 1.0 / 1209600.0);
-      beta = __builtin_fma(beta, th2, 1.0 / 30240.0);
-      beta = __builtin_fma(beta, th2, 1.0 / 720.0);
-      beta = __builtin_fma(beta, th2, 1.0 / 12.0);
-    } else {
-      const double th = sqrt(th2), sn = sqrt(s2);
-      beta = 1.0 / th2 - (1.0 + c) / (2.0 * th * sn);
-    }
+    // 1/theta^2 - cot(theta/2) / (2 theta) = 1/12 + th^2/720 + th^4/30240 + th^6/1209600 + th^8/47900160 + ...
+    const MathTab& T = after_const(kMathTab, th2);
+    double bs = T.beta_c[0];
+    for (int i = 1; i < 5; ++i) bs = fma_su(bs, th2, T.beta_c[i]);
+    const double bc = 1.0 / th2 - (1.0 + c) / (2.0 * th * sn);
+    const double beta = th2 < 0.1 ? bs : bc;
     const double a0 = 1.0 - beta * th2;
     // J = a0 I - 0.5 [w]x + beta w w^T
     Jinv[0] = a0 + beta * w[0] * w[0];

@@ -1,7 +1,9 @@
 // Generic HIP kernels of the projection path, templated on the constraint model.
 //
 // Mapping: one configuration per lane; the lane's FP64 iterate lives in LDS (a column
-// of a [D][blockDim] array, conflict-free), everything else in registers. The hot
+// of a [D][blockDim] array, conflict-free); the kinematic constants are read with scalar
+// loads (wave-uniform, so they occupy scalar registers), the collision data is staged in
+// LDS once per workgroup; everything else is in registers. The hot
 // loop (Alg. 2 ParallelProject with getDescentStep on one stacked block) per iteration:
 //   1. residual pass, FP64: forward kinematics, F(q), ||F||^2, and the per-block data
 //      the Jacobian columns need;
@@ -41,7 +43,23 @@ struct ProjArgs {
   int32_t check;
   unsigned int* counter;  // persistent: queue head (reset to 0 before the launch)
   int64_t n_static;       // persistent: configurations [0, n_static) are taken by thread id
+  int32_t n_obs;          // obstacles (dynamic LDS of the plain kernel, which checks in-kernel)
+  // FP32 mode: configurations whose FP32 step fails (factorisation or condition estimate) are
+  // handed to the FP64 tail kernel through this queue: defer_ik[2s], defer_ik[2s+1] = index and
+  // steps taken, defer_q[c * defer_cap + s] = FP64 iterate.
+  unsigned int* defer_count;
+  int32_t* defer_ik;
+  double* defer_q;
+  int64_t defer_cap;
 };
+
+constexpr int ST_DEFER = -2;  // internal: continue this configuration with FP64 steps
+
+// Stage the collision data in LDS (kernels that run the check start with this).
+__device__ __forceinline__ void stage_coll(CollConsts& dst, float4* obs_lds, const DevProblem* P, int n_obs) {
+  block_copy16(&dst, &P->k, int(sizeof(CollConsts)));
+  block_copy16(obs_lds, P->obs, n_obs * 16);
+}
 
 template <class IO>
 __device__ __forceinline__ double ld_io(const void* p, int64_t k) { return double(static_cast<const IO*>(p)[k]); }
@@ -128,10 +146,10 @@ constexpr double kFloorF64 = 1e-24;  // pivot floor relative to the largest Gram
 // exceeds cond_thr.
 template <class Model, class S, class Q>
 __device__ __forceinline__ bool descent_step(const Q& q, S* rhs, const typename Model::template SD<S>& sd,
-                                             const DevProblem* Pp, double lambda, double cond_thr, S floor_rel, S* dq) {
+                                             const Consts& C, double lambda, double cond_thr, S floor_rel, S* dq) {
   constexpr int M = Model::M;
   S G[M * (M + 1) / 2];
-  Model::template gram<S, false>(q, cparams(Pp), sd, G, nullptr, nullptr);
+  Model::template gram<S, false>(q, C, sd, G, nullptr, nullptr);
   S maxd = S(0);
   sfor<0, M>([&](auto I) {
     constexpr int i = decltype(I)::value;
@@ -142,7 +160,7 @@ __device__ __forceinline__ bool descent_step(const Q& q, S* rhs, const typename 
   if (!cholesky<Model, S>(G, invd, kappa, floor_rel * maxd)) return false;
   if (!(double(kappa) <= cond_thr)) return false;
   chol_solve<Model, S>(G, invd, rhs);
-  Model::template jty<S>(q, cparams(Pp), sd, rhs, dq);
+  Model::template jty<S>(q, C, sd, rhs, dq);
   return true;
 }
 
@@ -161,64 +179,65 @@ __device__ __forceinline__ int apply_step(const QLds& q, const S* dq, const Proj
   return -1;
 }
 
-// The whole step in FP64 for one lane (condition estimate above threshold or a failed FP32
-// factorisation). Kept out of line so its register needs do not shape the FP32 path.
-template <class Model>
-__device__ __noinline__ int fp64_step(QLds q, const ProjArgs* ap) {
-  const ProjArgs& a = *ap;
-  typename Model::template SD<double> sd;
-  double F[Model::M], dq[Model::D];
-  Model::template residual<double>(q, cparams(a.P), F, sd);
-  if (!descent_step<Model, double>(q, F, sd, a.P, a.lambda, 1e300, kFloorF64, dq)) return ST_SINGULAR;
-  return apply_step<Model, double>(q, dq, a);
-}
-
-// One Newton iteration for one lane. Returns -1 after taking a step, else the final status.
+// One Newton iteration for one lane: residual and convergence test in FP64, then the step in
+// precision S. Returns -1 after taking a step, else the final status; in FP32 mode ST_DEFER
+// when the FP32 factorisation fails or its condition estimate exceeds the threshold (the
+// iteration is then redone with an FP64 step, and the configuration stays in FP64 until it
+// ends).
 template <class Model, class S>
-__device__ __forceinline__ int newton_iteration(const QLds& q, int& k, const ProjArgs& a, double& resid) {
+__device__ __forceinline__ int newton_iteration(const QLds& q, int& k, const ProjArgs& a, const Consts& C, double& resid) {
   constexpr int D = Model::D, M = Model::M;
   typename Model::template SD<S> sd;
   S F[M];
-  const double n2 = Model::template residual<S>(q, cparams(a.P), F, sd);
+  const double n2 = Model::template residual<S>(q, C, F, sd);
   resid = sqrt(n2);
   if (!finite_t(n2)) return ST_NONFINITE;
   if (n2 < a.tol2) return ST_CONVERGED;
   if (k >= a.max_iter) return ST_MAX_ITER;
+  S dq[D];
   int st;
   if constexpr (std::is_same<S, float>::value) {
-    float dq[D];
-    if (descent_step<Model, float>(q, F, sd, a.P, a.lambda, a.cond_thr, kFloorF32, dq)) {
-      st = apply_step<Model, float>(q, dq, a);
-    } else {
-      atomicAdd(a.P->fallback_counter, 1ull);
-#ifdef MC_EXPERIMENT_NO_FALLBACK
-      st = ST_SINGULAR;
-#else
-      st = fp64_step<Model>(q, &a);
-#endif
-    }
+    if (!descent_step<Model, float>(q, F, sd, C, a.lambda, a.cond_thr, kFloorF32, dq)) return ST_DEFER;
+    st = apply_step<Model, float>(q, dq, a);
   } else {
-    double dq[D];
-    if (descent_step<Model, double>(q, F, sd, a.P, a.lambda, 1e300, kFloorF64, dq))
-      st = apply_step<Model, double>(q, dq, a);
-    else
-      st = ST_SINGULAR;
+    if (!descent_step<Model, double>(q, F, sd, C, a.lambda, 1e300, kFloorF64, dq)) return ST_SINGULAR;
+    st = apply_step<Model, double>(q, dq, a);
   }
   if (st < 0) ++k;
   return st;
 }
 
+// Run one configuration to the end with FP64 steps.
+template <class Model>
+__device__ __forceinline__ int finish_fp64(const QLds& q, int& k, const ProjArgs& a, const Consts& C, double& resid) {
+  int st;
+  do {
+    st = newton_iteration<Model, double>(q, k, a, C, resid);
+  } while (st < 0);
+  return st;
+}
+
+// Column c of configuration i in a [D][ld] array sits at (c ld + i); the pointer is bumped by
+// an opaque ld so the D addresses are formed one after another rather than all up front.
 template <class Model, class IO>
-__device__ __forceinline__ void load_q(const ProjArgs& a, int64_t i, const QLds& q) {
-  const int dof = a.P->dof;
-  for (int c = 0; c < Model::D; ++c) q.set(c, c < dof ? ld_io<IO>(a.q_in, c * a.ld_in + a.base + i) : 0.0);
+__device__ __forceinline__ void load_q(const ProjArgs& a, int dof, int64_t i, const QLds& q) {
+  const IO* p = static_cast<const IO*>(a.q_in) + a.base + i;
+  const int64_t ld = a.ld_in;
+  for (int c = 0; c < Model::D; ++c) {
+    q.set(c, c < dof ? double(*p) : 0.0);
+    p += after(ld, c);
+  }
 }
 
 template <class Model, class IO>
-__device__ __forceinline__ void store_result(const ProjArgs& a, int64_t i, const QLds& q, int st, int k, double resid) {
-  const int dof = a.P->dof;
-  for (int c = 0; c < Model::D; ++c)
-    if (c < dof) st_io<IO>(a.q_out, c * a.ld_out + a.base + i, q.at(c));
+__device__ __forceinline__ void store_result(const ProjArgs& a, int dof, int64_t i, const QLds& q, int st, int k,
+                                             double resid) {
+  IO* p = static_cast<IO*>(a.q_out) + a.base + i;
+  const int64_t ld = a.ld_out;
+  for (int c = 0; c < Model::D; ++c) {
+    if (c < dof) *p = IO(q.at(c));
+    p += after(ld, c);
+  }
   a.status[a.base + i] = int8_t(st);
   a.iters[a.base + i] = int8_t(k);
   st_io<IO>(a.resid, a.base + i, resid);
@@ -230,24 +249,59 @@ __device__ __forceinline__ void store_result(const ProjArgs& a, int64_t i, const
 template <class Model, class IO, class S>
 __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
   extern __shared__ double smem[];
-  const QLds q{smem + threadIdx.x, int(blockDim.x)};
+  const Consts& C = consts_of(a.P);
+  const int dof = C.dof;
+  const QLds q = q_lds<Model::D>(smem);
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n_static) i = a.n;  // not part of the static share
   int k = 0;
-  if (i < a.n) load_q<Model, IO>(a, i, q);
+  if (i < a.n) load_q<Model, IO>(a, dof, i, q);
   for (;;) {
     const bool active = i < a.n;
     if (!__any(active)) break;
     if (active) {
       double resid;
-      const int st = newton_iteration<Model, S>(q, k, a, resid);
-      if (st >= 0) {
-        store_result<Model, IO>(a, i, q, st, k, resid);
+      int st = newton_iteration<Model, S>(q, k, a, C, resid);
+      if (st == ST_DEFER) {
+        const unsigned slot = atomicAdd(a.defer_count, 1u);  // < defer_cap (sized for the batch)
+        atomicAdd(a.P->fallback_counter, 1ull);
+        a.defer_ik[2 * slot] = int32_t(i);
+        a.defer_ik[2 * slot + 1] = k;
+        double* dst = a.defer_q + slot;
+        for (int c = 0; c < Model::D; ++c) {
+          *dst = q.at(c);
+          dst += after(a.defer_cap, c);
+        }
+      } else if (st >= 0) {
+        store_result<Model, IO>(a, dof, i, q, st, k, resid);
+      }
+      if (st >= 0 || st == ST_DEFER) {
         i = a.n_static + int64_t(atomicAdd(a.counter, 1u));
         k = 0;
-        if (i < a.n) load_q<Model, IO>(a, i, q);
+        if (i < a.n) load_q<Model, IO>(a, dof, i, q);
       }
     }
+  }
+}
+
+// FP64 tail of the persistent variant: the configurations deferred by the FP32 kernel, one per
+// lane (grid-stride over the queue), continued from their stored FP64 iterate with FP64 steps.
+// Dynamic LDS: D * blockDim doubles.
+template <class Model, class IO>
+__global__ void __launch_bounds__(64) k_project_tail(ProjArgs a) {
+  extern __shared__ double smem[];
+  const Consts& C = consts_of(a.P);
+  const int dof = C.dof;
+  const QLds q = q_lds<Model::D>(smem);
+  const int64_t cnt = *a.defer_count;
+  for (int64_t slot = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; slot < cnt;
+       slot += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = a.defer_ik[2 * slot];
+    int k = a.defer_ik[2 * slot + 1];
+    for (int c = 0; c < Model::D; ++c) q.set(c, a.defer_q[c * a.defer_cap + slot]);
+    double resid;
+    const int st = finish_fp64<Model>(q, k, a, C, resid);
+    store_result<Model, IO>(a, dof, i, q, st, k, resid);
   }
 }
 
@@ -256,23 +310,34 @@ __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
 template <class Model, class IO, class S>
 __global__ void __launch_bounds__(64) k_project_plain(ProjArgs a) {
   extern __shared__ double smem[];
-  const QLds q{smem + threadIdx.x, int(blockDim.x)};
+  __shared__ CollConsts K;
+  float4* obs = reinterpret_cast<float4*>(smem + Model::D * blockDim.x);
+  const Consts& C = consts_of(a.P);
+  if (a.verdict && a.check) stage_coll(K, obs, a.P, a.n_obs);
+  __syncthreads();
+  const int dof = C.dof;
+  const QLds q = q_lds<Model::D>(smem);
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  load_q<Model, IO>(a, i, q);
+  load_q<Model, IO>(a, dof, i, q);
   int k = 0, st;
   double resid;
   for (;;) {
-    st = newton_iteration<Model, S>(q, k, a, resid);
+    st = newton_iteration<Model, S>(q, k, a, C, resid);
     if (st >= 0) break;
+    if (st == ST_DEFER) {  // same rule as the persistent variant: FP64 steps from here on
+      atomicAdd(a.P->fallback_counter, 1ull);
+      st = finish_fp64<Model>(q, k, a, C, resid);
+      break;
+    }
   }
-  store_result<Model, IO>(a, i, q, st, k, resid);
+  store_result<Model, IO>(a, dof, i, q, st, k, resid);
   if (a.verdict) {
     uint8_t v = V_UNCHECKED;
     if (a.check && st == ST_CONVERGED) {
       bool hit;
       float msd;
-      Model::template check<false>(q, cparams(a.P), hit, msd);
+      Model::template check<false>(q, C, K, obs, hit, msd);
       v = hit ? V_HIT : V_FREE;
     }
     a.verdict[a.base + i] = v;
@@ -287,20 +352,27 @@ struct CheckArgs {
   const int8_t* status;  // nullable: check only CONVERGED configurations
   uint8_t* verdict;
   void* minsd;           // nullable
+  int32_t n_obs;
 };
 
+// Dynamic LDS: n_obs float4.
 template <class Model, class IO, bool MINSD>
 __global__ void __launch_bounds__(256) k_check(CheckArgs a) {
+  extern __shared__ float4 obs[];
+  __shared__ CollConsts K;
+  const Consts& C = consts_of(a.P);
+  stage_coll(K, obs, a.P, a.n_obs);
+  __syncthreads();
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   if (a.status && a.status[i] != ST_CONVERGED) {
     a.verdict[i] = V_UNCHECKED;
     return;
   }
-  const QGlob<IO> q{static_cast<const IO*>(a.q), a.ld, i, a.P->dof};
+  const QGlob<IO> q{static_cast<const IO*>(a.q), a.ld, i, C.dof};
   bool hit;
   float msd;
-  Model::template check<MINSD>(q, cparams(a.P), hit, msd);
+  Model::template check<MINSD>(q, C, K, obs, hit, msd);
   a.verdict[i] = hit ? V_HIT : V_FREE;
   if constexpr (MINSD) st_io<IO>(a.minsd, i, double(msd));
 }
@@ -314,69 +386,110 @@ struct VjpArgs {
   const void* g;
   void* g_in;
   double cond_thr;
+  unsigned int* defer_count;  // FP32 mode: configurations left to the FP64 tail kernel
+  int32_t* defer_idx;
 };
 
-// FP64 Gram, factorisation and projection for one lane (condition estimate above threshold).
+// FP64 Gram, factorisation and projection for one lane: out = g - J^T (J J^T)^-1 J g.
 template <class Model>
-__device__ __noinline__ void vjp64(QLds q, const VjpArgs* ap, const double* gd, double* out) {
+__device__ __forceinline__ void vjp64(const QLds& q, const Consts& C, const double* gd, double* out) {
   constexpr int D = Model::D, M = Model::M;
-  const VjpArgs& a = *ap;
   typename Model::template SD<double> sd;
   double F[M], G[M * (M + 1) / 2], v[M], invd[M], kappa, jy[D];
-  Model::template residual<double>(q, cparams(a.P), F, sd);
-  Model::template gram<double, true>(q, cparams(a.P), sd, G, gd, v);
+  Model::template residual<double>(q, C, F, sd);
+  Model::template gram<double, true>(q, C, sd, G, gd, v);
   double maxd = 0.0;
   for (int r = 0; r < M; ++r) maxd = fmax(maxd, G[pidx(r, r)]);
   if (cholesky<Model, double>(G, invd, kappa, kFloorF64 * maxd)) {
     chol_solve<Model, double>(G, invd, v);
-    Model::template jty<double>(q, cparams(a.P), sd, v, jy);
+    Model::template jty<double>(q, C, sd, v, jy);
     for (int j = 0; j < D; ++j) out[j] = gd[j] - jy[j];
   } else {
     for (int j = 0; j < D; ++j) out[j] = __builtin_nan("");
   }
 }
 
+template <class Model, class IO>
+__device__ __forceinline__ void vjp_load(const VjpArgs& a, int dof, int64_t i, const QLds& q, double* gd) {
+  const IO* pq = static_cast<const IO*>(a.q) + i;
+  const IO* pg = static_cast<const IO*>(a.g) + i;
+  for (int c = 0; c < Model::D; ++c) {
+    q.set(c, c < dof ? double(*pq) : 0.0);
+    gd[c] = c < dof ? double(*pg) : 0.0;
+    const int64_t ld = after(a.ld, c);
+    pq += ld;
+    pg += ld;
+  }
+}
+
+template <class Model, class IO>
+__device__ __forceinline__ void vjp_store(const VjpArgs& a, int dof, int64_t i, const double* out) {
+  IO* p = static_cast<IO*>(a.g_in) + i;
+  for (int c = 0; c < Model::D; ++c) {
+    if (c < dof) *p = IO(out[c]);
+    p += after(a.ld, c);
+  }
+}
+
 // g_in = g - J^T (J J^T)^-1 J g at the converged configuration (J recomputed; the forward
-// pass stores nothing beyond q and status).
+// pass stores nothing beyond q and status). g_in = 0 for configurations that did not converge.
+// In FP32 mode a lane whose factorisation fails or whose condition estimate exceeds the
+// threshold is queued for k_vjp_tail, which redoes it in FP64.
 template <class Model, class IO, class S>
 __global__ void __launch_bounds__(256) k_vjp(VjpArgs a) {
   constexpr int D = Model::D, M = Model::M;
   extern __shared__ double smem[];
-  const QLds q{smem + threadIdx.x, int(blockDim.x)};
+  const Consts& C = consts_of(a.P);
+  const QLds q = q_lds<Model::D>(smem);
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  const int dof = a.P->dof;
+  const int dof = C.dof;
+  double out[D];
   if (a.status[i] != ST_CONVERGED) {
-    for (int c = 0; c < D; ++c)
-      if (c < dof) st_io<IO>(a.g_in, c * a.ld + i, 0.0);
+    for (int c = 0; c < D; ++c) out[c] = 0.0;
+    vjp_store<Model, IO>(a, dof, i, out);
     return;
   }
   double gd[D];
-  for (int c = 0; c < D; ++c) {
-    q.set(c, c < dof ? ld_io<IO>(a.q, c * a.ld + i) : 0.0);
-    gd[c] = c < dof ? ld_io<IO>(a.g, c * a.ld + i) : 0.0;
-  }
-  double out[D];
-  bool done = false;
+  vjp_load<Model, IO>(a, dof, i, q, gd);
   if constexpr (std::is_same<S, float>::value) {
     typename Model::template SD<float> sd;
     float F[M], gs[D], G[M * (M + 1) / 2], v[M], invd[M], kappa;
-    Model::template residual<float>(q, cparams(a.P), F, sd);
+    Model::template residual<float>(q, C, F, sd);
     for (int j = 0; j < D; ++j) gs[j] = float(gd[j]);
-    Model::template gram<float, true>(q, cparams(a.P), sd, G, gs, v);
+    Model::template gram<float, true>(q, C, sd, G, gs, v);
     if (cholesky<Model, float>(G, invd, kappa, kFloorF32) && double(kappa) <= a.cond_thr) {
       chol_solve<Model, float>(G, invd, v);
       float jy[D];
-      Model::template jty<float>(q, cparams(a.P), sd, v, jy);
+      Model::template jty<float>(q, C, sd, v, jy);
       for (int j = 0; j < D; ++j) out[j] = gd[j] - double(jy[j]);
-      done = true;
+      vjp_store<Model, IO>(a, dof, i, out);
     } else {
       atomicAdd(a.P->fallback_counter, 1ull);
+      a.defer_idx[atomicAdd(a.defer_count, 1u)] = int32_t(i);
     }
+  } else {
+    vjp64<Model>(q, C, gd, out);
+    vjp_store<Model, IO>(a, dof, i, out);
   }
-  if (!done) vjp64<Model>(q, &a, gd, out);
-  for (int c = 0; c < D; ++c)
-    if (c < dof) st_io<IO>(a.g_in, c * a.ld + i, out[c]);
+}
+
+// FP64 redo of the VJPs queued by k_vjp (grid-stride over the queue).
+template <class Model, class IO>
+__global__ void __launch_bounds__(64) k_vjp_tail(VjpArgs a) {
+  constexpr int D = Model::D;
+  extern __shared__ double smem[];
+  const Consts& C = consts_of(a.P);
+  const int dof = C.dof;
+  const QLds q = q_lds<Model::D>(smem);
+  const int64_t cnt = *a.defer_count;
+  for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < cnt; s += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = a.defer_idx[s];
+    double gd[D], out[D];
+    vjp_load<Model, IO>(a, dof, i, q, gd);
+    vjp64<Model>(q, C, gd, out);
+    vjp_store<Model, IO>(a, dof, i, out);
+  }
 }
 
 // Diagnostic: residual (FP64) and dense Jacobian (step precision S) as the projection
@@ -384,7 +497,7 @@ __global__ void __launch_bounds__(256) k_vjp(VjpArgs a) {
 template <class Model, class IO, class S>
 __global__ void __launch_bounds__(256) k_eval_fj(const DevProblem* Pp, int64_t n, const void* qv, int64_t ld, void* Fo, void* Jo) {
   constexpr int D = Model::D, M = Model::M;
-  const DevProblem& P = cparams(Pp);
+  const Consts& P = consts_of(Pp);
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int dof = P.dof, m = P.rows;

@@ -222,6 +222,13 @@ struct KInfo {
 
 
 // ------------------------------------------------------------------ model
+// Kinematic constants are read with scalar loads (uniform values cost scalar registers, not
+// vector registers), each joint's ordered after the walk reaches it.
+template <class T, class U>
+__device__ __forceinline__ const T& after_cp(const T& r, U dep) {
+  return after_const(r, dep);
+}
+
 template <class Topo>
 struct Kin {
   using KI = KInfo<Topo>;
@@ -251,46 +258,71 @@ struct Kin {
     return T(x);
   }
 
-  // Forward kinematics, streaming each link frame to visit(ic<j>, frame) in joint order.
+  // What the walk needs at joint j, read from LDS one joint ahead of its use.
+  template <class T>
+  struct JP {
+    T q;       // joint coordinate
+    T p[3];    // origin translation
+    T R[9];    // origin rotation (when the topology has rotated origins)
+    T m;       // link mass
+    T mc[3];   // mass * local CoM
+  };
+
+  template <class T, int j, class Q, class U>
+  static __device__ __forceinline__ JP<T> load_joint(const Q& q, const TP<T>& P0, U dep) {
+    JP<T> r;
+    r.q = joint_value<T, Topo::jtype[j]>(q.at(j, dep));
+    const TP<T>& P = after_cp(P0, dep);
+    for (int k = 0; k < 3; ++k) r.p[k] = P.jp[j][k];
+    if constexpr (Topo::origin_rot)
+      for (int k = 0; k < 9; ++k) r.R[k] = P.jR[j][k];
+    if constexpr (Topo::has_com && !Topo::massless(j)) {
+      r.m = P.mass[j];
+      for (int k = 0; k < 3; ++k) r.mc[k] = P.mcom[j][k];
+    }
+    return r;
+  }
+
+  // Forward kinematics, streaming each link frame to visit(ic<j>, frame, joint data) in joint
+  // order. Joint j+1's data is read while joint j is computed; joint j+1's read is ordered
+  // after joint j-1's frame, so the walk keeps one joint of data in flight.
   template <class T, class Q, class V>
   static __device__ __forceinline__ void fk(const Q& q, const TP<T>& P, V&& visit) {
     Rig<T> L[NJ];
+    JP<T> cur = load_joint<T, 0>(q, P, 0);
     sfor<0, NJ>([&](auto J) {
       constexpr int j = decltype(J)::value;
       constexpr int par = Topo::parent[j];
       constexpr int ax = Topo::axis[j];
+      JP<T> nxt;  // the next joint's data, requested one joint ahead
+      if constexpr (j + 1 < NJ) {
+        if constexpr (j > 0) nxt = load_joint<T, j + 1>(q, P, L[j - 1].p[2]);
+        else nxt = load_joint<T, j + 1>(q, P, cur.q);
+      }
       Rig<T>& X = L[j];
-      T qj;
       if constexpr (par < 0) {
-        qj = joint_value<T, Topo::jtype[j]>(q.at(j));
-        const TP<T>& Pj = P;
         if constexpr (Topo::origin_rot) {
-          for (int k = 0; k < 9; ++k) X.R[k] = Pj.jR[j][k];
+          for (int k = 0; k < 9; ++k) X.R[k] = cur.R[k];
         } else {
           for (int k = 0; k < 9; ++k) X.R[k] = (k % 4 == 0) ? T(1) : T(0);
         }
-        for (int k = 0; k < 3; ++k) X.p[k] = Pj.jp[j][k];
+        for (int k = 0; k < 3; ++k) X.p[k] = cur.p[k];
       } else {
         const Rig<T>& B = L[par];
-        // joint j's angle and origin are consumed only once its parent frame and the previous
-        // frame in depth-first order exist: the walk stays one chain at a time
-        const T dep = after2(B.p[2], B.p[2], L[j - 1].p[2]);
-        qj = joint_value<T, Topo::jtype[j]>(q.at(j, dep));
-        const TP<T>& Pj = after_params(P, dep);
         if constexpr (Topo::origin_rot) {
-          matmul3(B.R, Pj.jR[j], X.R);
+          matmul3(B.R, cur.R, X.R);
         } else {
           for (int k = 0; k < 9; ++k) X.R[k] = B.R[k];
         }
         T t[3];
-        matvec3(B.R, Pj.jp[j], t);
+        matvec3(B.R, cur.p, t);
         for (int k = 0; k < 3; ++k) X.p[k] = B.p[k] + t[k];
       }
       if constexpr (Topo::jtype[j] == PRI) {
-        for (int r = 0; r < 3; ++r) X.p[r] += X.R[3 * r + ax] * qj;
+        for (int r = 0; r < 3; ++r) X.p[r] += X.R[3 * r + ax] * cur.q;
       } else {
         T s, c;
-        sincos_t(qj, &s, &c);
+        sincos_t(cur.q, &s, &c);
         constexpr int i = (ax + 1) % 3, k = (ax + 2) % 3;
         for (int r = 0; r < 3; ++r) {
           const T a = X.R[3 * r + i], b = X.R[3 * r + k];
@@ -298,12 +330,14 @@ struct Kin {
           X.R[3 * r + k] = b * c - a * s;
         }
       }
-      visit(J, X);
+      visit(J, X, cur);
+      if constexpr (j + 1 < NJ) cur = nxt;
     });
   }
 
   template <class T>
-  static __device__ __forceinline__ void frame_pose(const Rig<T>& X, const TP<T>& P, int f, Rig<T>& out) {
+  static __device__ __forceinline__ void frame_pose(const Rig<T>& X, const TP<T>& P0, int f, Rig<T>& out) {
+    const TP<T>& P = after_cp(P0, X.p[2]);
     if constexpr (Topo::frame_rot) {
       matmul3(X.R, P.fR[f], out.R);
     } else {
@@ -327,9 +361,12 @@ struct Kin {
   }
 
   template <class S, int b>
-  static __device__ __forceinline__ void block_rows(const Rig<double>* Fr, const DevProblem& P, S* F, double& n2, SD<S>& sd) {
+  static __device__ __forceinline__ void block_rows(const Rig<double>* Fr, const Consts& P0, S* F, double& n2, SD<S>& sd) {
     constexpr int t = Topo::btype[b];
     constexpr int r0 = KI::brow0(b);
+    // the block's constants are read only once its frames exist
+    constexpr int flast = (t == B_REL) ? Topo::bfb[b] : Topo::bfa[b];
+    const Consts& P = after_cp(P0, Fr[flast < 0 ? 0 : flast].p[2]);
     if constexpr (t == B_POSE) {
       constexpr int fa = Topo::bfa[b];
       const double* Rt = P.d.refRt[b];
@@ -375,11 +412,11 @@ struct Kin {
   // Residual pass in FP64: returns ||F(q)||^2 (FP64); F in the step precision S and the
   // step data for the Jacobian passes.
   template <class S, class Q>
-  static __device__ __forceinline__ double residual(const Q& q, const DevProblem& P, S* F, SD<S>& sd) {
+  static __device__ __forceinline__ double residual(const Q& q, const Consts& P, S* F, SD<S>& sd) {
     Rig<double> Fr[NF];
     double cm[3] = {0.0, 0.0, 0.0};
     double n2 = 0.0;
-    fk<double>(q, P.d, [&](auto J, const Rig<double>& X) {
+    fk<double>(q, P.d, [&](auto J, const Rig<double>& X, const JP<double>& jp) {
       constexpr int j = decltype(J)::value;
       sfor<0, NF>([&](auto FI) {
         constexpr int f = decltype(FI)::value;
@@ -388,9 +425,8 @@ struct Kin {
       if constexpr (Topo::has_com) {
         if constexpr (!Topo::massless(j)) {
           double t[3];
-          matvec3(X.R, P.d.mcom[j], t);
-          const double mj = P.d.mass[j];
-          for (int k = 0; k < 3; ++k) cm[k] += t[k] + mj * X.p[k];
+          matvec3(X.R, jp.mc, t);
+          for (int k = 0; k < 3; ++k) cm[k] += t[k] + jp.m * X.p[k];
         }
         if constexpr (KI::end_needed(j + 1)) {
           for (int k = 0; k < 3; ++k) sd.Qe[j + 1][k] = S(cm[k]);
@@ -405,8 +441,9 @@ struct Kin {
       constexpr int b = decltype(BI)::value;
       if constexpr (Topo::btype[b] == B_COM) {
         constexpr int r0 = KI::brow0(b);
-        const double e0 = cm[0] * P.d.inv_total_mass - P.d.target[b][0];
-        const double e1 = cm[1] * P.d.inv_total_mass - P.d.target[b][1];
+        const TP<double>& Pd = after_cp(P.d, cm[1]);
+        const double e0 = cm[0] * Pd.inv_total_mass - Pd.target[b][0];
+        const double e1 = cm[1] * Pd.inv_total_mass - Pd.target[b][1];
         F[r0] = S(e0);
         F[r0 + 1] = S(e1);
         n2 += e0 * e0 + e1 * e1;
@@ -418,7 +455,8 @@ struct Kin {
   // Structurally nonzero entries of Jacobian column j (other rows untouched). Qr is the running
   // prefix sum of m_l c_l over the links before j and is advanced past link j.
   template <class S, int j>
-  static __device__ __forceinline__ void column(const Rig<S>& X, const TP<S>& T, const SD<S>& sd, S* Qr, S* col) {
+  static __device__ __forceinline__ void column(const Rig<S>& X, const JP<S>& jp, const TP<S>& T, const SD<S>& sd,
+                                                S* Qr, S* col) {
     constexpr int ax = Topo::axis[j];
     constexpr bool rev = Topo::jtype[j] == REV;
     const S z[3] = {X.R[ax], X.R[3 + ax], X.R[6 + ax]};
@@ -468,15 +506,14 @@ struct Kin {
     });
     if constexpr (Topo::has_com && !Topo::massless(j)) {
       S t[3];
-      matvec3(X.R, T.mcom[j], t);
-      const S mj = T.mass[j];
-      for (int k = 0; k < 3; ++k) Qr[k] += t[k] + mj * X.p[k];
+      matvec3(X.R, jp.mc, t);
+      for (int k = 0; k < 3; ++k) Qr[k] += t[k] + jp.m * X.p[k];
     }
   }
 
   // Gram pass: G += J_j J_j^T over all columns (packed lower triangle), optionally v = J g.
   template <class S, bool WITH_V, class Q>
-  static __device__ __forceinline__ void gram(const Q& q, const DevProblem& P, const SD<S>& sd, S* G, const S* g, S* v) {
+  static __device__ __forceinline__ void gram(const Q& q, const Consts& P, const SD<S>& sd, S* G, const S* g, S* v) {
     const TP<S>& T = tp<S>(P);
     sfor<0, M>([&](auto I) {
       constexpr int i = decltype(I)::value;
@@ -487,10 +524,10 @@ struct Kin {
       if constexpr (WITH_V) v[i] = S(0);
     });
     S Qr[3] = {S(0), S(0), S(0)};
-    fk<S>(q, T, [&](auto J, const Rig<S>& X) {
+    fk<S>(q, T, [&](auto J, const Rig<S>& X, const JP<S>& jp) {
       constexpr int j = decltype(J)::value;
       S col[M];
-      column<S, j>(X, T, sd, Qr, col);
+      column<S, j>(X, jp, T, sd, Qr, col);
       sfor<0, M>([&](auto I) {
         constexpr int i = decltype(I)::value;
         if constexpr (KI::rdep(i, j)) {
@@ -506,13 +543,13 @@ struct Kin {
 
   // J^T y pass.
   template <class S, class Q>
-  static __device__ __forceinline__ void jty(const Q& q, const DevProblem& P, const SD<S>& sd, const S* y, S* out) {
+  static __device__ __forceinline__ void jty(const Q& q, const Consts& P, const SD<S>& sd, const S* y, S* out) {
     const TP<S>& T = tp<S>(P);
     S Qr[3] = {S(0), S(0), S(0)};
-    fk<S>(q, T, [&](auto J, const Rig<S>& X) {
+    fk<S>(q, T, [&](auto J, const Rig<S>& X, const JP<S>& jp) {
       constexpr int j = decltype(J)::value;
       S col[M];
-      column<S, j>(X, T, sd, Qr, col);
+      column<S, j>(X, jp, T, sd, Qr, col);
       S acc = S(0);
       sfor<0, M>([&](auto I) {
         constexpr int i = decltype(I)::value;
@@ -524,14 +561,14 @@ struct Kin {
 
   // Dense Jacobian (diagnostic): J[r * D + c].
   template <class S, class Q>
-  static __device__ __forceinline__ void jacobian(const Q& q, const DevProblem& P, const SD<S>& sd, S* Jd) {
+  static __device__ __forceinline__ void jacobian(const Q& q, const Consts& P, const SD<S>& sd, S* Jd) {
     const TP<S>& T = tp<S>(P);
     S Qr[3] = {S(0), S(0), S(0)};
     for (int k = 0; k < M * D; ++k) Jd[k] = S(0);
-    fk<S>(q, T, [&](auto J, const Rig<S>& X) {
+    fk<S>(q, T, [&](auto J, const Rig<S>& X, const JP<S>& jp) {
       constexpr int j = decltype(J)::value;
       S col[M];
-      column<S, j>(X, T, sd, Qr, col);
+      column<S, j>(X, jp, T, sd, Qr, col);
       sfor<0, M>([&](auto I) {
         constexpr int i = decltype(I)::value;
         if constexpr (KI::rdep(i, j)) Jd[i * D + j] = col[i];
@@ -539,69 +576,98 @@ struct Kin {
     });
   }
 
-  // World-space collision test of the robot spheres of one link against the obstacles.
-  // Broad phase: link bounding sphere vs obstacle-cluster bounding spheres (both inflated so that
-  // no overlapping pair is ever culled); narrow phase: every sphere of the link vs every obstacle
-  // of an overlapping cluster.
+  // ---------------------------------------------------------------- collision check
+  // Links that carry spheres in this topology (compile-time slots; a runtime sphere range may
+  // still be empty).
+  static constexpr int NGEO = [] {
+    int n = 0;
+    for (int l = 0; l < NJ; ++l) n += Topo::may_have_spheres(l) ? 1 : 0;
+    return n;
+  }();
+
+  // Exact sphere test of one link's spheres (world frame X) against obstacles [o0, o1).
   template <bool MINSD>
-  static __device__ __forceinline__ void check_link(const Rig<float>& X, const DevProblem& P, int l, bool& hit, float& minsd) {
-    const int s0 = P.sph_begin[l], s1 = P.sph_begin[l + 1];
-    if (s0 >= s1) return;
-    if constexpr (MINSD) {
-      for (int s = s0; s < s1; ++s) {
-        const float4 sp = P.sph[s];
-        float c[3];
-        const float lc[3] = {sp.x, sp.y, sp.z};
-        matvec3(X.R, lc, c);
-        for (int k = 0; k < 3; ++k) c[k] += X.p[k];
-        for (int o = 0; o < P.n_obs; ++o) {
-          const float4 ob = P.obs[o];
-          const float dx = c[0] - ob.x, dy = c[1] - ob.y, dz = c[2] - ob.z;
-          const float d2 = dx * dx + dy * dy + dz * dz;
-          const float rr = sp.w + ob.w;
-          hit = hit || (d2 < rr * rr);
-          minsd = fminf(minsd, __fsqrt_rn(d2) - rr);
-        }
-      }
-    } else {
-      const float4 bs = P.link_bs[l];
-      const float lc[3] = {bs.x, bs.y, bs.z};
-      float cb[3];
-      matvec3(X.R, lc, cb);
-      for (int k = 0; k < 3; ++k) cb[k] += X.p[k];
-      for (int c = 0; c < P.n_clus; ++c) {
-        const float4 cl = P.clus[c];
-        const float dx = cb[0] - cl.x, dy = cb[1] - cl.y, dz = cb[2] - cl.z;
-        const float rr = bs.w + cl.w;
-        const bool ov = !hit && (dx * dx + dy * dy + dz * dz < rr * rr);
-        if (ov) {
-          const int2 rg = P.clus_range[c];
-          for (int s = s0; s < s1; ++s) {
-            const float4 sp = P.sph[s];
-            float cs[3];
-            const float sl[3] = {sp.x, sp.y, sp.z};
-            matvec3(X.R, sl, cs);
-            for (int k = 0; k < 3; ++k) cs[k] += X.p[k];
-            for (int o = rg.x; o < rg.y; ++o) {
-              const float4 ob = P.obs[o];
-              const float ex = cs[0] - ob.x, ey = cs[1] - ob.y, ez = cs[2] - ob.z;
-              const float r2 = sp.w + ob.w;
-              hit = hit || (ex * ex + ey * ey + ez * ez < r2 * r2);
-            }
-          }
-        }
+  static __device__ __forceinline__ void narrow(const Rig<float>& X, const CollConsts& K, const float4* obs, int l,
+                                                int o0, int o1, bool& hit, float& minsd) {
+    const int s0 = K.sph_begin[l], s1 = K.sph_begin[l + 1];
+    for (int s = s0; s < s1; ++s) {
+      const float4 sp = K.sph[s];
+      const float lc[3] = {sp.x, sp.y, sp.z};
+      float c[3];
+      matvec3(X.R, lc, c);
+      for (int k = 0; k < 3; ++k) c[k] += X.p[k];
+      for (int o = o0; o < o1; ++o) {
+        const float4 ob = obs[o];
+        const float dx = c[0] - ob.x, dy = c[1] - ob.y, dz = c[2] - ob.z;
+        const float d2 = dx * dx + dy * dy + dz * dz;
+        const float rr = sp.w + ob.w;
+        hit = hit || (d2 < rr * rr);
+        if constexpr (MINSD) minsd = fminf(minsd, __fsqrt_rn(d2) - rr);
       }
     }
   }
 
+  // Collision check of one configuration (robot spheres vs obstacle spheres, strict overlap).
+  // Broad phase, cluster-major: the world centres of all link bounding spheres are formed
+  // first, then every obstacle cluster (LDS broadcast) is tested against all of them, giving
+  // per lane a mask of links and a mask of clusters that overlap something. Narrow phase (only
+  // when a lane has an overlap): every sphere of a flagged link against every obstacle of a
+  // flagged cluster, a superset of the overlapping pairs, so the verdict is exact. MINSD
+  // requests the exhaustive minimum signed distance instead.
   template <bool MINSD, class Q>
-  static __device__ __forceinline__ void check(const Q& q, const DevProblem& P, bool& hit, float& minsd) {
+  static __device__ __forceinline__ void check(const Q& q, const Consts& P, const CollConsts& K, const float4* obs,
+                                               bool& hit, float& minsd) {
     hit = false;
     minsd = __builtin_huge_valf();
-    fk<float>(q, P.f, [&](auto J, const Rig<float>& X) {
+    if constexpr (MINSD) {
+      fk<float>(q, P.f, [&](auto J, const Rig<float>& X, const JP<float>&) {
+        constexpr int l = decltype(J)::value;
+        if constexpr (Topo::may_have_spheres(l)) narrow<true>(X, K, obs, l, 0, K.n_obs, hit, minsd);
+      });
+      return;
+    }
+    float cb[NJ][3];
+    fk<float>(q, P.f, [&](auto J, const Rig<float>& X, const JP<float>&) {
       constexpr int l = decltype(J)::value;
       if constexpr (Topo::may_have_spheres(l)) {
-        if (MINSD || !hit) check_link<MINSD>(X, P, l, hit, minsd);
+        const float4 bs = K.link_bs[l];
+        const float lc[3] = {bs.x, bs.y, bs.z};
+        matvec3(X.R, lc, cb[l]);
+        for (int k = 0; k < 3; ++k) cb[l][k] += X.p[k];
+      }
+    });
+    uint64_t linkmask = 0, clmask_lo = 0, clmask_hi = 0;
+    for (int c = 0; c < K.n_clus; ++c) {
+      const float4 cl = K.clus[c];
+      bool any = false;
+      sfor<0, NJ>([&](auto J) {
+        constexpr int l = decltype(J)::value;
+        if constexpr (Topo::may_have_spheres(l)) {
+          const float r = K.link_bs[l].w + cl.w;
+          const float dx = cb[l][0] - cl.x, dy = cb[l][1] - cl.y, dz = cb[l][2] - cl.z;
+          const bool ov = (dx * dx + dy * dy + dz * dz < r * r) && K.link_bs[l].w >= 0.f;
+          linkmask |= uint64_t(ov) << l;
+          any = any || ov;
+        }
+      });
+      if (any) {
+        if (c < 64) clmask_lo |= uint64_t(1) << c;
+        else clmask_hi |= uint64_t(1) << (c - 64);
+      }
+    }
+    if (linkmask == 0) return;
+    fk<float>(q, P.f, [&](auto J, const Rig<float>& X, const JP<float>&) {
+      constexpr int l = decltype(J)::value;
+      if constexpr (Topo::may_have_spheres(l)) {
+        if ((linkmask >> l) & 1) {
+          for (int c = 0; c < K.n_clus; ++c) {
+            const bool on = c < 64 ? ((clmask_lo >> c) & 1) : ((clmask_hi >> (c - 64)) & 1);
+            if (on && !hit) {
+              const int2 rg = K.clus_range[c];
+              narrow<false>(X, K, obs, l, rg.x, rg.y, hit, minsd);
+            }
+          }
+        }
       }
     });
   }

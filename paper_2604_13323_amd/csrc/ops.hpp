@@ -13,8 +13,10 @@ struct FamilyOps {
   int dof_max;  // compiled D (padded for the linear family)
   hipError_t (*project_persistent)(const ProjArgs& a, int grid, int block, hipStream_t s);
   hipError_t (*project_plain)(const ProjArgs& a, hipStream_t s);
+  hipError_t (*project_tail)(const ProjArgs& a, int grid, hipStream_t s);  // FP32 mode only
   hipError_t (*check)(const CheckArgs& a, int minsd, hipStream_t s);
   hipError_t (*vjp)(const VjpArgs& a, hipStream_t s);
+  hipError_t (*vjp_tail)(const VjpArgs& a, int grid, hipStream_t s);  // FP32 mode only
   hipError_t (*eval_fj)(const DevProblem* P, int64_t n, const void* q, int64_t ld, void* F, void* J, hipStream_t s);
   int (*persistent_blocks_per_cu)(int block);
   size_t (*lds_bytes)(int block);
@@ -30,13 +32,23 @@ struct OpsImpl {
     return hipGetLastError();
   }
   static hipError_t project_plain(const ProjArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_project_plain<Model, IO, S>), dim3(blocks_for(a.n, 64)), dim3(64), lds_bytes(64), s, a);
+    const size_t sm = lds_bytes(64) + ((a.verdict && a.check) ? size_t(a.n_obs) * 16 : 0);
+    hipLaunchKernelGGL((k_project_plain<Model, IO, S>), dim3(blocks_for(a.n, 64)), dim3(64), sm, s, a);
+    return hipGetLastError();
+  }
+  static hipError_t project_tail(const ProjArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_project_tail<Model, IO>), dim3(grid), dim3(64), lds_bytes(64), s, a);
+    return hipGetLastError();
+  }
+  static hipError_t vjp_tail(const VjpArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_vjp_tail<Model, IO>), dim3(grid), dim3(64), lds_bytes(64), s, a);
     return hipGetLastError();
   }
   static hipError_t check(const CheckArgs& a, int minsd, hipStream_t s) {
     const dim3 g(blocks_for(a.n, 256)), b(256);
-    if (minsd) hipLaunchKernelGGL((k_check<Model, IO, true>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_check<Model, IO, false>), g, b, 0, s, a);
+    const size_t sm = size_t(a.n_obs) * 16;
+    if (minsd) hipLaunchKernelGGL((k_check<Model, IO, true>), g, b, sm, s, a);
+    else hipLaunchKernelGGL((k_check<Model, IO, false>), g, b, sm, s, a);
     return hipGetLastError();
   }
   static hipError_t vjp(const VjpArgs& a, hipStream_t s) {
@@ -61,8 +73,10 @@ struct OpsImpl {
     o.dof_max = Model::D;
     o.project_persistent = &project_persistent;
     o.project_plain = &project_plain;
+    o.project_tail = std::is_same<S, float>::value ? &project_tail : nullptr;
     o.check = &check;
     o.vjp = &vjp;
+    o.vjp_tail = std::is_same<S, float>::value ? &vjp_tail : nullptr;
     o.eval_fj = &eval_fj;
     o.persistent_blocks_per_cu = &persistent_blocks_per_cu;
     o.lds_bytes = &lds_bytes;

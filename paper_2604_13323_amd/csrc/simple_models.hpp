@@ -10,10 +10,11 @@ namespace mc {
 // spheres, narrow phase on the obstacles of overlapping clusters), or the exhaustive minimum
 // signed distance.
 template <bool MINSD>
-__device__ __forceinline__ void point_check(const float* c, float r, const DevProblem& P, bool& hit, float& minsd) {
+__device__ __forceinline__ void point_check(const float* c, float r, const CollConsts& K, const float4* obs, bool& hit,
+                                            float& minsd) {
   if constexpr (MINSD) {
-    for (int o = 0; o < P.n_obs; ++o) {
-      const float4 ob = P.obs[o];
+    for (int o = 0; o < K.n_obs; ++o) {
+      const float4 ob = obs[o];
       const float dx = c[0] - ob.x, dy = c[1] - ob.y, dz = c[2] - ob.z;
       const float d2 = dx * dx + dy * dy + dz * dz;
       const float rr = r + ob.w;
@@ -21,14 +22,14 @@ __device__ __forceinline__ void point_check(const float* c, float r, const DevPr
       minsd = fminf(minsd, __fsqrt_rn(d2) - rr);
     }
   } else {
-    for (int k = 0; k < P.n_clus; ++k) {
-      const float4 cl = P.clus[k];
+    for (int k = 0; k < K.n_clus; ++k) {
+      const float4 cl = K.clus[k];
       const float dx = c[0] - cl.x, dy = c[1] - cl.y, dz = c[2] - cl.z;
       const float rr = r + cl.w;
       if (!hit && dx * dx + dy * dy + dz * dz < rr * rr) {
-        const int2 rg = P.clus_range[k];
+        const int2 rg = K.clus_range[k];
         for (int o = rg.x; o < rg.y; ++o) {
-          const float4 ob = P.obs[o];
+          const float4 ob = obs[o];
           const float ex = c[0] - ob.x, ey = c[1] - ob.y, ez = c[2] - ob.z;
           const float r2 = r + ob.w;
           hit = hit || (ex * ex + ey * ey + ez * ez < r2 * r2);
@@ -45,7 +46,7 @@ struct SphereModel {
   template <class S> struct SD { S dummy; };
 
   template <class S, class Q>
-  static __device__ __forceinline__ double residual(const Q& q, const DevProblem&, S* F, SD<S>&) {
+  static __device__ __forceinline__ double residual(const Q& q, const Consts&, S* F, SD<S>&) {
     const double a = q.at(0), b = q.at(1), c = q.at(2);
     const double f = a * a + b * b + c * c - 1.0;
     F[0] = S(f);
@@ -53,26 +54,27 @@ struct SphereModel {
   }
   // J = 2 q^T, so J J^T = 4 q.q and J g = 2 q.g
   template <class S, bool WITH_V, class Q>
-  static __device__ __forceinline__ void gram(const Q& q, const DevProblem&, const SD<S>&, S* G, const S* g, S* v) {
+  static __device__ __forceinline__ void gram(const Q& q, const Consts&, const SD<S>&, S* G, const S* g, S* v) {
     const S a = S(q.at(0)), b = S(q.at(1)), c = S(q.at(2));
     G[0] = S(4) * (a * a + b * b + c * c);
     if constexpr (WITH_V) v[0] = S(2) * (a * g[0] + b * g[1] + c * g[2]);
   }
   template <class S, class Q>
-  static __device__ __forceinline__ void jty(const Q& q, const DevProblem&, const SD<S>&, const S* y, S* out) {
+  static __device__ __forceinline__ void jty(const Q& q, const Consts&, const SD<S>&, const S* y, S* out) {
     for (int k = 0; k < 3; ++k) out[k] = S(2) * S(q.at(k)) * y[0];
   }
   template <class S, class Q>
-  static __device__ __forceinline__ void jacobian(const Q& q, const DevProblem&, const SD<S>&, S* J) {
+  static __device__ __forceinline__ void jacobian(const Q& q, const Consts&, const SD<S>&, S* J) {
     for (int k = 0; k < 3; ++k) J[k] = S(2) * S(q.at(k));
   }
   template <bool MINSD, class Q>
-  static __device__ __forceinline__ void check(const Q& q, const DevProblem& P, bool& hit, float& minsd) {
+  static __device__ __forceinline__ void check(const Q& q, const Consts&, const CollConsts& K, const float4* obs,
+                                               bool& hit, float& minsd) {
     hit = false;
     minsd = __builtin_huge_valf();
-    const float4 ps = P.point_sph;
+    const float4 ps = K.point_sph;
     const float c[3] = {float(q.at(0)) + ps.x, float(q.at(1)) + ps.y, float(q.at(2)) + ps.z};
-    point_check<MINSD>(c, ps.w, P, hit, minsd);
+    point_check<MINSD>(c, ps.w, K, obs, hit, minsd);
   }
 };
 
@@ -86,7 +88,7 @@ struct LinearModel {
   template <class S> struct SD { S dummy; };
 
   template <class S, class Q>
-  static __device__ __forceinline__ double residual(const Q& q, const DevProblem& P, S* F, SD<S>&) {
+  static __device__ __forceinline__ double residual(const Q& q, const Consts& P, S* F, SD<S>&) {
     double qv[D], n2 = 0.0;
     for (int c = 0; c < D; ++c) qv[c] = q.at(c);
     for (int r = 0; r < M; ++r) {
@@ -99,7 +101,7 @@ struct LinearModel {
     return n2;
   }
   template <class S, bool WITH_V, class Q>
-  static __device__ __forceinline__ void gram(const Q&, const DevProblem& P, const SD<S>&, S* G, const S* g, S* v) {
+  static __device__ __forceinline__ void gram(const Q&, const Consts& P, const SD<S>&, S* G, const S* g, S* v) {
     const TP<S>& T = tp<S>(P);
     for (int i = 0; i < M; ++i) {
       for (int k = 0; k <= i; ++k) {
@@ -115,7 +117,7 @@ struct LinearModel {
     }
   }
   template <class S, class Q>
-  static __device__ __forceinline__ void jty(const Q&, const DevProblem& P, const SD<S>&, const S* y, S* out) {
+  static __device__ __forceinline__ void jty(const Q&, const Consts& P, const SD<S>&, const S* y, S* out) {
     const TP<S>& T = tp<S>(P);
     for (int c = 0; c < D; ++c) {
       S acc = S(0);
@@ -124,13 +126,14 @@ struct LinearModel {
     }
   }
   template <class S, class Q>
-  static __device__ __forceinline__ void jacobian(const Q&, const DevProblem& P, const SD<S>&, S* J) {
+  static __device__ __forceinline__ void jacobian(const Q&, const Consts& P, const SD<S>&, S* J) {
     const TP<S>& T = tp<S>(P);
     for (int r = 0; r < M; ++r)
       for (int c = 0; c < D; ++c) J[r * D + c] = T.A[r][c];
   }
   template <bool MINSD, class Q>
-  static __device__ __forceinline__ void check(const Q&, const DevProblem&, bool& hit, float& minsd) {
+  static __device__ __forceinline__ void check(const Q&, const Consts&, const CollConsts&, const float4*, bool& hit,
+                                               float& minsd) {
     hit = false;
     minsd = __builtin_huge_valf();
   }

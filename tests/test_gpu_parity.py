@@ -209,6 +209,36 @@ def test_plain_and_fused_are_bitwise_identical(mc, name):
         assert torch.equal(o.verdict, ref.verdict)
 
 
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+def test_fp64_tail_queue_matches_fp64_mode(mc, name):
+    """A condition threshold below 1 sends every configuration that takes a step to the FP64 path
+    (the tail kernel in the fused variant, in-kernel in the plain one). From there the iteration
+    is the FP64-mode iteration, so results equal FP64 mode on the same (FP32-rounded) inputs
+    after rounding the output to FP32."""
+    sc, P, q, offs, tol, mi = config_inputs(name, small=True, max_geo=16)
+    G = gpu_problem(mc, sc)
+    q32 = to_dev(q, torch.float32)
+    q64 = q32.double()
+    G.fallback_count(reset=True)
+    rf = G.project(q32, tol=tol, max_iter=mi, variant="fused", cond=0.5)
+    rp = G.project(q32, tol=tol, max_iter=mi, variant="plain", geo_offsets=offs, cond=0.5)
+    r64 = G.project(q64, tol=tol, max_iter=mi, variant="fused")
+    torch.cuda.synchronize()
+    stepped = int((r64.iters.cpu().numpy() > 0).sum())
+    assert G.fallback_count(reset=True) >= 2 * stepped  # fused and plain each moved them to FP64
+    for r in (rf, rp):
+        assert torch.equal(r.status, r64.status)
+        assert torch.equal(r.iters, r64.iters)
+        assert torch.equal(r.q, r64.q.float())
+        assert torch.equal(r.verdict, r64.verdict)
+    # the VJP tail: every converged configuration redone in FP64 equals FP64 mode
+    g = torch.randn_like(r64.q)
+    gi32 = G.vjp(rf.q, rf.status, g.float(), cond=0.5)
+    gi64 = G.vjp(rf.q.double(), rf.status, g.float().double())
+    torch.cuda.synchronize()
+    assert torch.equal(gi32, gi64.float())
+
+
 # ---------------------------------------------------------------- collision parity
 @pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3"])
 def test_check_batch_matches_oracle(mc, name):
