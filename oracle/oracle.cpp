@@ -18,10 +18,11 @@
 //   relative pose error of Eq. 2, the humanoid CoM constraint of the Digit
 //   constraint figure (equality to the support-polygon centroid), and the SO(3)
 //   log map with the first-order Taylor form of 1/sinc near zero (Sec. IV-A,
-//   "Tracing Compiler for Constraints").
-//   Collision check after projection (Sec. IV-A: "Collision checking is
-//   performed in parallel after projection"): robot spheres vs obstacle spheres,
-//   strict overlap ||c_i - o_j||^2 < (r_i + r_j)^2, brute force over all pairs.
+//   the paragraph on the tracing compiler).
+//   Collision check of the projected configurations (Sec. IV-A, the validation
+//   that follows projection in the extend step): robot spheres vs obstacle
+//   spheres, strict overlap ||c_i - o_j||^2 < (r_i + r_j)^2, brute force over
+//   all pairs.
 //   VJP (not in the paper): g_in = (I - J^+ J) g at the converged point.
 //
 // Readings where the paper is silent (also listed in the design notes):

@@ -236,7 +236,9 @@ bool validate_family(const HScene& s, std::string& err) {
 
 // ---- obstacle clusters: recursive median split on the widest axis, <= kClusterSize each
 constexpr int kClusterSize = 16;
-constexpr double kBoundMargin = 1e-4;  // metres added to every bounding radius (covers FP32 rounding)
+constexpr double kBoundMargin = 1e-4;  // metres added to every bound (covers FP32 rounding)
+constexpr int kGroupSize = 8;          // clusters per group (the second level of boxes)
+static_assert((MAXC + kGroupSize - 1) / kGroupSize <= MAXSUP, "group table too small");
 
 void build_clusters(std::vector<std::array<double, 4>>& obs, int lo, int hi,
                     std::vector<std::array<double, 4>>& cl, std::vector<std::array<int, 2>>& rg) {
@@ -266,8 +268,15 @@ void build_clusters(std::vector<std::array<double, 4>>& obs, int lo, int hi,
   build_clusters(obs, mid, hi, cl, rg);
 }
 
+// Link bounding spheres and the box around all obstacles (both inflated by kBoundMargin).
+struct HBounds {
+  double lbs[MAXJ][4];
+  double lo[3], hi[3];
+};
+
 template <class T>
-void fill_tp(TP<T>& t, const HScene& s, const std::vector<HT>& tref, const std::vector<double>& submass, double Mtot) {
+void fill_tp(TP<T>& t, const HScene& s, const std::vector<HT>& tref, const std::vector<double>& submass, double Mtot,
+             const HBounds& hb) {
   std::memset(&t, 0, sizeof(TP<T>));
   for (size_t j = 0; j < s.joints.size() && j < MAXJ; ++j) {
     for (int k = 0; k < 9; ++k) t.jR[j][k] = T(s.joints[j].R[k]);
@@ -287,6 +296,12 @@ void fill_tp(TP<T>& t, const HScene& s, const std::vector<HT>& tref, const std::
     for (int k = 0; k < 3; ++k) t.target[b][k] = T(s.blocks[b].target[k]);
   }
   t.inv_total_mass = Mtot > 0 ? T(1.0 / Mtot) : T(0);
+  for (int l = 0; l < MAXJ; ++l)
+    for (int k = 0; k < 4; ++k) t.lbs[l][k] = float(hb.lbs[l][k]);
+  for (int k = 0; k < 3; ++k) {
+    t.obs_lo[k] = float(hb.lo[k]);
+    t.obs_hi[k] = float(hb.hi[k]);
+  }
   if (s.family == MC_FAMILY_LINEAR) {
     for (int r = 0; r < s.m; ++r) {
       for (int c = 0; c < s.d; ++c) t.A[r][c] = T(s.A[size_t(r) * s.d + c]);
@@ -382,13 +397,16 @@ struct mc_problem {
   size_t max_lds_per_block = 0;
   DevProblem* dev = nullptr;
   float4* obs = nullptr;
-  int n_obs = 0;
-  unsigned int* counter = nullptr;  // [0] work-queue head, [1] projection FP64 queue, [2] VJP FP64 queue
+  int n_obs = 0, n_sph = 0;
+  unsigned int* counter = nullptr;  // [0] work-queue head, [1] projection FP64 queue, [2] VJP FP64 queue,
+                                    // [3] exact-check queue
   unsigned long long* fallback = nullptr;
   // FP64 tail queues (FP32 mode), grown to the largest batch seen; calls on one handle must not
   // overlap (one stream at a time).
   mutable double* defer_q = nullptr;
   mutable int32_t* defer_ik = nullptr;
+  mutable double* chk_q = nullptr;
+  mutable int32_t* chk_idx = nullptr;
   mutable int64_t defer_cap = 0;
   mutable int32_t* vjp_idx = nullptr;
   mutable int64_t vjp_cap = 0;
@@ -398,13 +416,17 @@ struct mc_problem {
 static hipError_t grow_defer(const mc_problem* p, int64_t n, int dmax) {
   if (n <= p->defer_cap) return hipSuccess;
   hipError_t e;
-  if (p->defer_q && (e = hipFree(p->defer_q)) != hipSuccess) return e;
-  if (p->defer_ik && (e = hipFree(p->defer_ik)) != hipSuccess) return e;
+  for (void* b : {(void*)p->defer_q, (void*)p->defer_ik, (void*)p->chk_q, (void*)p->chk_idx})
+    if (b && (e = hipFree(b)) != hipSuccess) return e;
   p->defer_q = nullptr;
   p->defer_ik = nullptr;
+  p->chk_q = nullptr;
+  p->chk_idx = nullptr;
   p->defer_cap = 0;
   if ((e = hipMalloc((void**)&p->defer_q, size_t(n) * size_t(dmax) * sizeof(double))) != hipSuccess) return e;
   if ((e = hipMalloc((void**)&p->defer_ik, size_t(n) * 2 * sizeof(int32_t))) != hipSuccess) return e;
+  if ((e = hipMalloc((void**)&p->chk_q, size_t(n) * size_t(dmax) * sizeof(double))) != hipSuccess) return e;
+  if ((e = hipMalloc((void**)&p->chk_idx, size_t(n) * sizeof(int32_t))) != hipSuccess) return e;
   p->defer_cap = n;
   return hipSuccess;
 }
@@ -450,6 +472,8 @@ void mc_problem_destroy(mc_problem* p) {
   hipFree(p->fallback);
   hipFree(p->defer_q);
   hipFree(p->defer_ik);
+  hipFree(p->chk_q);
+  hipFree(p->chk_idx);
   hipFree(p->vjp_idx);
   delete p;
 }
@@ -486,8 +510,8 @@ mc_status mc_problem_create(const void* blob, size_t nbytes, mc_problem** out) {
 
   DevProblem* hp = new DevProblem;
   std::memset(hp, 0, sizeof(DevProblem));
-  fill_tp<double>(hp->c.d, s, tref, submass, Mtot);
-  fill_tp<float>(hp->c.f, s, tref, submass, Mtot);
+  HBounds hb;
+  std::memset(&hb, 0, sizeof hb);
   hp->c.dof = s.d;
   hp->c.rows = s.m;
   hp->c.lin_m = s.family == MC_FAMILY_LINEAR ? s.m : 0;
@@ -524,8 +548,13 @@ mc_status mc_problem_create(const void* blob, size_t nbytes, mc_problem** out) {
         r = std::max(r, std::sqrt(dx * dx + dy * dy + dz * dz) + sp.r);
       }
       K.link_bs[l] = make_float4(float(c[0]), float(c[1]), float(c[2]), float(r + kBoundMargin));
+      hb.lbs[l][0] = c[0];
+      hb.lbs[l][1] = c[1];
+      hb.lbs[l][2] = c[2];
+      hb.lbs[l][3] = r + kBoundMargin;
     } else {
       K.link_bs[l] = make_float4(0.f, 0.f, 0.f, -1.f);
+      hb.lbs[l][3] = -1.0;
     }
   }
   for (int l = MAXJ; l < MAXJ + 4; ++l) K.sph_begin[l] = idx;
@@ -547,10 +576,43 @@ mc_status mc_problem_create(const void* blob, size_t nbytes, mc_problem** out) {
   K.n_clus = int(cl.size());
   std::vector<float4> obs_f(obs.size());
   for (size_t i = 0; i < obs.size(); ++i) obs_f[i] = make_float4(float(obs[i][0]), float(obs[i][1]), float(obs[i][2]), float(obs[i][3]));
+  // cluster boxes (bounding the obstacle spheres, inflated), then groups of up to kGroupSize
+  // consecutive clusters (neighbours in the median-split order) with the union box
+  std::vector<std::array<double, 6>> box(cl.size());
   for (size_t i = 0; i < cl.size(); ++i) {
-    K.clus[i] = make_float4(float(cl[i][0]), float(cl[i][1]), float(cl[i][2]), float(cl[i][3]));
+    std::array<double, 6> b{1e300, 1e300, 1e300, -1e300, -1e300, -1e300};
+    for (int o = rg[i][0]; o < rg[i][1]; ++o)
+      for (int a = 0; a < 3; ++a) {
+        b[a] = std::min(b[a], obs[o][a] - obs[o][3]);
+        b[3 + a] = std::max(b[3 + a], obs[o][a] + obs[o][3]);
+      }
+    for (int a = 0; a < 3; ++a) { b[a] -= kBoundMargin; b[3 + a] += kBoundMargin; }
+    box[i] = b;
+    K.clus_lo[i] = make_float4(float(b[0]), float(b[1]), float(b[2]), 0.f);
+    K.clus_hi[i] = make_float4(float(b[3]), float(b[4]), float(b[5]), 0.f);
     K.clus_range[i] = make_int2(rg[i][0], rg[i][1]);
   }
+  K.n_sup = 0;
+  for (size_t c0 = 0; c0 < cl.size(); c0 += kGroupSize) {
+    const size_t c1 = std::min(cl.size(), c0 + kGroupSize);
+    std::array<double, 6> b{1e300, 1e300, 1e300, -1e300, -1e300, -1e300};
+    for (size_t c = c0; c < c1; ++c)
+      for (int a = 0; a < 3; ++a) { b[a] = std::min(b[a], box[c][a]); b[3 + a] = std::max(b[3 + a], box[c][3 + a]); }
+    K.sup_lo[K.n_sup] = make_float4(float(b[0]), float(b[1]), float(b[2]), 0.f);
+    K.sup_hi[K.n_sup] = make_float4(float(b[3]), float(b[4]), float(b[5]), 0.f);
+    K.sup_range[K.n_sup] = make_int2(int(c0), int(c1));
+    ++K.n_sup;
+  }
+
+  // box around all obstacle spheres (an empty box, lo > hi, when there are none)
+  for (int a = 0; a < 3; ++a) { hb.lo[a] = 1e30; hb.hi[a] = -1e30; }
+  for (const auto& o : obs)
+    for (int a = 0; a < 3; ++a) {
+      hb.lo[a] = std::min(hb.lo[a], o[a] - o[3] - kBoundMargin);
+      hb.hi[a] = std::max(hb.hi[a], o[a] + o[3] + kBoundMargin);
+    }
+  fill_tp<double>(hp->c.d, s, tref, submass, Mtot, hb);
+  fill_tp<float>(hp->c.f, s, tref, submass, Mtot, hb);
 
   mc_problem* p = new mc_problem;
   p->family = s.family;
@@ -574,6 +636,7 @@ mc_status mc_problem_create(const void* blob, size_t nbytes, mc_problem** out) {
   hp->obs = p->obs;
   hp->fallback_counter = p->fallback;
   p->n_obs = K.n_obs;
+  p->n_sph = K.n_sph;
   const unsigned long long zero64 = 0;
   const unsigned int zero32[4] = {0, 0, 0, 0};
   if ((e = hipMemcpy(p->dev, hp, sizeof(DevProblem), hipMemcpyHostToDevice)) != hipSuccess ||
@@ -650,6 +713,7 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
   a.max_iter = opts->max_iter;
   a.check = opts->check_collision;
   a.counter = p->counter;
+  a.n_sph = p->n_sph;
   a.n_obs = p->n_obs;
   hipError_t e;
   if (variant == 1) {
@@ -662,7 +726,7 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
     }
   } else {
     int wpb = opts->waves_per_block > 0 ? opts->waves_per_block : 1;
-    while (wpb > 1 && ops->lds_bytes(64 * wpb) + sizeof(Consts) > p->max_lds_per_block) wpb >>= 1;
+    while (wpb > 1 && ops->lds_bytes(64 * wpb) > p->max_lds_per_block) wpb >>= 1;
     const int block = 64 * wpb;
     int bpc = opts->blocks_per_cu > 0 ? opts->blocks_per_cu : ops->persistent_blocks_per_cu(block);
     int64_t grid = int64_t(p->n_cu) * bpc;
@@ -671,34 +735,23 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
     a.n = n;
     a.n_static = std::min<int64_t>(n, grid * block);
     const bool tail = ops->project_tail != nullptr;
-    if (tail) {
-      if ((e = grow_defer(p, n, ops->dof_max)) != hipSuccess) return hip_fail(e, "project_batch: FP64 queue allocation");
+    const bool ctail = verdict && opts->check_collision && ops->check_tail != nullptr;
+    if (tail || ctail) {
+      if ((e = grow_defer(p, n, ops->dof_max)) != hipSuccess) return hip_fail(e, "project_batch: queue allocation");
       a.defer_count = p->counter + 1;
       a.defer_ik = p->defer_ik;
       a.defer_q = p->defer_q;
       a.defer_cap = p->defer_cap;
+      a.chk_count = p->counter + 3;
+      a.chk_idx = p->chk_idx;
+      a.chk_q = p->chk_q;
     }
-    hipLaunchKernelGGL(k_reset_u32, dim3(1), dim3(64), 0, s, p->counter, 2);
+    a.verdict = verdict;
+    hipLaunchKernelGGL(k_reset_u32, dim3(1), dim3(64), 0, s, p->counter, 4);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "project_batch: reset");
     if ((e = ops->project_persistent(a, int(grid), block, s)) != hipSuccess) return hip_fail(e, "project_batch: persistent launch");
     if (tail && (e = ops->project_tail(a, p->n_cu, s)) != hipSuccess) return hip_fail(e, "project_batch: FP64 tail launch");
-    if (verdict) {
-      CheckArgs c;
-      c.P = p->dev;
-      c.n = n;
-      c.q = q_out;
-      c.ld = ld_out;
-      c.status = status;
-      c.verdict = verdict;
-      c.minsd = nullptr;
-      c.n_obs = p->n_obs;
-      if (opts->check_collision) {
-        if ((e = ops->check(c, 0, s)) != hipSuccess) return hip_fail(e, "project_batch: check launch");
-      } else {
-        hipLaunchKernelGGL(k_fill_u8, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, verdict, n, uint8_t(V_UNCHECKED));
-        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "project_batch: verdict fill");
-      }
-    }
+    if (ctail && (e = ops->check_tail(a, p->n_cu, s)) != hipSuccess) return hip_fail(e, "project_batch: check tail launch");
   }
   if (geo_ok) {
     hipLaunchKernelGGL(k_geo_ok, dim3((n_geo + 255) / 256), dim3(256), 0, s, n_geo, geo_offsets, n, status, verdict, geo_ok);
@@ -725,7 +778,6 @@ mc_status check_batch(const mc_problem* p, int64_t n, const void* q, int64_t ld,
   c.status = nullptr;
   c.verdict = verdict;
   c.minsd = min_signed_dist;
-  c.n_obs = p->n_obs;
   hipError_t e = ops->check(c, min_signed_dist != nullptr, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "check_batch: launch");
   return MC_OK;

@@ -45,26 +45,45 @@ struct TP {
   T inv_total_mass;
   T A[LIN_M][LIN_D];   // linear family (zero padded)
   T b[LIN_M];
+  float lbs[MAXJ][4];  // link bounding sphere (local centre, inflated radius; radius < 0: none)
+  float obs_lo[4];     // box bounding all obstacle spheres (inflated; empty box without obstacles)
+  float obs_hi[4];
 };
 
-// Kinematic and constraint constants (copied to LDS by the projection kernels).
+// Kinematic and constraint constants (read by the kernels with scalar loads).
 struct alignas(16) Consts {
   TP<double> d;
   TP<float> f;
   int32_t dof, rows, lin_m, pad;
 };
 
-// Collision constants (copied to LDS by the kernels that check collisions); the
-// obstacles themselves follow as a dynamic LDS array of n_obs float4.
+constexpr int MAXSUP = 32;  // groups of obstacle clusters
+
+// Collision data. Obstacles are grouped by a recursive median split into clusters of at most 16
+// spheres, and consecutive clusters into groups of at most 8; both levels carry an axis-aligned
+// box that bounds their spheres (inflated by a small margin), and each robot link a bounding
+// sphere of its own spheres.
 struct alignas(16) CollConsts {
-  int32_t n_sph, n_obs, n_clus, pad;
+  int32_t n_sph, n_obs, n_clus, n_sup;
   int32_t sph_begin[MAXJ + 4];   // spheres of link l: [sph_begin[l], sph_begin[l+1])
   float4 sph[MAXS];              // local centre, radius
   float4 link_bs[MAXJ];          // link bounding sphere: local centre, radius (inflated); w < 0: none
   float4 point_sph;              // sphere family: offset and radius of the point robot
-  float4 clus[MAXC];             // cluster bounding spheres (centre, inflated radius)
+  float4 clus_lo[MAXC];          // cluster box: lower corner (xyz)
+  float4 clus_hi[MAXC];          // cluster box: upper corner (xyz)
   int2 clus_range[MAXC];         // obstacle index range of each cluster
+  float4 sup_lo[MAXSUP];         // group box: lower corner
+  float4 sup_hi[MAXSUP];         // group box: upper corner
+  int2 sup_range[MAXSUP];        // cluster index range of each group
 };
+
+// Squared distance from point c to the box [lo, hi] (0 inside).
+__device__ __forceinline__ float box_dist2(const float* c, const float4& lo, const float4& hi) {
+  const float dx = fmaxf(fmaxf(lo.x - c[0], c[0] - hi.x), 0.f);
+  const float dy = fmaxf(fmaxf(lo.y - c[1], c[1] - hi.y), 0.f);
+  const float dz = fmaxf(fmaxf(lo.z - c[2], c[2] - hi.z), 0.f);
+  return dx * dx + dy * dy + dz * dz;
+}
 
 struct DevProblem {
   Consts c;
@@ -134,6 +153,20 @@ __device__ __forceinline__ const Consts& consts_of(const DevProblem* P) {
   CT* c = (CT*)uniform_ptr(&P->c);
   asm volatile("" : "+s"(c));
   return *(const Consts*)c;
+}
+// The collision data and obstacle array as scalar-load memory (wave-uniform reads).
+__device__ __forceinline__ const CollConsts& coll_of(const DevProblem* P) {
+  using CT = const __attribute__((address_space(4))) CollConsts;
+  CT* c = (CT*)uniform_ptr(&P->k);
+  asm volatile("" : "+s"(c));
+  return *(const CollConsts*)c;
+}
+__device__ __forceinline__ const float4* obs_of(const DevProblem* P) {
+  using PT = const float4* const __attribute__((address_space(4)));
+  const float4* o = *(PT*)uniform_ptr(&P->obs);
+  using OT = const __attribute__((address_space(4))) float4;
+  OT* oc = (OT*)uniform_ptr(o);
+  return (const float4*)oc;
 }
 // Same for a reference into LDS: its reads happen after dep.
 template <class T, class U>

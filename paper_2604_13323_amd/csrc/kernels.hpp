@@ -43,7 +43,6 @@ struct ProjArgs {
   int32_t check;
   unsigned int* counter;  // persistent: queue head (reset to 0 before the launch)
   int64_t n_static;       // persistent: configurations [0, n_static) are taken by thread id
-  int32_t n_obs;          // obstacles (dynamic LDS of the plain kernel, which checks in-kernel)
   // FP32 mode: configurations whose FP32 step fails (factorisation or condition estimate) are
   // handed to the FP64 tail kernel through this queue: defer_ik[2s], defer_ik[2s+1] = index and
   // steps taken, defer_q[c * defer_cap + s] = FP64 iterate.
@@ -51,15 +50,16 @@ struct ProjArgs {
   int32_t* defer_ik;
   double* defer_q;
   int64_t defer_cap;
+  // Fused collision check: converged configurations whose broad-phase test (done inside the
+  // last residual pass) found a link near the obstacles are queued here for the exact check
+  // (index in chk_idx[s], FP64 configuration at chk_q[c * defer_cap + s]).
+  unsigned int* chk_count;
+  int32_t* chk_idx;
+  double* chk_q;
+  int32_t n_sph, n_obs;   // robot and obstacle spheres (LDS size of the exact-check kernel)
 };
 
 constexpr int ST_DEFER = -2;  // internal: continue this configuration with FP64 steps
-
-// Stage the collision data in LDS (kernels that run the check start with this).
-__device__ __forceinline__ void stage_coll(CollConsts& dst, float4* obs_lds, const DevProblem* P, int n_obs) {
-  block_copy16(&dst, &P->k, int(sizeof(CollConsts)));
-  block_copy16(obs_lds, P->obs, n_obs * 16);
-}
 
 template <class IO>
 __device__ __forceinline__ double ld_io(const void* p, int64_t k) { return double(static_cast<const IO*>(p)[k]); }
@@ -184,12 +184,13 @@ __device__ __forceinline__ int apply_step(const QLds& q, const S* dq, const Proj
 // when the FP32 factorisation fails or its condition estimate exceeds the threshold (the
 // iteration is then redone with an FP64 step, and the configuration stays in FP64 until it
 // ends).
-template <class Model, class S>
-__device__ __forceinline__ int newton_iteration(const QLds& q, int& k, const ProjArgs& a, const Consts& C, double& resid) {
+template <class Model, class S, bool BROAD = false>
+__device__ __forceinline__ int newton_iteration(const QLds& q, int& k, const ProjArgs& a, const Consts& C, double& resid,
+                                                bool* near = nullptr) {
   constexpr int D = Model::D, M = Model::M;
   typename Model::template SD<S> sd;
   S F[M];
-  const double n2 = Model::template residual<S>(q, C, F, sd);
+  const double n2 = Model::template residual<S, BROAD>(q, C, F, sd, near);
   resid = sqrt(n2);
   if (!finite_t(n2)) return ST_NONFINITE;
   if (n2 < a.tol2) return ST_CONVERGED;
@@ -246,6 +247,42 @@ __device__ __forceinline__ void store_result(const ProjArgs& a, int dof, int64_t
 // Persistent projection kernel: a grid of resident waves pulls configurations from a device
 // work queue (atomic counter), one per lane, and refills a lane when its configuration ends.
 // Dynamic LDS: D * blockDim doubles.
+// Append the calling lane's FP64 configuration to a queue (slot < defer_cap: the queues are
+// sized for the batch).
+template <class Model>
+__device__ __forceinline__ unsigned queue_q(const QLds& q, unsigned* count, double* qbuf, int64_t cap) {
+  const unsigned slot = atomicAdd(count, 1u);
+  double* dst = qbuf + slot;
+  for (int c = 0; c < Model::D; ++c) {
+    *dst = q.at(c);
+    dst += after(cap, c);
+  }
+  return slot;
+}
+
+template <class Model, class IO>
+__device__ __forceinline__ void load_queued(const double* qbuf, int64_t cap, int64_t slot, const QLds& q) {
+  const double* src = qbuf + slot;
+  for (int c = 0; c < Model::D; ++c) {
+    q.set(c, *src);
+    src += after(cap, c);
+  }
+}
+
+// Collision verdict of a configuration that ended with status st (exact check in-line).
+template <class Model>
+__device__ __forceinline__ uint8_t verdict_inline(const QLds& q, const Consts& C, const ProjArgs& a, int st) {
+  if (!a.check || st != ST_CONVERGED) return V_UNCHECKED;
+  const CollConsts& K = coll_of(a.P);
+  return Model::template check_group<1>(q, C, K, K.sph, obs_of(a.P)) ? V_HIT : V_FREE;
+}
+
+// Persistent projection kernel: a grid of resident waves pulls configurations from a device
+// work queue (atomic counter), one per lane, and refills a lane when its configuration ends.
+// With a verdict array the collision check is fused: tree models run the broad-phase test in
+// every residual pass, so at convergence a configuration with no link near the obstacles is
+// FREE at once, and the others are queued for the exact check (k_check_tail).
+// Dynamic LDS: D * blockDim doubles.
 template <class Model, class IO, class S>
 __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
   extern __shared__ double smem[];
@@ -256,24 +293,32 @@ __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
   if (i >= a.n_static) i = a.n;  // not part of the static share
   int k = 0;
   if (i < a.n) load_q<Model, IO>(a, dof, i, q);
+  constexpr bool fused = Model::broad_in_residual;
   for (;;) {
     const bool active = i < a.n;
     if (!__any(active)) break;
     if (active) {
       double resid;
-      int st = newton_iteration<Model, S>(q, k, a, C, resid);
+      bool near = true;
+      int st = newton_iteration<Model, S, fused>(q, k, a, C, resid, &near);
       if (st == ST_DEFER) {
-        const unsigned slot = atomicAdd(a.defer_count, 1u);  // < defer_cap (sized for the batch)
+        const unsigned slot = queue_q<Model>(q, a.defer_count, a.defer_q, a.defer_cap);
         atomicAdd(a.P->fallback_counter, 1ull);
         a.defer_ik[2 * slot] = int32_t(i);
         a.defer_ik[2 * slot + 1] = k;
-        double* dst = a.defer_q + slot;
-        for (int c = 0; c < Model::D; ++c) {
-          *dst = q.at(c);
-          dst += after(a.defer_cap, c);
-        }
       } else if (st >= 0) {
         store_result<Model, IO>(a, dof, i, q, st, k, resid);
+        if (a.verdict) {
+          if constexpr (fused) {
+            if (a.check && st == ST_CONVERGED && near) {
+              a.chk_idx[queue_q<Model>(q, a.chk_count, a.chk_q, a.defer_cap)] = int32_t(i);
+            } else {
+              a.verdict[i] = (a.check && st == ST_CONVERGED) ? V_FREE : V_UNCHECKED;
+            }
+          } else {
+            a.verdict[i] = verdict_inline<Model>(q, C, a, st);
+          }
+        }
       }
       if (st >= 0 || st == ST_DEFER) {
         i = a.n_static + int64_t(atomicAdd(a.counter, 1u));
@@ -281,6 +326,30 @@ __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
         if (i < a.n) load_q<Model, IO>(a, dof, i, q);
       }
     }
+  }
+}
+
+// Exact collision check of the configurations queued by k_project_persistent: L lanes per
+// configuration (grid-stride over the queue).
+// Dynamic LDS: D * blockDim doubles, then the robot spheres and the obstacles (float4 each).
+template <class Model, class IO, int L>
+__global__ void __launch_bounds__(64) k_check_tail(ProjArgs a) {
+  extern __shared__ double smem[];
+  const Consts& C = consts_of(a.P);
+  const CollConsts& K = coll_of(a.P);
+  const int64_t cnt = *a.chk_count;
+  if (int64_t(blockIdx.x) * blockDim.x / L >= cnt) return;  // no queued work for this block
+  const QLds q = q_lds<Model::D>(smem);
+  float4* sph = reinterpret_cast<float4*>(smem + Model::D * blockDim.x);
+  float4* obs = sph + K.n_sph;
+  block_copy16(sph, K.sph, K.n_sph * 16);
+  block_copy16(obs, obs_of(a.P), K.n_obs * 16);
+  __syncthreads();
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (int64_t slot = gid / L; slot < cnt; slot += int64_t(gridDim.x) * blockDim.x / L) {
+    load_queued<Model, IO>(a.chk_q, a.defer_cap, slot, q);
+    const bool hit = Model::template check_group<L>(q, C, K, sph, obs);
+    if ((gid & (L - 1)) == 0) a.verdict[a.chk_idx[slot]] = hit ? V_HIT : V_FREE;
   }
 }
 
@@ -298,23 +367,21 @@ __global__ void __launch_bounds__(64) k_project_tail(ProjArgs a) {
        slot += int64_t(gridDim.x) * blockDim.x) {
     const int64_t i = a.defer_ik[2 * slot];
     int k = a.defer_ik[2 * slot + 1];
-    for (int c = 0; c < Model::D; ++c) q.set(c, a.defer_q[c * a.defer_cap + slot]);
+    load_queued<Model, IO>(a.defer_q, a.defer_cap, slot, q);
     double resid;
     const int st = finish_fp64<Model>(q, k, a, C, resid);
     store_result<Model, IO>(a, dof, i, q, st, k, resid);
+    if (a.verdict) a.verdict[i] = verdict_inline<Model>(q, C, a, st);
   }
 }
 
 // Plain kernel: one launch per geodesic, one configuration per lane, projection and
-// collision check in the same kernel, no work queue.
+// collision check in the same kernel, no work queues (the FP64 steps and the exact check of
+// flagged configurations run in-line).
 template <class Model, class IO, class S>
 __global__ void __launch_bounds__(64) k_project_plain(ProjArgs a) {
   extern __shared__ double smem[];
-  __shared__ CollConsts K;
-  float4* obs = reinterpret_cast<float4*>(smem + Model::D * blockDim.x);
   const Consts& C = consts_of(a.P);
-  if (a.verdict && a.check) stage_coll(K, obs, a.P, a.n_obs);
-  __syncthreads();
   const int dof = C.dof;
   const QLds q = q_lds<Model::D>(smem);
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -322,25 +389,23 @@ __global__ void __launch_bounds__(64) k_project_plain(ProjArgs a) {
   load_q<Model, IO>(a, dof, i, q);
   int k = 0, st;
   double resid;
+  constexpr bool fused = Model::broad_in_residual;
+  bool near = true;
   for (;;) {
-    st = newton_iteration<Model, S>(q, k, a, C, resid);
+    st = newton_iteration<Model, S, fused>(q, k, a, C, resid, &near);
     if (st >= 0) break;
     if (st == ST_DEFER) {  // same rule as the persistent variant: FP64 steps from here on
       atomicAdd(a.P->fallback_counter, 1ull);
       st = finish_fp64<Model>(q, k, a, C, resid);
+      near = true;
       break;
     }
   }
   store_result<Model, IO>(a, dof, i, q, st, k, resid);
   if (a.verdict) {
-    uint8_t v = V_UNCHECKED;
-    if (a.check && st == ST_CONVERGED) {
-      bool hit;
-      float msd;
-      Model::template check<false>(q, C, K, obs, hit, msd);
-      v = hit ? V_HIT : V_FREE;
-    }
-    a.verdict[a.base + i] = v;
+    // same broad-phase rule as the persistent variant; the exact check runs in-line
+    const bool skip = fused && a.check && st == ST_CONVERGED && !near;
+    a.verdict[a.base + i] = skip ? uint8_t(V_FREE) : verdict_inline<Model>(q, C, a, st);
   }
 }
 
@@ -352,29 +417,33 @@ struct CheckArgs {
   const int8_t* status;  // nullable: check only CONVERGED configurations
   uint8_t* verdict;
   void* minsd;           // nullable
-  int32_t n_obs;
 };
 
-// Dynamic LDS: n_obs float4.
-template <class Model, class IO, bool MINSD>
+// check_batch: L lanes per configuration (L = 1 with the exhaustive minimum signed distance).
+template <class Model, class IO, bool MINSD, int L>
 __global__ void __launch_bounds__(256) k_check(CheckArgs a) {
-  extern __shared__ float4 obs[];
-  __shared__ CollConsts K;
   const Consts& C = consts_of(a.P);
-  stage_coll(K, obs, a.P, a.n_obs);
-  __syncthreads();
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t i = gid / L;
+  if (i >= a.n) return;  // whole groups leave together
+  const bool lead = (gid & (L - 1)) == 0;
   if (a.status && a.status[i] != ST_CONVERGED) {
-    a.verdict[i] = V_UNCHECKED;
+    if (lead) a.verdict[i] = V_UNCHECKED;
     return;
   }
   const QGlob<IO> q{static_cast<const IO*>(a.q), a.ld, i, C.dof};
-  bool hit;
-  float msd;
-  Model::template check<MINSD>(q, C, K, obs, hit, msd);
-  a.verdict[i] = hit ? V_HIT : V_FREE;
-  if constexpr (MINSD) st_io<IO>(a.minsd, i, double(msd));
+  if constexpr (MINSD) {
+    static_assert(L == 1, "the exhaustive distance runs one lane per configuration");
+    bool hit;
+    float msd;
+    Model::min_signed_distance(q, C, coll_of(a.P), obs_of(a.P), hit, msd);
+    a.verdict[i] = hit ? V_HIT : V_FREE;
+    st_io<IO>(a.minsd, i, double(msd));
+  } else {
+    const CollConsts& K = coll_of(a.P);
+    const bool hit = Model::template check_group<L>(q, C, K, K.sph, obs_of(a.P));
+    if (lead) a.verdict[i] = hit ? V_HIT : V_FREE;
+  }
 }
 
 struct VjpArgs {

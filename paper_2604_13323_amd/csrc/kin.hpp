@@ -1,8 +1,8 @@
 // Kinematic-tree constraint models with compile-time topology.
 //
-// The paper generates branch-free, loop-unrolled code for each robot with a
-// tracing compiler (Sec. IV-A, "Tracing Compiler for Constraints"). Here the
-// same effect comes from C++ templates: a robot's joint tree, joint types and
+// The paper traces each robot's kinematics into straight-line SIMD code with no
+// branches or loops (Sec. IV-A, tracing compiler). Here the same effect comes
+// from C++ templates: a robot's joint tree, joint types and
 // axes, end-effector frames and constraint blocks are constexpr data, and every
 // loop over joints, rows and Gram entries is unrolled at compile time with the
 // structural zeros of the Jacobian, the Gram matrix and its Cholesky factor
@@ -234,6 +234,7 @@ struct Kin {
   using KI = KInfo<Topo>;
   static constexpr int NJ = Topo::NJ, NB = Topo::NB, NF = Topo::NF, M = Topo::M, D = Topo::NJ;
   static constexpr int family = Topo::family;
+  static constexpr bool broad_in_residual = true;  // residual<S, true> reports link-near-obstacles
   static constexpr bool lnz(int i, int k) { return KI::LP.nz[i][k]; }
 
   // Per-iteration data from the residual pass used by the Jacobian passes.
@@ -284,9 +285,11 @@ struct Kin {
   }
 
   // Forward kinematics, streaming each link frame to visit(ic<j>, frame, joint data) in joint
-  // order. Joint j+1's data is read while joint j is computed; joint j+1's read is ordered
-  // after joint j-1's frame, so the walk keeps one joint of data in flight.
-  template <class T, class Q, class V>
+  // order. Joint j+1's data is read while joint j is computed; with ORDERED, joint j+1's read
+  // is ordered after joint j-1's frame, so the walk keeps one joint of data in flight (register
+  // budget of the projection passes); without, the compiler may issue every read up front (the
+  // collision kernels, which have registers to spare and little arithmetic to hide latency).
+  template <class T, bool ORDERED = true, class Q, class V>
   static __device__ __forceinline__ void fk(const Q& q, const TP<T>& P, V&& visit) {
     Rig<T> L[NJ];
     JP<T> cur = load_joint<T, 0>(q, P, 0);
@@ -296,7 +299,8 @@ struct Kin {
       constexpr int ax = Topo::axis[j];
       JP<T> nxt;  // the next joint's data, requested one joint ahead
       if constexpr (j + 1 < NJ) {
-        if constexpr (j > 0) nxt = load_joint<T, j + 1>(q, P, L[j - 1].p[2]);
+        if constexpr (!ORDERED) nxt = load_joint<T, j + 1>(q, P, 0);
+        else if constexpr (j > 0) nxt = load_joint<T, j + 1>(q, P, L[j - 1].p[2]);
         else nxt = load_joint<T, j + 1>(q, P, cur.q);
       }
       Rig<T>& X = L[j];
@@ -410,14 +414,29 @@ struct Kin {
   }
 
   // Residual pass in FP64: returns ||F(q)||^2 (FP64); F in the step precision S and the
-  // step data for the Jacobian passes.
-  template <class S, class Q>
-  static __device__ __forceinline__ double residual(const Q& q, const Consts& P, S* F, SD<S>& sd) {
+  // step data for the Jacobian passes. With BROAD, the pass also sets `near` when the
+  // bounding sphere of some link reaches into the box around all obstacles (the first test of
+  // the collision broad phase, on the frames this pass computes anyway).
+  template <class S, bool BROAD = false, class Q>
+  static __device__ __forceinline__ double residual(const Q& q, const Consts& P, S* F, SD<S>& sd,
+                                                    bool* near = nullptr) {
     Rig<double> Fr[NF];
     double cm[3] = {0.0, 0.0, 0.0};
     double n2 = 0.0;
+    int nr = 0;
     fk<double>(q, P.d, [&](auto J, const Rig<double>& X, const JP<double>& jp) {
       constexpr int j = decltype(J)::value;
+      if constexpr (BROAD && Topo::may_have_spheres(j)) {
+        const TP<double>& Pb = after_cp(P.d, X.p[2]);
+        const float4 blo = make_float4(Pb.obs_lo[0], Pb.obs_lo[1], Pb.obs_lo[2], 0.f);
+        const float4 bhi = make_float4(Pb.obs_hi[0], Pb.obs_hi[1], Pb.obs_hi[2], 0.f);
+        const float* bs = Pb.lbs[j];
+        float c[3];
+        for (int k = 0; k < 3; ++k)
+          c[k] = float(X.p[k] + X.R[3 * k] * bs[0] + X.R[3 * k + 1] * bs[1] + X.R[3 * k + 2] * bs[2]);
+        nr |= (bs[3] >= 0.f) & (box_dist2(c, blo, bhi) <= bs[3] * bs[3]);
+        asm volatile("" : "+v"(nr));  // pins the test to this point of the walk (no sinking)
+      }
       sfor<0, NF>([&](auto FI) {
         constexpr int f = decltype(FI)::value;
         if constexpr (Topo::frame_link[f] == j) frame_pose<double>(X, P.d, f, Fr[f]);
@@ -449,6 +468,7 @@ struct Kin {
         n2 += e0 * e0 + e1 * e1;
       }
     });
+    if constexpr (BROAD) *near = nr != 0;
     return n2;
   }
 
@@ -607,68 +627,91 @@ struct Kin {
     }
   }
 
-  // Collision check of one configuration (robot spheres vs obstacle spheres, strict overlap).
-  // Broad phase, cluster-major: the world centres of all link bounding spheres are formed
-  // first, then every obstacle cluster (LDS broadcast) is tested against all of them, giving
-  // per lane a mask of links and a mask of clusters that overlap something. Narrow phase (only
-  // when a lane has an overlap): every sphere of a flagged link against every obstacle of a
-  // flagged cluster, a superset of the overlapping pairs, so the verdict is exact. MINSD
-  // requests the exhaustive minimum signed distance instead.
-  template <bool MINSD, class Q>
-  static __device__ __forceinline__ void check(const Q& q, const Consts& P, const CollConsts& K, const float4* obs,
-                                               bool& hit, float& minsd) {
-    hit = false;
-    minsd = __builtin_huge_valf();
-    if constexpr (MINSD) {
-      fk<float>(q, P.f, [&](auto J, const Rig<float>& X, const JP<float>&) {
-        constexpr int l = decltype(J)::value;
-        if constexpr (Topo::may_have_spheres(l)) narrow<true>(X, K, obs, l, 0, K.n_obs, hit, minsd);
-      });
-      return;
-    }
-    float cb[NJ][3];
-    fk<float>(q, P.f, [&](auto J, const Rig<float>& X, const JP<float>&) {
+  // Collision check of one configuration (robot spheres vs obstacle spheres, strict overlap) by
+  // a group of L consecutive lanes that all hold the same configuration (L = 1, 2, 4, ..., 64).
+  // Lane t of the group owns clusters t, t + L, ... (the boxes of its first slots are loaded once,
+  // before the walk, and kept in registers). The walk streams each link frame; for a link with spheres every
+  // lane tests the link's bounding sphere against its clusters' boxes, a ballot gives the group
+  // the clusters the link overlaps, and for each of those the L lanes share the exact tests of the
+  // link's spheres (sph) against the cluster's obstacles (obs). sph and obs may point to LDS
+  // copies. Returns the verdict (the same in all L lanes).
+  template <int L, class Q>
+  static __device__ __forceinline__ bool check_group(const Q& q, const Consts& P, const CollConsts& K,
+                                                     const float4* sph, const float4* obs) {
+    static_assert(L >= 1 && L <= 64 && (L & (L - 1)) == 0, "L must be a power of two <= 64");
+    constexpr int PB = (MAXC + L - 1) / L < 8 ? (MAXC + L - 1) / L : 8;  // boxes kept in registers
+    const int lane = int(__lane_id());
+    const int t = lane & (L - 1);
+    const int shift = lane & ~(L - 1);
+    const uint64_t gmask = L == 64 ? ~uint64_t(0) : ((uint64_t(1) << L) - 1);
+    const int ncl = K.n_clus;
+    const int nb = (ncl + L - 1) / L;  // cluster slots per lane
+    float4 blo[PB], bhi[PB];
+    sfor<0, PB>([&](auto BI) {
+      constexpr int bi = decltype(BI)::value;
+      const int c = bi * L + t;
+      blo[bi] = c < ncl ? K.clus_lo[c] : make_float4(1e30f, 1e30f, 1e30f, 0.f);  // empty box
+      bhi[bi] = c < ncl ? K.clus_hi[c] : make_float4(-1e30f, -1e30f, -1e30f, 0.f);
+    });
+    bool hit = false;
+    fk<float, false>(q, P.f, [&](auto J, const Rig<float>& X, const JP<float>&) {
       constexpr int l = decltype(J)::value;
       if constexpr (Topo::may_have_spheres(l)) {
         const float4 bs = K.link_bs[l];
-        const float lc[3] = {bs.x, bs.y, bs.z};
-        matvec3(X.R, lc, cb[l]);
-        for (int k = 0; k < 3; ++k) cb[l][k] += X.p[k];
-      }
-    });
-    uint64_t linkmask = 0, clmask_lo = 0, clmask_hi = 0;
-    for (int c = 0; c < K.n_clus; ++c) {
-      const float4 cl = K.clus[c];
-      bool any = false;
-      sfor<0, NJ>([&](auto J) {
-        constexpr int l = decltype(J)::value;
-        if constexpr (Topo::may_have_spheres(l)) {
-          const float r = K.link_bs[l].w + cl.w;
-          const float dx = cb[l][0] - cl.x, dy = cb[l][1] - cl.y, dz = cb[l][2] - cl.z;
-          const bool ov = (dx * dx + dy * dy + dz * dz < r * r) && K.link_bs[l].w >= 0.f;
-          linkmask |= uint64_t(ov) << l;
-          any = any || ov;
-        }
-      });
-      if (any) {
-        if (c < 64) clmask_lo |= uint64_t(1) << c;
-        else clmask_hi |= uint64_t(1) << (c - 64);
-      }
-    }
-    if (linkmask == 0) return;
-    fk<float>(q, P.f, [&](auto J, const Rig<float>& X, const JP<float>&) {
-      constexpr int l = decltype(J)::value;
-      if constexpr (Topo::may_have_spheres(l)) {
-        if ((linkmask >> l) & 1) {
-          for (int c = 0; c < K.n_clus; ++c) {
-            const bool on = c < 64 ? ((clmask_lo >> c) & 1) : ((clmask_hi >> (c - 64)) & 1);
-            if (on && !hit) {
-              const int2 rg = K.clus_range[c];
-              narrow<false>(X, K, obs, l, rg.x, rg.y, hit, minsd);
+        if (bs.w >= 0.f) {
+          const float lc[3] = {bs.x, bs.y, bs.z};
+          float cb[3];
+          matvec3(X.R, lc, cb);
+          for (int k = 0; k < 3; ++k) cb[k] += X.p[k];
+          const float r2 = bs.w * bs.w;
+          const int s0 = K.sph_begin[l], ns = K.sph_begin[l + 1] - s0;
+          // exact tests of the link against the clusters of slot b that some lane found overlapping
+          auto process = [&](int b, bool ov) {
+            uint64_t m = (uint64_t(__ballot(ov)) >> shift) & gmask;
+            while (m) {  // the same list in all L lanes
+              const int cc = b * L + __builtin_ctzll(m);
+              m &= m - 1;
+              const int2 rg = K.clus_range[cc];
+              const int no = rg.y - rg.x, np = ns * no;
+              for (int pi = t; pi < np; pi += L) {
+                const int si = pi / no, oi = pi - si * no;
+                const float4 sp = sph[s0 + si];
+                const float4 ob = obs[rg.x + oi];
+                const float lp[3] = {sp.x, sp.y, sp.z};
+                float w[3];
+                matvec3(X.R, lp, w);
+                const float dx = w[0] + X.p[0] - ob.x, dy = w[1] + X.p[1] - ob.y, dz = w[2] + X.p[2] - ob.z;
+                const float rr = sp.w + ob.w;
+                hit = hit || (dx * dx + dy * dy + dz * dz < rr * rr);
+              }
             }
+          };
+          uint32_t own = 0;  // bit b: this lane's cluster of slot b overlaps the link's bound
+          sfor<0, PB>([&](auto BI) {
+            constexpr int bi = decltype(BI)::value;
+            own |= uint32_t(box_dist2(cb, blo[bi], bhi[bi]) <= r2) << bi;
+          });
+          const int nbp = nb < PB ? nb : PB;
+          for (int b = 0; b < nbp; ++b) process(b, (own >> b) & 1u);
+          for (int b = PB; b < nb; ++b) {  // clusters beyond the register-resident ones
+            const int c = b * L + t;
+            process(b, c < ncl && box_dist2(cb, K.clus_lo[c], K.clus_hi[c]) <= r2);
           }
         }
       }
+    });
+    return ((uint64_t(__ballot(hit)) >> shift) & gmask) != 0;
+  }
+
+  // Exhaustive minimum signed distance over all sphere pairs (and the verdict), one lane.
+  template <class Q>
+  static __device__ __forceinline__ void min_signed_distance(const Q& q, const Consts& P, const CollConsts& K,
+                                                             const float4* obs, bool& hit, float& minsd) {
+    hit = false;
+    minsd = __builtin_huge_valf();
+    fk<float>(q, P.f, [&](auto J, const Rig<float>& X, const JP<float>&) {
+      constexpr int l = decltype(J)::value;
+      if constexpr (Topo::may_have_spheres(l)) narrow<true>(X, K, obs, l, 0, K.n_obs, hit, minsd);
     });
   }
 };

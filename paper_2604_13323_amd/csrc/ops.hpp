@@ -14,6 +14,7 @@ struct FamilyOps {
   hipError_t (*project_persistent)(const ProjArgs& a, int grid, int block, hipStream_t s);
   hipError_t (*project_plain)(const ProjArgs& a, hipStream_t s);
   hipError_t (*project_tail)(const ProjArgs& a, int grid, hipStream_t s);  // FP32 mode only
+  hipError_t (*check_tail)(const ProjArgs& a, int grid, hipStream_t s);
   hipError_t (*check)(const CheckArgs& a, int minsd, hipStream_t s);
   hipError_t (*vjp)(const VjpArgs& a, hipStream_t s);
   hipError_t (*vjp_tail)(const VjpArgs& a, int grid, hipStream_t s);  // FP32 mode only
@@ -24,6 +25,9 @@ struct FamilyOps {
 
 inline unsigned blocks_for(int64_t n, int block) { return unsigned((n + block - 1) / block); }
 
+constexpr int kCheckLanes = 4;       // check_batch: lanes per configuration
+constexpr int kTailCheckLanes = 32;  // exact check of the flagged configurations of a projection
+
 template <class Model, class IO, class S>
 struct OpsImpl {
   static size_t lds_bytes(int block) { return size_t(Model::D) * sizeof(double) * size_t(block); }
@@ -32,12 +36,16 @@ struct OpsImpl {
     return hipGetLastError();
   }
   static hipError_t project_plain(const ProjArgs& a, hipStream_t s) {
-    const size_t sm = lds_bytes(64) + ((a.verdict && a.check) ? size_t(a.n_obs) * 16 : 0);
-    hipLaunchKernelGGL((k_project_plain<Model, IO, S>), dim3(blocks_for(a.n, 64)), dim3(64), sm, s, a);
+    hipLaunchKernelGGL((k_project_plain<Model, IO, S>), dim3(blocks_for(a.n, 64)), dim3(64), lds_bytes(64), s, a);
     return hipGetLastError();
   }
   static hipError_t project_tail(const ProjArgs& a, int grid, hipStream_t s) {
     hipLaunchKernelGGL((k_project_tail<Model, IO>), dim3(grid), dim3(64), lds_bytes(64), s, a);
+    return hipGetLastError();
+  }
+  static hipError_t check_tail(const ProjArgs& a, int grid, hipStream_t s) {
+    const size_t lds = lds_bytes(64) + size_t(a.n_sph + a.n_obs) * 16;
+    hipLaunchKernelGGL((k_check_tail<Model, IO, kTailCheckLanes>), dim3(grid), dim3(64), lds, s, a);
     return hipGetLastError();
   }
   static hipError_t vjp_tail(const VjpArgs& a, int grid, hipStream_t s) {
@@ -45,10 +53,12 @@ struct OpsImpl {
     return hipGetLastError();
   }
   static hipError_t check(const CheckArgs& a, int minsd, hipStream_t s) {
-    const dim3 g(blocks_for(a.n, 256)), b(256);
-    const size_t sm = size_t(a.n_obs) * 16;
-    if (minsd) hipLaunchKernelGGL((k_check<Model, IO, true>), g, b, sm, s, a);
-    else hipLaunchKernelGGL((k_check<Model, IO, false>), g, b, sm, s, a);
+    if (minsd) {
+      hipLaunchKernelGGL((k_check<Model, IO, true, 1>), dim3(blocks_for(a.n, 256)), dim3(256), 0, s, a);
+    } else {
+      constexpr int L = kCheckLanes;
+      hipLaunchKernelGGL((k_check<Model, IO, false, L>), dim3(blocks_for(a.n * L, 256)), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
   }
   static hipError_t vjp(const VjpArgs& a, hipStream_t s) {
@@ -74,6 +84,7 @@ struct OpsImpl {
     o.project_persistent = &project_persistent;
     o.project_plain = &project_plain;
     o.project_tail = std::is_same<S, float>::value ? &project_tail : nullptr;
+    o.check_tail = Model::broad_in_residual ? &check_tail : nullptr;
     o.check = &check;
     o.vjp = &vjp;
     o.vjp_tail = std::is_same<S, float>::value ? &vjp_tail : nullptr;

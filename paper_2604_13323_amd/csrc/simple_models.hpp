@@ -6,9 +6,8 @@
 
 namespace mc {
 
-// Point-robot sphere test against the clustered obstacles (broad phase on cluster bounding
-// spheres, narrow phase on the obstacles of overlapping clusters), or the exhaustive minimum
-// signed distance.
+// Point-robot sphere test against the grouped, clustered obstacles (group and cluster boxes,
+// then the obstacles of overlapping clusters), or the exhaustive minimum signed distance.
 template <bool MINSD>
 __device__ __forceinline__ void point_check(const float* c, float r, const CollConsts& K, const float4* obs, bool& hit,
                                             float& minsd) {
@@ -22,17 +21,18 @@ __device__ __forceinline__ void point_check(const float* c, float r, const CollC
       minsd = fminf(minsd, __fsqrt_rn(d2) - rr);
     }
   } else {
-    for (int k = 0; k < K.n_clus; ++k) {
-      const float4 cl = K.clus[k];
-      const float dx = c[0] - cl.x, dy = c[1] - cl.y, dz = c[2] - cl.z;
-      const float rr = r + cl.w;
-      if (!hit && dx * dx + dy * dy + dz * dz < rr * rr) {
-        const int2 rg = K.clus_range[k];
-        for (int o = rg.x; o < rg.y; ++o) {
-          const float4 ob = obs[o];
-          const float ex = c[0] - ob.x, ey = c[1] - ob.y, ez = c[2] - ob.z;
-          const float r2 = r + ob.w;
-          hit = hit || (ex * ex + ey * ey + ez * ez < r2 * r2);
+    for (int g = 0; g < K.n_sup; ++g) {
+      if (!__any(!hit && box_dist2(c, K.sup_lo[g], K.sup_hi[g]) <= r * r)) continue;  // wave-uniform
+      const int2 cr = K.sup_range[g];
+      for (int k = cr.x; k < cr.y; ++k) {
+        if (!hit && box_dist2(c, K.clus_lo[k], K.clus_hi[k]) <= r * r) {
+          const int2 rg = K.clus_range[k];
+          for (int o = rg.x; o < rg.y; ++o) {
+            const float4 ob = obs[o];
+            const float ex = c[0] - ob.x, ey = c[1] - ob.y, ez = c[2] - ob.z;
+            const float r2 = r + ob.w;
+            hit = hit || (ex * ex + ey * ey + ez * ez < r2 * r2);
+          }
         }
       }
     }
@@ -41,12 +41,13 @@ __device__ __forceinline__ void point_check(const float* c, float r, const CollC
 
 struct SphereModel {
   static constexpr int family = 0;
+  static constexpr bool broad_in_residual = false;
   static constexpr int D = 3, M = 1;
   static constexpr bool lnz(int, int) { return true; }
   template <class S> struct SD { S dummy; };
 
-  template <class S, class Q>
-  static __device__ __forceinline__ double residual(const Q& q, const Consts&, S* F, SD<S>&) {
+  template <class S, bool BROAD = false, class Q>
+  static __device__ __forceinline__ double residual(const Q& q, const Consts&, S* F, SD<S>&, bool* = nullptr) {
     const double a = q.at(0), b = q.at(1), c = q.at(2);
     const double f = a * a + b * b + c * c - 1.0;
     F[0] = S(f);
@@ -67,14 +68,25 @@ struct SphereModel {
   static __device__ __forceinline__ void jacobian(const Q& q, const Consts&, const SD<S>&, S* J) {
     for (int k = 0; k < 3; ++k) J[k] = S(2) * S(q.at(k));
   }
-  template <bool MINSD, class Q>
-  static __device__ __forceinline__ void check(const Q& q, const Consts&, const CollConsts& K, const float4* obs,
-                                               bool& hit, float& minsd) {
+  // Point robot: every lane of the group runs the whole (cheap) test.
+  template <int L, class Q>
+  static __device__ __forceinline__ bool check_group(const Q& q, const Consts&, const CollConsts& K, const float4*,
+                                                     const float4* obs) {
+    bool hit = false;
+    float minsd;
+    const float4 ps = K.point_sph;
+    const float c[3] = {float(q.at(0)) + ps.x, float(q.at(1)) + ps.y, float(q.at(2)) + ps.z};
+    point_check<false>(c, ps.w, K, obs, hit, minsd);
+    return hit;
+  }
+  template <class Q>
+  static __device__ __forceinline__ void min_signed_distance(const Q& q, const Consts&, const CollConsts& K,
+                                                             const float4* obs, bool& hit, float& minsd) {
     hit = false;
     minsd = __builtin_huge_valf();
     const float4 ps = K.point_sph;
     const float c[3] = {float(q.at(0)) + ps.x, float(q.at(1)) + ps.y, float(q.at(2)) + ps.z};
-    point_check<MINSD>(c, ps.w, K, obs, hit, minsd);
+    point_check<true>(c, ps.w, K, obs, hit, minsd);
   }
 };
 
@@ -83,12 +95,13 @@ struct SphereModel {
 // so they contribute nothing to the step.
 struct LinearModel {
   static constexpr int family = 1;
+  static constexpr bool broad_in_residual = false;
   static constexpr int D = LIN_D, M = LIN_M;
   static constexpr bool lnz(int, int) { return true; }
   template <class S> struct SD { S dummy; };
 
-  template <class S, class Q>
-  static __device__ __forceinline__ double residual(const Q& q, const Consts& P, S* F, SD<S>&) {
+  template <class S, bool BROAD = false, class Q>
+  static __device__ __forceinline__ double residual(const Q& q, const Consts& P, S* F, SD<S>&, bool* = nullptr) {
     double qv[D], n2 = 0.0;
     for (int c = 0; c < D; ++c) qv[c] = q.at(c);
     for (int r = 0; r < M; ++r) {
@@ -131,9 +144,14 @@ struct LinearModel {
     for (int r = 0; r < M; ++r)
       for (int c = 0; c < D; ++c) J[r * D + c] = T.A[r][c];
   }
-  template <bool MINSD, class Q>
-  static __device__ __forceinline__ void check(const Q&, const Consts&, const CollConsts&, const float4*, bool& hit,
-                                               float& minsd) {
+  template <int L, class Q>
+  static __device__ __forceinline__ bool check_group(const Q&, const Consts&, const CollConsts&, const float4*,
+                                                     const float4*) {
+    return false;
+  }
+  template <class Q>
+  static __device__ __forceinline__ void min_signed_distance(const Q&, const Consts&, const CollConsts&, const float4*,
+                                                             bool& hit, float& minsd) {
     hit = false;
     minsd = __builtin_huge_valf();
   }

@@ -4,9 +4,11 @@ These are the operations the method has to perform per configuration (FMA = 2 FL
 counted from the scene's structure: forward kinematics once per iteration, the residual,
 the Jacobian columns once, the Gram matrix J J^T over structural nonzeros, the Cholesky
 factorisation and two triangular solves over the nonzeros of the factor, J^T y and the
-update. Recomputations an implementation makes (the library re-runs the kinematics in its
-Gram and J^T y passes to save registers) are not counted; sine/cosine, square roots and
-reciprocals count as one FLOP each.
+update; and, once per configuration, the broad phase of the collision check (each link's
+bounding sphere moved to the world frame and tested against the box around the obstacles).
+Recomputations an implementation makes (the library re-runs the kinematics in its Gram and
+J^T y passes to save registers, and runs the broad-phase test in every residual pass, not only
+the last) are not counted; sine/cosine, square roots and reciprocals count as one FLOP each.
 """
 from __future__ import annotations
 
@@ -139,7 +141,9 @@ def iteration_flops(sc: S.Scene) -> dict:
     jty = 2 * int(Jp.sum())
     it = dict(fk=fk + frames, residual=res, jacobian=cols, gram=gram, cholesky=chol, solve=solves, jty=jty,
               update=4 * d)
-    return dict(per_iter=sum(it.values()), final=fk + frames + res, parts=it)
+    n_geo_links = len(set(int(l) for l in sc.spheres[:, 0] if l >= 0)) if sc.spheres is not None and len(sc.spheres) else 0
+    broad = 35 * n_geo_links  # R c + p (18) and the box distance test (17) per link with spheres
+    return dict(per_iter=sum(it.values()), final=fk + frames + res + broad, parts=dict(it, broad_once=broad))
 
 
 def batch_flops(sc: S.Scene, iters: np.ndarray) -> float:

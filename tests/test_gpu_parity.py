@@ -192,7 +192,7 @@ def test_c1_with_divergence_exit(mc, dt, qtol):
     print("c1 max_step 0.5", stats)
 
 
-@pytest.mark.parametrize("name", ["c0", "c3"])
+@pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3"])
 def test_plain_and_fused_are_bitwise_identical(mc, name):
     sc, P, q, offs, tol, mi = config_inputs(name, small=True)
     G = gpu_problem(mc, sc)
@@ -239,6 +239,27 @@ def test_fp64_tail_queue_matches_fp64_mode(mc, name):
     assert torch.equal(gi32, gi64.float())
 
 
+@pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3"])
+def test_fused_verdicts_match_oracle(mc, name):
+    """Verdicts written by project_batch (fused: broad-phase flag from the last residual pass,
+    exact check only for flagged configurations) equal the oracle's brute-force check of the
+    same output configurations outside the 1e-5 m band; non-converged ones are UNCHECKED."""
+    sc, P, q, offs, tol, mi = config_inputs(name, small=True)
+    G = gpu_problem(mc, sc)
+    r = G.project(to_dev(q, torch.float32), tol=tol, max_iter=mi, variant="fused")
+    torch.cuda.synchronize()
+    st = from_dev(r.status).astype(int)
+    v = from_dev(r.verdict).astype(int)
+    conv = st == CONV
+    assert (v[~conv] == 2).all()
+    qg = from_dev(r.q).T[conv]
+    vo, sdo = P.check(qg)
+    out = np.abs(sdo) > 1e-5
+    assert (v[conv][out] == vo[out]).all(), f"{np.sum(v[conv][out] != vo[out])} verdicts differ"
+    if name != "c0":
+        assert (vo == 1).any() or name == "c3", "workload has no colliding configuration to exercise the queue"
+
+
 # ---------------------------------------------------------------- collision parity
 @pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3"])
 def test_check_batch_matches_oracle(mc, name):
@@ -277,6 +298,41 @@ def test_vjp_matches_oracle(mc, name):
         den = np.maximum(np.linalg.norm(go[ok], axis=1), 1e-3 * np.linalg.norm(g[ok], axis=1))
         assert (num / den).max() < rtol, (num / den).max()
         assert np.all(gg[~ok] == 0)
+
+
+def test_vjp_matches_fp64_central_differences_c4(mc):
+    """C4 differentiation check: GPU VJPs (FP32 mode, FP64 solve only where the condition estimate
+    exceeds 1e6) against FP64 central finite differences (h = 1e-6) of the oracle's projection,
+    on 256 configurations sampled from the converged ones and re-projected to ||F|| < 1e-13 (the
+    VJP is the derivative of the projection there). Relative error in ||g_in||, bound 1e-3."""
+    sc, P, q, offs, tol, mi = config_inputs("c4", small=True)
+    G = gpu_problem(mc, sc)
+    r = G.project(to_dev(q, torch.float32), tol=tol, max_iter=mi)
+    torch.cuda.synchronize()
+    st = from_dev(r.status).astype(int)
+    rng = np.random.default_rng(3)  # stream 3: the FD sample
+    idx = rng.choice(np.where(st == CONV)[0], size=min(256, int((st == CONV).sum())), replace=False)
+    q0, s0, _, _ = P.project(from_dev(r.q).T[idx].astype(np.float64), tol=1e-13, max_iter=100)
+    assert (s0 == CONV).all()
+    g = rng.standard_normal(q0.shape)
+    h = 1e-6
+    d = sc.d
+    qp = np.repeat(q0, d, axis=0) + h * np.tile(np.eye(d), (len(q0), 1))
+    qm = np.repeat(q0, d, axis=0) - h * np.tile(np.eye(d), (len(q0), 1))
+    pp, sp, _, _ = P.project(qp, tol=1e-13, max_iter=100)
+    pm, sm, _, _ = P.project(qm, tol=1e-13, max_iter=100)
+    assert (sp == CONV).all() and (sm == CONV).all()
+    dP = ((pp - pm) / (2 * h)).reshape(len(q0), d, d)  # [n, k (input), :] = dP/dq_k
+    g_fd = np.einsum("nkj,nj->nk", dP, g)                # (dP/dq)^T g
+    gi = G.vjp(to_dev(q0, torch.float32), torch.zeros(len(q0), dtype=torch.int8, device="cuda"),
+               to_dev(g, torch.float32))
+    torch.cuda.synchronize()
+    gg = from_dev(gi).T.astype(np.float64)
+    rel = np.linalg.norm(gg - g_fd, axis=1) / np.linalg.norm(g_fd, axis=1)
+    assert rel.max() < 1e-3, f"max relative error {rel.max():.3e}"
+    # and the oracle's gradient (explicit null-space projector) agrees with both
+    go, _ = P.vjp(q0, g, s0)
+    assert (np.linalg.norm(go - g_fd, axis=1) / np.linalg.norm(g_fd, axis=1)).max() < 1e-6
 
 
 def test_path_length_and_interpolation_match_oracle(mc):
