@@ -36,10 +36,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+PROJECTION_SOURCES = ("common.hpp", "kin.hpp", "kernels.hpp", "simple_models.hpp", "fam_humanoid36_f32.hip")
+
+
 def source_hash() -> str:
+    """Hash of the sources the humanoid projection kernel is compiled from (its counter-based traffic
+    figure is reported only while they are unchanged)."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2604_13323_amd", "csrc", "*"))):
-        with open(p, "rb") as f:
+    for name in PROJECTION_SOURCES:
+        with open(os.path.join(ROOT, "paper_2604_13323_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
@@ -88,11 +93,51 @@ def cpu_baseline(cfg, max_configs: int):
     conv = st == 0
     v, _ = P.check(qo[conv])
     dt = time.perf_counter() - t0
+    # one thread on the first 2,048 configurations of the same sample
+    q1 = q[:2048]
+    t1 = time.perf_counter()
+    qo1, st1, _, _ = P.project(q1, tol=cfg["tol"], max_iter=cfg["max_iter"], threads=1)
+    P.check(qo1[st1 == 0], threads=1)
+    dt1 = time.perf_counter() - t1
     return dict(value=float(conv.sum() / dt), unit="converged projections/s", cores=oracle.max_threads(),
                 kind="oracle",
                 sample=f"{len(q)} configurations ({g_take} geodesics x {per}) of the humanoid batch, "
                        f"projection + brute-force collision check, FP64, {dt:.2f} s",
-                seconds=dt, n=int(len(q)))
+                seconds=dt, n=int(len(q)),
+                single_thread=dict(value=float((st1 == 0).sum() / dt1), n=int(len(q1)), seconds=dt1))
+
+
+def other_workloads(M, S, FL, torch, steps):
+    """The smaller configurations through the same fused path (attribution rows, not the headline):
+    throughput, iteration statistics, algorithmic FLOP rate and HBM rate (inputs, outputs, status,
+    iterations, residual and verdict bytes) of the whole projection step."""
+    rows = {}
+    for name in ("c0", "c1", "c2"):
+        cfg = S.make_config(name)
+        sc = cfg["scene"]
+        G = M.Problem(sc.to_blob())
+        if "q" in cfg:
+            q = torch.from_numpy(np.ascontiguousarray(cfg["q"].T)).to("cuda", torch.float32)
+        else:
+            q, _, _ = build_batch(G, cfg, torch)
+        n = q.shape[1]
+        kw = dict(tol=cfg["tol"], max_iter=cfg["max_iter"])
+        out = G.project(q, variant="fused", **kw)
+        ms = timed(lambda: G.project(q, variant="fused", out=out, **kw), steps, 2, torch)
+        st = out.status.cpu().numpy()
+        it = out.iters.cpu().numpy().astype(np.int64)
+        vd = out.verdict.cpu().numpy()
+        conv = st == 0
+        byts = n * (2 * sc.d * 4 + 4 + 3)
+        rows[name] = dict(configs=n, dof=sc.d, rows=sc.m, ms_per_step=ms, converged_per_s=float(conv.sum() / (ms * 1e-3)),
+                          converged_frac=float(conv.mean()), iters_mean=float(it.mean()),
+                          iters_p99=float(np.percentile(it, 99)),
+                          collision_free_frac_of_converged=float((vd[conv] == 0).mean()) if conv.any() else None,
+                          fp64_fallbacks=G.fallback_count(reset=True),
+                          tflops_algorithmic=FL.batch_flops(sc, it) / (ms * 1e-3) / 1e12,
+                          hbm_gbs_algorithmic=byts / (ms * 1e-3) / 1e9)
+        log(f"{name}: {n} configurations, {ms:.3f} ms/step, {rows[name]['converged_per_s']:.4g} converged/s")
+    return rows
 
 
 def main():
@@ -109,6 +154,8 @@ def main():
                     help="also run a plain 256 MiB device copy (counter calibration for profiling runs)")
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true", help="use the library's default launch shape")
+    ap.add_argument("--no-others", action="store_true", help="skip the C0-C2 attribution rows")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the projection shards by whole "
@@ -135,6 +182,13 @@ def main():
     out = G.project(q_in, variant="fused", **kw)
     torch.cuda.synchronize()
     log(f"humanoid batch: {n} configurations built; first projection done")
+    tuning = None
+    if not args.no_autotune and args.waves_per_block == 0 and args.blocks_per_cu == 0:
+        from paper_2604_13323_amd import autotune
+        tuning = autotune.tune(G, q_in, tol=tol, max_iter=mi, cache_path=None)
+        kw.update(tuning["best"])
+        shapes = ", ".join("%dx%d: %.3f" % (r["waves_per_block"], r["blocks_per_cu"], r["ms"]) for r in tuning["table"])
+        log(f"autotuned launch shape: {tuning['best']} ({shapes} ms)")
 
     # --- headline: fused persistent projection + collision check
     G.fallback_count(reset=True)
@@ -178,6 +232,18 @@ def main():
         plain = dict(ms_per_step=ms_plain, value=n_conv / (ms_plain * 1e-3), launches=len(offs_host) - 1,
                      identical_outputs=same)
         log(f"plain: {ms_plain:.3f} ms/step ({plain['value']:.4g}/s), outputs identical to fused: {same}")
+        # the same per-geodesic launches captured once in a HIP graph and replayed (launch cost removed)
+        offs_d = torch.from_numpy(offs_host).cuda()
+        outg = M.ProjectResult(q=torch.empty_like(out.q), status=torch.empty_like(out.status),
+                               iters=torch.empty_like(out.iters), resid=torch.empty_like(out.resid),
+                               verdict=torch.empty_like(out.verdict), geo_ok=None)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            G.project(q_in, variant="plain", geo_offsets=offs_d, geo_offsets_host=offs_host, out=outg, **kw)
+        ms_pg = timed(graph.replay, args.plain_steps, 1, torch)
+        same_g = bool(torch.equal(outg.q, out.q) and torch.equal(outg.status, out.status))
+        plain["graph"] = dict(ms_per_step=ms_pg, value=n_conv / (ms_pg * 1e-3), identical_outputs=same_g)
+        log(f"plain + hipGraph: {ms_pg:.3f} ms/step ({n_conv / (ms_pg * 1e-3):.4g}/s), identical: {same_g}")
 
     # --- fwd + VJP on the differentiation batch
     fv = None
@@ -203,6 +269,8 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
+
+    others = None if args.no_others else other_workloads(M, S, FL, torch, args.steps)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -235,11 +303,14 @@ def main():
         "plain": plain,
         "fused_vs_plain": (value / plain["value"]) if plain else None,
         "fwd_vjp": fv,
+        "other_workloads": others,
         "stats": {"converged_frac": n_conv / n, "iters_mean": float(iters.mean()),
                   "iters_p99": float(np.percentile(iters, 99)), "iters_max": int(iters.max()),
                   "collision_free_frac_of_converged": float((verdict[status == 0] == 0).mean()) if n_conv else None,
                   "fp64_fallbacks_per_step": fallbacks / max(1, args.steps + args.warmup),
-                  "check_ms": ms_check, "projection_ms": ms_proj,
+                  "check_batch_ms": ms_check, "projection_ms": ms_proj,
+                  "launch_shape": {k: kw[k] for k in ("waves_per_block", "blocks_per_cu")},
+                  "autotune": tuning["table"] if tuning else None,
                   "gpu": torch.cuda.get_device_name(0)},
     }
     print(json.dumps(result), flush=True)

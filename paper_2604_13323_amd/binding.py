@@ -159,7 +159,11 @@ class Problem:
     # -- projection -------------------------------------------------------
     def project(self, q: torch.Tensor, tol=1e-6, max_iter=50, alpha=1.0, lam=0.0, max_step=0.0, cond=1e6,
                 check=True, variant="auto", geo_offsets=None, geo_ok=False, waves_per_block=0, blocks_per_cu=0,
-                out: ProjectResult | None = None) -> ProjectResult:
+                out: ProjectResult | None = None, geo_offsets_host=None) -> ProjectResult:
+        """Project the columns of q ([d, n], float32 or float64). geo_offsets (CSR, int32) may be a host array
+        or a device tensor; the plain variant also needs them on the host (geo_offsets_host, or a host
+        geo_offsets). Under stream capture pass device offsets, `out`, and call once eagerly beforehand with a
+        batch at least as large (that sizes the library's work queues)."""
         n, ld = _soa(q, self.d, "project")
         dt = _dtype_code(q)
         dev = q.device
@@ -171,12 +175,19 @@ class Problem:
                                 verdict=torch.empty(n, dtype=torch.uint8, device=dev),
                                 geo_ok=None)
         offs_dev, offs_host, n_geo = None, None, 0
+        if geo_offsets_host is not None:
+            offs_host = np.ascontiguousarray(np.asarray(geo_offsets_host, dtype=np.int32))
+            n_geo = len(offs_host) - 1
         if geo_offsets is not None:
-            offs_np = np.ascontiguousarray(np.asarray(geo_offsets, dtype=np.int32))
-            n_geo = len(offs_np) - 1
-            offs_host = offs_np
-            offs_dev = geo_offsets if isinstance(geo_offsets, torch.Tensor) and geo_offsets.is_cuda else \
-                torch.from_numpy(offs_np).to(dev)
+            if isinstance(geo_offsets, torch.Tensor) and geo_offsets.is_cuda:
+                offs_dev = geo_offsets
+                n_geo = geo_offsets.numel() - 1
+            else:
+                offs_np = np.ascontiguousarray(np.asarray(geo_offsets, dtype=np.int32))
+                n_geo = len(offs_np) - 1
+                if offs_host is None:
+                    offs_host = offs_np
+                offs_dev = torch.from_numpy(offs_np).to(dev)
             out._offs = offs_dev  # keep alive while the stream runs
             if geo_ok and out.geo_ok is None:
                 out.geo_ok = torch.empty(n_geo, dtype=torch.uint8, device=dev)

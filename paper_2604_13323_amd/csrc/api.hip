@@ -410,6 +410,9 @@ struct mc_problem {
   mutable int64_t defer_cap = 0;
   mutable int32_t* vjp_idx = nullptr;
   mutable int64_t vjp_cap = 0;
+  // resident workgroups per CU of the persistent kernel, by (FP64 mode, waves per block = 1, 2, 4);
+  // queried once, so later calls (and calls under stream capture) make no runtime query
+  mutable int occ[2][3] = {{0, 0, 0}, {0, 0, 0}};
 };
 
 // Grow a tail queue to hold n entries (synchronises the device when it reallocates).
@@ -728,7 +731,12 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
     int wpb = opts->waves_per_block > 0 ? opts->waves_per_block : 1;
     while (wpb > 1 && ops->lds_bytes(64 * wpb) > p->max_lds_per_block) wpb >>= 1;
     const int block = 64 * wpb;
-    int bpc = opts->blocks_per_cu > 0 ? opts->blocks_per_cu : ops->persistent_blocks_per_cu(block);
+    int bpc = opts->blocks_per_cu;
+    if (bpc <= 0) {
+      int& c = p->occ[ops->f64][wpb == 1 ? 0 : wpb == 2 ? 1 : 2];
+      if (c <= 0) c = ops->persistent_blocks_per_cu(block);
+      bpc = c;
+    }
     int64_t grid = int64_t(p->n_cu) * bpc;
     grid = std::min<int64_t>(grid, (n + block - 1) / block);
     a.base = 0;
@@ -751,7 +759,8 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "project_batch: reset");
     if ((e = ops->project_persistent(a, int(grid), block, s)) != hipSuccess) return hip_fail(e, "project_batch: persistent launch");
     if (tail && (e = ops->project_tail(a, p->n_cu, s)) != hipSuccess) return hip_fail(e, "project_batch: FP64 tail launch");
-    if (ctail && (e = ops->check_tail(a, p->n_cu, s)) != hipSuccess) return hip_fail(e, "project_batch: check tail launch");
+    // 2 workgroups of 4 waves per CU: 2,048 flagged configurations per round (blocks without work leave at once)
+    if (ctail && (e = ops->check_tail(a, 2 * p->n_cu, s)) != hipSuccess) return hip_fail(e, "project_batch: check tail launch");
   }
   if (geo_ok) {
     hipLaunchKernelGGL(k_geo_ok, dim3((n_geo + 255) / 256), dim3(256), 0, s, n_geo, geo_offsets, n, status, verdict, geo_ok);

@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
 // configuration (grid-stride over the queue).
 // Dynamic LDS: D * blockDim doubles, then the robot spheres and the obstacles (float4 each).
 template <class Model, class IO, int L>
-__global__ void __launch_bounds__(64) k_check_tail(ProjArgs a) {
+__global__ void __launch_bounds__(256) k_check_tail(ProjArgs a) {
   extern __shared__ double smem[];
   const Consts& C = consts_of(a.P);
   const CollConsts& K = coll_of(a.P);

@@ -26,7 +26,7 @@ struct FamilyOps {
 inline unsigned blocks_for(int64_t n, int block) { return unsigned((n + block - 1) / block); }
 
 constexpr int kCheckLanes = 4;       // check_batch: lanes per configuration
-constexpr int kTailCheckLanes = 32;  // exact check of the flagged configurations of a projection
+constexpr int kTailCheckLanes = 64;  // exact check of the flagged configurations of a projection (a wave each)
 
 template <class Model, class IO, class S>
 struct OpsImpl {
@@ -44,8 +44,8 @@ struct OpsImpl {
     return hipGetLastError();
   }
   static hipError_t check_tail(const ProjArgs& a, int grid, hipStream_t s) {
-    const size_t lds = lds_bytes(64) + size_t(a.n_sph + a.n_obs) * 16;
-    hipLaunchKernelGGL((k_check_tail<Model, IO, kTailCheckLanes>), dim3(grid), dim3(64), lds, s, a);
+    const size_t lds = lds_bytes(256) + size_t(a.n_sph + a.n_obs) * 16;
+    hipLaunchKernelGGL((k_check_tail<Model, IO, kTailCheckLanes>), dim3(grid), dim3(256), lds, s, a);
     return hipGetLastError();
   }
   static hipError_t vjp_tail(const VjpArgs& a, int grid, hipStream_t s) {
