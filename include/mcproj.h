@@ -92,10 +92,15 @@ typedef struct {
   int32_t waves_per_block;    /* fused variant: 1, 2 or 4 wavefronts per workgroup (0 = auto)   */
   int32_t blocks_per_cu;      /* fused variant: resident workgroups per CU for the persistent
                                  grid (0 = auto)                                                */
+  int32_t mode;               /* 0 stacked: one min-norm step on all constraint rows together;
+                                 1 cyclic (Sec. IV-C, Alg. 2 getDescentStep): one min-norm step
+                                 per constraint block, in the scene's block order, each from the
+                                 configuration the previous one left; an iteration is one cycle
+                                 and max_step bounds its total displacement. Fused variant only. */
 } mc_project_opts;
 
 /* Default options (tol 1e-6, max_iter 50, alpha 1, lambda 0, max_step off, threshold 1e6,
-   check on, variant auto). */
+   check on, variant auto, stacked mode). */
 void mc_default_opts(mc_project_opts* opts);
 
 /* Create a problem from a scene blob (magic 'MCCS', version 1: the little-endian layout written

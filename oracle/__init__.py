@@ -50,7 +50,8 @@ def lib():
         L.oracle_residual.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, ctypes.c_int]
         L.oracle_jacobian.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, ctypes.c_int]
         L.oracle_project.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, P, P, P, ctypes.c_double,
-                                     ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, P]
+                                     ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, P,
+                                     ctypes.c_int]
         L.oracle_check.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, P, ctypes.c_int]
         L.oracle_vjp.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, P, P, P, ctypes.c_int]
         L.oracle_path_length.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_int32, P, P]
@@ -104,9 +105,11 @@ class Problem:
         return J
 
     def project(self, q, tol=1e-6, max_iter=50, alpha=1.0, lam=0.0, max_step=0.0, threads: int = 0,
-                path_info: bool = False):
+                path_info: bool = False, mode: str = "stacked"):
         """Returns (q_out, status, iters, resid) and, with path_info, an [n, 2] array holding the
-        smallest sigma_min(J) along each path and its longest step."""
+        smallest sigma_min(J) along each path and its longest step (the longest iteration
+        displacement in cyclic mode). mode: "stacked" (one system per step) or "cyclic" (one step
+        per constraint block, in order)."""
         q = np.ascontiguousarray(q, np.float64).reshape(-1, self.d)
         n = q.shape[0]
         qo = np.zeros_like(q)
@@ -116,7 +119,7 @@ class Problem:
         pi = np.zeros((n, 2)) if path_info else None
         rc = lib().oracle_project(*self._args(), n, _p(q), _p(qo), _p(st), _p(it), _p(rs), float(tol),
                                   int(max_iter), float(alpha), float(lam), float(max_step), threads,
-                                  None if pi is None else _p(pi))
+                                  None if pi is None else _p(pi), {"stacked": 0, "cyclic": 1}[mode])
         if rc != 0:
             raise ValueError("oracle_project failed (%d)" % rc)
         return (qo, st, it, rs, pi) if path_info else (qo, st, it, rs)

@@ -397,14 +397,13 @@ void jacobi_singular_values(int rows, int cols, const double* A_in, double* sv) 
 
 bool all_finite(const double* x, int n) { for (int i = 0; i < n; ++i) if (!std::isfinite(x[i])) return false; return true; }
 
-struct Opts { double tol; int max_iter; double alpha, lambda, max_step; };
+struct Opts { double tol; int max_iter; double alpha, lambda, max_step; int mode; };  // mode 1: cyclic
 
 // Descent step delta with J delta ~= F: minimum-norm (lambda = 0) or damped (lambda > 0).
 // J is m x d row-major. Returns false on a singular Jacobian. smin_out (nullable) receives
 // the smallest singular value of J.
-bool descent_step(const Scene& s, const double* J, const double* F, double lambda, double* delta,
+bool descent_step(int m, int d, const double* J, const double* F, double lambda, double* delta,
                   double* smin_out = nullptr) {
-  const int m = s.m, d = s.d;
   // singularity test on J (= on J^T) by its singular values
   std::vector<double> At(size_t(d) * m);  // J^T, column-major d x m: column i = row i of J
   for (int i = 0; i < m; ++i) for (int j = 0; j < d; ++j) At[size_t(i) * d + j] = J[size_t(i) * d + j];
@@ -448,6 +447,54 @@ bool descent_step(const Scene& s, const double* J, const double* F, double lambd
 
 double norm2(const double* x, int n) { double a = 0; for (int i = 0; i < n; ++i) a += x[i] * x[i]; return std::sqrt(a); }
 
+// Cyclic mode of ParallelProject (Alg. 2 with getDescentStep looping over the constraints,
+// Sec. IV-C): each iteration first evaluates the whole stacked residual for the convergence
+// test, then, for each constraint block in the scene's order, takes the min-norm step of that
+// block's rows alone, evaluated at the configuration the previous blocks left. The divergence
+// test applies to the displacement of the whole iteration (the step getDescentStep returns);
+// when it fires the configuration is left where the iteration started.
+void project_one_cyclic(const Scene& s, const Targets& tg, const Opts& o, const double* q0, double* q,
+                        int8_t* status, int32_t* iters, double* resid, double* path) {
+  const int d = s.d, m = s.m;
+  std::vector<double> F(m), J(size_t(m) * d), delta(d), qs(d);
+  for (int j = 0; j < d; ++j) q[j] = q0[j];
+  if (path) { path[0] = INFINITY; path[1] = 0.0; }
+  for (int k = 0;; ++k) {
+    residual<double>(s, tg, q, F.data());
+    double nF = norm2(F.data(), m);
+    *resid = nF;
+    *iters = k;
+    if (!all_finite(F.data(), m) || !all_finite(q, d)) { *status = ST_NONFINITE; return; }
+    if (nF < o.tol) { *status = ST_CONVERGED; return; }
+    if (k >= o.max_iter) { *status = ST_MAX_ITER; return; }
+    for (int j = 0; j < d; ++j) qs[j] = q[j];
+    int r0 = 0;
+    for (const auto& b : s.blocks) {
+      const int mb = block_rows(b, s);
+      residual<double>(s, tg, q, F.data());
+      jacobian(s, tg, q, J.data());
+      if (!all_finite(J.data() + size_t(r0) * d, mb * d)) { *status = ST_NONFINITE; return; }
+      double smin = 0.0;
+      const bool ok = descent_step(mb, d, J.data() + size_t(r0) * d, F.data() + r0, o.lambda, delta.data(), &smin);
+      if (path) path[0] = std::min(path[0], smin);
+      if (!ok) { *status = ST_SINGULAR; return; }
+      for (int j = 0; j < d; ++j) delta[j] *= o.alpha;
+      if (!all_finite(delta.data(), d)) { *status = ST_NONFINITE; return; }
+      for (int j = 0; j < d; ++j) q[j] -= delta[j];
+      r0 += mb;
+    }
+    double tot = 0.0;
+    for (int j = 0; j < d; ++j) tot += (q[j] - qs[j]) * (q[j] - qs[j]);
+    tot = std::sqrt(tot);
+    if (path) path[1] = std::max(path[1], tot);
+    if (o.max_step > 0.0 && tot > o.max_step) {
+      for (int j = 0; j < d; ++j) q[j] = qs[j];
+      *status = ST_DIVERGED;
+      return;
+    }
+  }
+}
+
 // ParallelProject for one configuration (Alg. 2), per-configuration termination.
 // path (nullable) receives {smallest sigma_min(J) over the steps taken, longest step}, used by
 // the parity tests to recognise ill-conditioned projection paths.
@@ -468,7 +515,7 @@ void project_one(const Scene& s, const Targets& tg, const Opts& o, const double*
     jacobian(s, tg, q, J.data());
     if (!all_finite(J.data(), m * d)) { *status = ST_NONFINITE; return; }
     double smin = 0.0;
-    const bool ok = descent_step(s, J.data(), F.data(), o.lambda, delta.data(), &smin);
+    const bool ok = descent_step(m, d, J.data(), F.data(), o.lambda, delta.data(), &smin);
     if (path) path[0] = std::min(path[0], smin);
     if (!ok) { *status = ST_SINGULAR; return; }
     for (int j = 0; j < d; ++j) delta[j] *= o.alpha;
@@ -582,18 +629,23 @@ int oracle_jacobian(const void* blob, size_t nbytes, int64_t n, const double* q,
 
 // Projection of n configurations (row-major [n][d]).
 // path_info (nullable) [n][2]: smallest sigma_min(J) along the path, longest step.
+// mode 0: stacked system per step; mode 1: cyclic over the constraint blocks.
 int oracle_project(const void* blob, size_t nbytes, int64_t n, const double* q_in, double* q_out,
                    int8_t* status, int32_t* iters, double* resid, double tol, int32_t max_iter,
-                   double alpha, double lambda, double max_step, int nthreads, double* path_info) {
+                   double alpha, double lambda, double max_step, int nthreads, double* path_info, int mode) {
   Scene s;
   if (!parse(blob, nbytes, s)) return 1;
-  if (n < 0 || !(tol > 0) || max_iter < 0) return 2;
+  if (n < 0 || !(tol > 0) || max_iter < 0 || (mode != 0 && mode != 1)) return 2;
   Targets tg = make_targets(s);
-  Opts o{tol, max_iter, alpha, lambda, max_step};
+  Opts o{tol, max_iter, alpha, lambda, max_step, mode};
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads_or_default(nthreads))
-  for (int64_t i = 0; i < n; ++i)
-    project_one(s, tg, o, q_in + i * s.d, q_out + i * s.d, status + i, iters + i, resid + i,
-                path_info ? path_info + 2 * i : nullptr);
+  for (int64_t i = 0; i < n; ++i) {
+    double* pi = path_info ? path_info + 2 * i : nullptr;
+    if (mode == 1)
+      project_one_cyclic(s, tg, o, q_in + i * s.d, q_out + i * s.d, status + i, iters + i, resid + i, pi);
+    else
+      project_one(s, tg, o, q_in + i * s.d, q_out + i * s.d, status + i, iters + i, resid + i, pi);
+  }
   return 0;
 }
 

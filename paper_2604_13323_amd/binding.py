@@ -31,7 +31,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("lambda_", ctypes.c_double), ("max_step", ctypes.c_double),
                 ("fp64_cond_threshold", ctypes.c_double), ("check_collision", ctypes.c_int32),
-                ("variant", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+                ("variant", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("mode", ctypes.c_int32)]
 
 
 _lib = None
@@ -106,8 +107,11 @@ def _soa(q: torch.Tensor, d: int, name: str):
     return q.shape[1], q.stride(0)
 
 
+MODES = {"stacked": 0, "cyclic": 1}
+
+
 def make_opts(dtype=MC_F32, tol=1e-6, max_iter=50, alpha=1.0, lam=0.0, max_step=0.0, cond=1e6, check=True,
-              variant="auto", waves_per_block=0, blocks_per_cu=0) -> Opts:
+              variant="auto", waves_per_block=0, blocks_per_cu=0, mode="stacked") -> Opts:
     o = Opts()
     lib().mc_default_opts(ctypes.byref(o))
     o.dtype = dtype
@@ -121,6 +125,7 @@ def make_opts(dtype=MC_F32, tol=1e-6, max_iter=50, alpha=1.0, lam=0.0, max_step=
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.waves_per_block = waves_per_block
     o.blocks_per_cu = blocks_per_cu
+    o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     return o
 
 
@@ -159,7 +164,7 @@ class Problem:
     # -- projection -------------------------------------------------------
     def project(self, q: torch.Tensor, tol=1e-6, max_iter=50, alpha=1.0, lam=0.0, max_step=0.0, cond=1e6,
                 check=True, variant="auto", geo_offsets=None, geo_ok=False, waves_per_block=0, blocks_per_cu=0,
-                out: ProjectResult | None = None, geo_offsets_host=None) -> ProjectResult:
+                out: ProjectResult | None = None, geo_offsets_host=None, mode="stacked") -> ProjectResult:
         """Project the columns of q ([d, n], float32 or float64). geo_offsets (CSR, int32) may be a host array
         or a device tensor; the plain variant also needs them on the host (geo_offsets_host, or a host
         geo_offsets). Under stream capture pass device offsets, `out`, and call once eagerly beforehand with a
@@ -191,7 +196,8 @@ class Problem:
             out._offs = offs_dev  # keep alive while the stream runs
             if geo_ok and out.geo_ok is None:
                 out.geo_ok = torch.empty(n_geo, dtype=torch.uint8, device=dev)
-        o = make_opts(dt, tol, max_iter, alpha, lam, max_step, cond, check, variant, waves_per_block, blocks_per_cu)
+        o = make_opts(dt, tol, max_iter, alpha, lam, max_step, cond, check, variant, waves_per_block, blocks_per_cu,
+                      mode)
         rc = lib().project_batch(self._h, n, _ptr(q), ld, _ptr(out.q), out.q.stride(0), _ptr(out.status),
                                  _ptr(out.iters), _ptr(out.resid), _ptr(out.verdict), _ptr(offs_dev),
                                  None if offs_host is None else offs_host.ctypes.data_as(ctypes.c_void_p),

@@ -372,9 +372,15 @@ __global__ void k_path_grad(int64_t n, const IO* q, int64_t ld, const int32_t* o
     }
     if (has_next) seg = nn;
   }
-  // wave reduction, one atomic per wave
+  // wave reduction, then the workgroup's waves through LDS: one atomic per workgroup
   for (int off = 32; off > 0; off >>= 1) seg += __shfl_xor(seg, off);
-  if (loss && (threadIdx.x & 63) == 0 && seg != 0.0) atomicAdd(loss, IO(seg));
+  __shared__ double part[4];  // launched with 256 threads
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = seg;
+  __syncthreads();
+  if (loss && threadIdx.x == 0) {
+    const double t = part[0] + part[1] + part[2] + part[3];
+    if (t != 0.0) atomicAdd(loss, IO(t));
+  }
 }
 
 __global__ void k_geo_ok(int n_geo, const int32_t* offs, int64_t n, const int8_t* status, const uint8_t* verdict, uint8_t* ok) {
@@ -461,6 +467,7 @@ void mc_default_opts(mc_project_opts* o) {
   o->variant = 0;
   o->waves_per_block = 0;
   o->blocks_per_cu = 0;
+  o->mode = 0;
 }
 
 int32_t mc_problem_dof(const mc_problem* p) { return p ? p->d : -1; }
@@ -669,6 +676,8 @@ static mc_status check_opts(const mc_problem* p, const mc_project_opts* o) {
   if (o->waves_per_block != 0 && o->waves_per_block != 1 && o->waves_per_block != 2 && o->waves_per_block != 4)
     return fail(MC_ERR_INVALID_ARG, "waves_per_block must be 0, 1, 2 or 4");
   if (o->blocks_per_cu < 0 || o->blocks_per_cu > 64) return fail(MC_ERR_INVALID_ARG, "blocks_per_cu must be 0..64");
+  if (o->mode != 0 && o->mode != 1) return fail(MC_ERR_INVALID_ARG, "mode must be 0 (stacked) or 1 (cyclic)");
+  if (o->mode == 1 && o->variant == 1) return fail(MC_ERR_UNSUPPORTED, "the cyclic mode runs in the fused variant only");
   (void)p;
   return MC_OK;
 }
@@ -729,12 +738,13 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
     }
   } else {
     int wpb = opts->waves_per_block > 0 ? opts->waves_per_block : 1;
-    while (wpb > 1 && ops->lds_bytes(64 * wpb) > p->max_lds_per_block) wpb >>= 1;
+    const bool cyc = opts->mode == 1;
+    while (wpb > 1 && (cyc ? 2 : 1) * ops->lds_bytes(64 * wpb) > p->max_lds_per_block) wpb >>= 1;
     const int block = 64 * wpb;
     int bpc = opts->blocks_per_cu;
     if (bpc <= 0) {
       int& c = p->occ[ops->f64][wpb == 1 ? 0 : wpb == 2 ? 1 : 2];
-      if (c <= 0) c = ops->persistent_blocks_per_cu(block);
+      if (c <= 0) c = ops->persistent_blocks_per_cu(block);  // registers bound it, not LDS
       bpc = c;
     }
     int64_t grid = int64_t(p->n_cu) * bpc;
@@ -757,8 +767,10 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
     a.verdict = verdict;
     hipLaunchKernelGGL(k_reset_u32, dim3(1), dim3(64), 0, s, p->counter, 4);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "project_batch: reset");
-    if ((e = ops->project_persistent(a, int(grid), block, s)) != hipSuccess) return hip_fail(e, "project_batch: persistent launch");
-    if (tail && (e = ops->project_tail(a, p->n_cu, s)) != hipSuccess) return hip_fail(e, "project_batch: FP64 tail launch");
+    if ((e = (cyc ? ops->project_persistent_cyclic : ops->project_persistent)(a, int(grid), block, s)) != hipSuccess)
+      return hip_fail(e, "project_batch: persistent launch");
+    if (tail && (e = (cyc ? ops->project_tail_cyclic : ops->project_tail)(a, p->n_cu, s)) != hipSuccess)
+      return hip_fail(e, "project_batch: FP64 tail launch");
     // 2 workgroups of 4 waves per CU: 2,048 flagged configurations per round (blocks without work leave at once)
     if (ctail && (e = ops->check_tail(a, 2 * p->n_cu, s)) != hipSuccess) return hip_fail(e, "project_batch: check tail launch");
   }

@@ -80,13 +80,14 @@ struct QGlob {  // configuration i of a [D][ld] array in global memory
 // In-place right-looking Cholesky of the packed lower triangle G (structural zeros of the
 // factor skipped at compile time). Returns false on a non-positive or non-finite pivot, or a
 // pivot below floor. invd receives 1 / L_ii; kappa the estimate (max L_ii / min L_ii)^2.
-template <class Model, class S>
+template <class Model, class S, uint32_t RM = ~uint32_t(0)>
 __device__ __forceinline__ bool cholesky(S* G, S* invd, S& kappa, S floor) {
   constexpr int M = Model::M;
   bool ok = true;
   S dmin = S(3.0e38), dmax = S(0);
   sfor<0, M>([&](auto K) {
     constexpr int k = decltype(K)::value;
+    if constexpr (((RM >> k) & 1u) != 0) {
     const S d = G[pidx(k, k)];
     ok = ok && (d > floor) && finite_t(d);
     const S r = rsqrt_t(d);
@@ -97,17 +98,18 @@ __device__ __forceinline__ bool cholesky(S* G, S* invd, S& kappa, S floor) {
     dmax = l > dmax ? l : dmax;
     sfor<k + 1, M>([&](auto I) {
       constexpr int i = decltype(I)::value;
-      if constexpr (Model::lnz(i, k)) G[pidx(i, k)] *= r;
+      if constexpr (Model::lnz(i, k) && ((RM >> i) & 1u)) G[pidx(i, k)] *= r;
     });
     sfor<k + 1, M>([&](auto I) {
       constexpr int i = decltype(I)::value;
-      if constexpr (Model::lnz(i, k)) {
+      if constexpr (Model::lnz(i, k) && ((RM >> i) & 1u)) {
         sfor<k + 1, i + 1>([&](auto Jx) {
           constexpr int j = decltype(Jx)::value;
-          if constexpr (Model::lnz(j, k)) G[pidx(i, j)] -= G[pidx(i, k)] * G[pidx(j, k)];
+          if constexpr (Model::lnz(j, k) && ((RM >> j) & 1u)) G[pidx(i, j)] -= G[pidx(i, k)] * G[pidx(j, k)];
         });
       }
     });
+    }
   });
   const S ratio = dmax / dmin;
   kappa = ratio * ratio;
@@ -115,26 +117,30 @@ __device__ __forceinline__ bool cholesky(S* G, S* invd, S& kappa, S floor) {
 }
 
 // Solve L L^T y = b in place (b overwritten by y).
-template <class Model, class S>
+template <class Model, class S, uint32_t RM = ~uint32_t(0)>
 __device__ __forceinline__ void chol_solve(const S* L, const S* invd, S* y) {
   constexpr int M = Model::M;
   sfor<0, M>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    S acc = y[i];
-    sfor<0, i>([&](auto K) {
-      constexpr int k = decltype(K)::value;
-      if constexpr (Model::lnz(i, k)) acc -= L[pidx(i, k)] * y[k];
-    });
-    y[i] = acc * invd[i];
+    if constexpr ((RM >> i) & 1u) {
+      S acc = y[i];
+      sfor<0, i>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        if constexpr (Model::lnz(i, k) && ((RM >> k) & 1u)) acc -= L[pidx(i, k)] * y[k];
+      });
+      y[i] = acc * invd[i];
+    }
   });
   sfor<0, M>([&](auto I) {
     constexpr int i = M - 1 - decltype(I)::value;
-    S acc = y[i];
-    sfor<i + 1, M>([&](auto K) {
-      constexpr int k = decltype(K)::value;
-      if constexpr (Model::lnz(k, i)) acc -= L[pidx(k, i)] * y[k];
-    });
-    y[i] = acc * invd[i];
+    if constexpr ((RM >> i) & 1u) {
+      S acc = y[i];
+      sfor<i + 1, M>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        if constexpr (Model::lnz(k, i) && ((RM >> k) & 1u)) acc -= L[pidx(k, i)] * y[k];
+      });
+      y[i] = acc * invd[i];
+    }
   });
 }
 
@@ -144,23 +150,26 @@ constexpr double kFloorF64 = 1e-24;  // pivot floor relative to the largest Gram
 // One descent step in precision S: dq = J^T (J J^T + lambda I)^-1 rhs (rhs = F for Newton;
 // overwritten). Returns false when the factorisation fails or its condition estimate
 // exceeds cond_thr.
-template <class Model, class S, class Q>
+// RM restricts the system to the rows of one block (cyclic mode).
+template <class Model, class S, uint32_t RM = ~uint32_t(0), class Q>
 __device__ __forceinline__ bool descent_step(const Q& q, S* rhs, const typename Model::template SD<S>& sd,
                                              const Consts& C, double lambda, double cond_thr, S floor_rel, S* dq) {
   constexpr int M = Model::M;
   S G[M * (M + 1) / 2];
-  Model::template gram<S, false>(q, C, sd, G, nullptr, nullptr);
+  Model::template gram<S, false, RM>(q, C, sd, G, nullptr, nullptr);
   S maxd = S(0);
   sfor<0, M>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    G[pidx(i, i)] += S(lambda);
-    maxd = G[pidx(i, i)] > maxd ? G[pidx(i, i)] : maxd;
+    if constexpr ((RM >> i) & 1u) {
+      G[pidx(i, i)] += S(lambda);
+      maxd = G[pidx(i, i)] > maxd ? G[pidx(i, i)] : maxd;
+    }
   });
   S invd[M], kappa;
-  if (!cholesky<Model, S>(G, invd, kappa, floor_rel * maxd)) return false;
+  if (!cholesky<Model, S, RM>(G, invd, kappa, floor_rel * maxd)) return false;
   if (!(double(kappa) <= cond_thr)) return false;
-  chol_solve<Model, S>(G, invd, rhs);
-  Model::template jty<S>(q, C, sd, rhs, dq);
+  chol_solve<Model, S, RM>(G, invd, rhs);
+  Model::template jty<S, RM>(q, C, sd, rhs, dq);
   return true;
 }
 
@@ -208,12 +217,88 @@ __device__ __forceinline__ int newton_iteration(const QLds& q, int& k, const Pro
   return st;
 }
 
+// One iteration of the cyclic mode (Alg. 2, getDescentStep looping over the constraints, Sec.
+// IV-C): the full residual and the convergence test, then one min-norm step per constraint block
+// in order, each taken from the configuration the previous block left; the divergence test
+// (MaxDistance) applies to the displacement of the whole iteration. q0 receives the iterate at
+// the start of the iteration. In FP32 mode a failed factorisation in any block restores that
+// iterate and returns ST_DEFER (the iteration is redone in FP64).
+template <class Model, class S, bool BROAD = false>
+__device__ __forceinline__ int cyclic_iteration(const QLds& q, const QLds& q0, int& k, const ProjArgs& a,
+                                                const Consts& C, double& resid, bool* near = nullptr) {
+  constexpr int D = Model::D, M = Model::M, NB = Model::NBLK;
+  constexpr bool f32 = std::is_same<S, float>::value;
+  typename Model::template SD<S> sd;
+  S F[M];
+  const double n2 = Model::template residual<S, BROAD>(q, C, F, sd, near);
+  resid = sqrt(n2);
+  if (!finite_t(n2)) return ST_NONFINITE;
+  if (n2 < a.tol2) return ST_CONVERGED;
+  if (k >= a.max_iter) return ST_MAX_ITER;
+  for (int c = 0; c < D; ++c) q0.set(c, q.at(c));
+  int st = -1;
+  bool failed = false;
+  sfor<0, NB>([&](auto BI) {
+    constexpr int b = decltype(BI)::value;
+    constexpr uint32_t RM = Model::block_rows_mask(b);
+    if (st < 0 && !failed) {
+      // the first block steps from the iterate whose residual is already in F and sd
+      if constexpr (b > 0) Model::template residual<S, false, RM>(q, C, F, sd);
+      S dq[D];
+      if (!descent_step<Model, S, RM>(q, F, sd, C, a.lambda, f32 ? a.cond_thr : 1e300, f32 ? S(kFloorF32) : S(kFloorF64),
+                                      dq)) {
+        failed = true;
+      } else {
+        double s2 = 0.0;
+        for (int j = 0; j < D; ++j) {
+          const double dj = a.alpha * double(dq[j]);
+          s2 += dj * dj;
+        }
+        if (!finite_t(s2)) st = ST_NONFINITE;
+        else
+          for (int j = 0; j < D; ++j) q.set(j, q.at(j) - a.alpha * double(dq[j]));
+      }
+    }
+  });
+  if (failed) {
+    if constexpr (f32) {
+      for (int c = 0; c < D; ++c) q.set(c, q0.at(c));
+      return ST_DEFER;
+    } else {
+      return ST_SINGULAR;
+    }
+  }
+  if (st >= 0) return st;
+  if (a.max_step > 0.0) {
+    double s2 = 0.0;
+    for (int c = 0; c < D; ++c) {
+      const double t = q.at(c) - q0.at(c);
+      s2 += t * t;
+    }
+    if (s2 > a.max_step * a.max_step) {
+      for (int c = 0; c < D; ++c) q.set(c, q0.at(c));
+      return ST_DIVERGED;
+    }
+  }
+  ++k;
+  return -1;
+}
+
+// One iteration of either mode.
+template <class Model, class S, bool CYC, bool BROAD = false>
+__device__ __forceinline__ int iteration(const QLds& q, const QLds& q0, int& k, const ProjArgs& a, const Consts& C,
+                                         double& resid, bool* near = nullptr) {
+  if constexpr (CYC) return cyclic_iteration<Model, S, BROAD>(q, q0, k, a, C, resid, near);
+  else return newton_iteration<Model, S, BROAD>(q, k, a, C, resid, near);
+}
+
 // Run one configuration to the end with FP64 steps.
-template <class Model>
-__device__ __forceinline__ int finish_fp64(const QLds& q, int& k, const ProjArgs& a, const Consts& C, double& resid) {
+template <class Model, bool CYC = false>
+__device__ __forceinline__ int finish_fp64(const QLds& q, const QLds& q0, int& k, const ProjArgs& a, const Consts& C,
+                                          double& resid) {
   int st;
   do {
-    st = newton_iteration<Model, double>(q, k, a, C, resid);
+    st = iteration<Model, double, CYC>(q, q0, k, a, C, resid);
   } while (st < 0);
   return st;
 }
@@ -283,12 +368,13 @@ __device__ __forceinline__ uint8_t verdict_inline(const QLds& q, const Consts& C
 // every residual pass, so at convergence a configuration with no link near the obstacles is
 // FREE at once, and the others are queued for the exact check (k_check_tail).
 // Dynamic LDS: D * blockDim doubles.
-template <class Model, class IO, class S>
+template <class Model, class IO, class S, bool CYC = false>
 __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
   extern __shared__ double smem[];
   const Consts& C = consts_of(a.P);
   const int dof = C.dof;
   const QLds q = q_lds<Model::D>(smem);
+  const QLds q0 = q_lds<Model::D>(smem + (CYC ? Model::D * blockDim.x : 0));  // cyclic: iterate at iteration start
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n_static) i = a.n;  // not part of the static share
   int k = 0;
@@ -300,7 +386,7 @@ __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
     if (active) {
       double resid;
       bool near = true;
-      int st = newton_iteration<Model, S, fused>(q, k, a, C, resid, &near);
+      int st = iteration<Model, S, CYC, fused>(q, q0, k, a, C, resid, &near);
       if (st == ST_DEFER) {
         const unsigned slot = queue_q<Model>(q, a.defer_count, a.defer_q, a.defer_cap);
         atomicAdd(a.P->fallback_counter, 1ull);
@@ -330,14 +416,18 @@ __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
 }
 
 // Exact collision check of the configurations queued by k_project_persistent: L lanes per
-// configuration (grid-stride over the queue).
+// configuration (grid-stride over the queue). Two instances are launched: a wave per
+// configuration while the queue is short (at most `small` entries: latency-bound, few waves) and
+// a few lanes per configuration when it is long (most configurations near the obstacles); each
+// returns at once when the queue length is not its case.
 // Dynamic LDS: D * blockDim doubles, then the robot spheres and the obstacles (float4 each).
 template <class Model, class IO, int L>
-__global__ void __launch_bounds__(256) k_check_tail(ProjArgs a) {
+__global__ void __launch_bounds__(256) k_check_tail(ProjArgs a, int64_t small) {
   extern __shared__ double smem[];
   const Consts& C = consts_of(a.P);
   const CollConsts& K = coll_of(a.P);
   const int64_t cnt = *a.chk_count;
+  if ((cnt <= small) != (L == 64)) return;                  // the other instance's case
   if (int64_t(blockIdx.x) * blockDim.x / L >= cnt) return;  // no queued work for this block
   const QLds q = q_lds<Model::D>(smem);
   float4* sph = reinterpret_cast<float4*>(smem + Model::D * blockDim.x);
@@ -356,12 +446,13 @@ __global__ void __launch_bounds__(256) k_check_tail(ProjArgs a) {
 // FP64 tail of the persistent variant: the configurations deferred by the FP32 kernel, one per
 // lane (grid-stride over the queue), continued from their stored FP64 iterate with FP64 steps.
 // Dynamic LDS: D * blockDim doubles.
-template <class Model, class IO>
+template <class Model, class IO, bool CYC = false>
 __global__ void __launch_bounds__(64) k_project_tail(ProjArgs a) {
   extern __shared__ double smem[];
   const Consts& C = consts_of(a.P);
   const int dof = C.dof;
   const QLds q = q_lds<Model::D>(smem);
+  const QLds q0 = q_lds<Model::D>(smem + (CYC ? Model::D * blockDim.x : 0));
   const int64_t cnt = *a.defer_count;
   for (int64_t slot = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; slot < cnt;
        slot += int64_t(gridDim.x) * blockDim.x) {
@@ -369,7 +460,7 @@ __global__ void __launch_bounds__(64) k_project_tail(ProjArgs a) {
     int k = a.defer_ik[2 * slot + 1];
     load_queued<Model, IO>(a.defer_q, a.defer_cap, slot, q);
     double resid;
-    const int st = finish_fp64<Model>(q, k, a, C, resid);
+    const int st = finish_fp64<Model, CYC>(q, q0, k, a, C, resid);
     store_result<Model, IO>(a, dof, i, q, st, k, resid);
     if (a.verdict) a.verdict[i] = verdict_inline<Model>(q, C, a, st);
   }
@@ -396,7 +487,7 @@ __global__ void __launch_bounds__(64) k_project_plain(ProjArgs a) {
     if (st >= 0) break;
     if (st == ST_DEFER) {  // same rule as the persistent variant: FP64 steps from here on
       atomicAdd(a.P->fallback_counter, 1ull);
-      st = finish_fp64<Model>(q, k, a, C, resid);
+      st = finish_fp64<Model>(q, q, k, a, C, resid);
       near = true;
       break;
     }

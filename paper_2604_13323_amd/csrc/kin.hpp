@@ -144,6 +144,7 @@ struct KInfo {
     for (int k = 0; k < b; ++k) r += brows(k);
     return r;
   }
+  static constexpr uint32_t brmask(int b) { return ((uint32_t(1) << brows(b)) - 1u) << brow0(b); }
   static constexpr int flink(int f) { return Topo::frame_link[f]; }
   // 0: block b does not depend on joint j; +-1: it does (sign for REL).
   static constexpr int dep(int b, int j) {
@@ -235,6 +236,12 @@ struct Kin {
   static constexpr int NJ = Topo::NJ, NB = Topo::NB, NF = Topo::NF, M = Topo::M, D = Topo::NJ;
   static constexpr int family = Topo::family;
   static constexpr bool broad_in_residual = true;  // residual<S, true> reports link-near-obstacles
+  static constexpr int NBLK = NB;                  // constraint blocks (the cyclic mode steps them in order)
+  static constexpr uint32_t ALL = ~uint32_t(0);
+  static constexpr uint32_t block_rows_mask(int b) { return KI::brmask(b); }
+  template <uint32_t RM>
+  static constexpr bool sel(int b) { return (KI::brmask(b) & RM) != 0; }
+  static constexpr bool in_rows(uint32_t rm, int r) { return (rm >> r) & 1u; }
   static constexpr bool lnz(int i, int k) { return KI::LP.nz[i][k]; }
 
   // Per-iteration data from the residual pass used by the Jacobian passes.
@@ -417,7 +424,8 @@ struct Kin {
   // step data for the Jacobian passes. With BROAD, the pass also sets `near` when the
   // bounding sphere of some link reaches into the box around all obstacles (the first test of
   // the collision broad phase, on the frames this pass computes anyway).
-  template <class S, bool BROAD = false, class Q>
+  // RM selects the rows (blocks) to evaluate; the other entries of F and sd are left untouched.
+  template <class S, bool BROAD = false, uint32_t RM = ALL, class Q>
   static __device__ __forceinline__ double residual(const Q& q, const Consts& P, S* F, SD<S>& sd,
                                                     bool* near = nullptr) {
     Rig<double> Fr[NF];
@@ -453,12 +461,12 @@ struct Kin {
       }
       sfor<0, NB>([&](auto BI) {
         constexpr int b = decltype(BI)::value;
-        if constexpr (KI::complete_link(b) == j) block_rows<S, b>(Fr, P, F, n2, sd);
+        if constexpr (KI::complete_link(b) == j && sel<RM>(b)) block_rows<S, b>(Fr, P, F, n2, sd);
       });
     });
     sfor<0, NB>([&](auto BI) {
       constexpr int b = decltype(BI)::value;
-      if constexpr (Topo::btype[b] == B_COM) {
+      if constexpr (Topo::btype[b] == B_COM && sel<RM>(b)) {
         constexpr int r0 = KI::brow0(b);
         const TP<double>& Pd = after_cp(P.d, cm[1]);
         const double e0 = cm[0] * Pd.inv_total_mass - Pd.target[b][0];
@@ -474,7 +482,7 @@ struct Kin {
 
   // Structurally nonzero entries of Jacobian column j (other rows untouched). Qr is the running
   // prefix sum of m_l c_l over the links before j and is advanced past link j.
-  template <class S, int j>
+  template <class S, int j, uint32_t RM = ALL>
   static __device__ __forceinline__ void column(const Rig<S>& X, const JP<S>& jp, const TP<S>& T, const SD<S>& sd,
                                                 S* Qr, S* col) {
     constexpr int ax = Topo::axis[j];
@@ -483,7 +491,7 @@ struct Kin {
     const S* o = X.p;
     sfor<0, NB>([&](auto BI) {
       constexpr int b = decltype(BI)::value;
-      constexpr int sg = KI::dep(b, j);
+      constexpr int sg = sel<RM>(b) ? KI::dep(b, j) : 0;
       constexpr int t = Topo::btype[b];
       constexpr int r0 = KI::brow0(b);
       if constexpr (sg != 0 && (t == B_POSE || t == B_REL)) {
@@ -532,28 +540,30 @@ struct Kin {
   }
 
   // Gram pass: G += J_j J_j^T over all columns (packed lower triangle), optionally v = J g.
-  template <class S, bool WITH_V, class Q>
+  template <class S, bool WITH_V, uint32_t RM = ALL, class Q>
   static __device__ __forceinline__ void gram(const Q& q, const Consts& P, const SD<S>& sd, S* G, const S* g, S* v) {
     const TP<S>& T = tp<S>(P);
     sfor<0, M>([&](auto I) {
       constexpr int i = decltype(I)::value;
-      sfor<0, i + 1>([&](auto K) {
-        constexpr int k = decltype(K)::value;
-        if constexpr (lnz(i, k)) G[pidx(i, k)] = S(0);
-      });
-      if constexpr (WITH_V) v[i] = S(0);
+      if constexpr (in_rows(RM, i)) {
+        sfor<0, i + 1>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          if constexpr (lnz(i, k) && in_rows(RM, k)) G[pidx(i, k)] = S(0);
+        });
+        if constexpr (WITH_V) v[i] = S(0);
+      }
     });
     S Qr[3] = {S(0), S(0), S(0)};
     fk<S>(q, T, [&](auto J, const Rig<S>& X, const JP<S>& jp) {
       constexpr int j = decltype(J)::value;
       S col[M];
-      column<S, j>(X, jp, T, sd, Qr, col);
+      column<S, j, RM>(X, jp, T, sd, Qr, col);
       sfor<0, M>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        if constexpr (KI::rdep(i, j)) {
+        if constexpr (KI::rdep(i, j) && in_rows(RM, i)) {
           sfor<0, i + 1>([&](auto K) {
             constexpr int k = decltype(K)::value;
-            if constexpr (KI::rdep(k, j)) G[pidx(i, k)] += col[i] * col[k];
+            if constexpr (KI::rdep(k, j) && in_rows(RM, k)) G[pidx(i, k)] += col[i] * col[k];
           });
           if constexpr (WITH_V) v[i] += col[i] * g[j];
         }
@@ -562,18 +572,18 @@ struct Kin {
   }
 
   // J^T y pass.
-  template <class S, class Q>
+  template <class S, uint32_t RM = ALL, class Q>
   static __device__ __forceinline__ void jty(const Q& q, const Consts& P, const SD<S>& sd, const S* y, S* out) {
     const TP<S>& T = tp<S>(P);
     S Qr[3] = {S(0), S(0), S(0)};
     fk<S>(q, T, [&](auto J, const Rig<S>& X, const JP<S>& jp) {
       constexpr int j = decltype(J)::value;
       S col[M];
-      column<S, j>(X, jp, T, sd, Qr, col);
+      column<S, j, RM>(X, jp, T, sd, Qr, col);
       S acc = S(0);
       sfor<0, M>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        if constexpr (KI::rdep(i, j)) acc += col[i] * y[i];
+        if constexpr (KI::rdep(i, j) && in_rows(RM, i)) acc += col[i] * y[i];
       });
       out[j] = acc;
     });
@@ -658,7 +668,9 @@ struct Kin {
       constexpr int l = decltype(J)::value;
       if constexpr (Topo::may_have_spheres(l)) {
         const float4 bs = K.link_bs[l];
-        if (bs.w >= 0.f) {
+        // a group that already has its verdict skips the remaining links
+        const bool done = ((uint64_t(__ballot(hit)) >> shift) & gmask) != 0;
+        if (bs.w >= 0.f && !done) {
           const float lc[3] = {bs.x, bs.y, bs.z};
           float cb[3];
           matvec3(X.R, lc, cb);

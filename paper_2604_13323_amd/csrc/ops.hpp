@@ -12,6 +12,8 @@ struct FamilyOps {
   int f64;      // 1: FP64 mode tables (IO = double, S = double)
   int dof_max;  // compiled D (padded for the linear family)
   hipError_t (*project_persistent)(const ProjArgs& a, int grid, int block, hipStream_t s);
+  hipError_t (*project_persistent_cyclic)(const ProjArgs& a, int grid, int block, hipStream_t s);
+  hipError_t (*project_tail_cyclic)(const ProjArgs& a, int grid, hipStream_t s);  // FP32 mode only
   hipError_t (*project_plain)(const ProjArgs& a, hipStream_t s);
   hipError_t (*project_tail)(const ProjArgs& a, int grid, hipStream_t s);  // FP32 mode only
   hipError_t (*check_tail)(const ProjArgs& a, int grid, hipStream_t s);
@@ -26,13 +28,23 @@ struct FamilyOps {
 inline unsigned blocks_for(int64_t n, int block) { return unsigned((n + block - 1) / block); }
 
 constexpr int kCheckLanes = 4;       // check_batch: lanes per configuration
-constexpr int kTailCheckLanes = 64;  // exact check of the flagged configurations of a projection (a wave each)
+constexpr int kTailCheckLanesLong = 4;  // exact check of a long queue of flagged configurations
 
 template <class Model, class IO, class S>
 struct OpsImpl {
   static size_t lds_bytes(int block) { return size_t(Model::D) * sizeof(double) * size_t(block); }
   static hipError_t project_persistent(const ProjArgs& a, int grid, int block, hipStream_t s) {
     hipLaunchKernelGGL((k_project_persistent<Model, IO, S>), dim3(grid), dim3(block), lds_bytes(block), s, a);
+    return hipGetLastError();
+  }
+  // cyclic mode (models with several constraint blocks): a second LDS tile holds the iterate at
+  // the start of each iteration
+  static hipError_t project_persistent_cyclic(const ProjArgs& a, int grid, int block, hipStream_t s) {
+    hipLaunchKernelGGL((k_project_persistent<Model, IO, S, true>), dim3(grid), dim3(block), 2 * lds_bytes(block), s, a);
+    return hipGetLastError();
+  }
+  static hipError_t project_tail_cyclic(const ProjArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_project_tail<Model, IO, true>), dim3(grid), dim3(64), 2 * lds_bytes(64), s, a);
     return hipGetLastError();
   }
   static hipError_t project_plain(const ProjArgs& a, hipStream_t s) {
@@ -45,7 +57,11 @@ struct OpsImpl {
   }
   static hipError_t check_tail(const ProjArgs& a, int grid, hipStream_t s) {
     const size_t lds = lds_bytes(256) + size_t(a.n_sph + a.n_obs) * 16;
-    hipLaunchKernelGGL((k_check_tail<Model, IO, kTailCheckLanes>), dim3(grid), dim3(256), lds, s, a);
+    const int64_t small = int64_t(grid) * 4;  // one pass of the grid at a wave per configuration
+    hipLaunchKernelGGL((k_check_tail<Model, IO, 64>), dim3(grid), dim3(256), lds, s, a, small);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_check_tail<Model, IO, kTailCheckLanesLong>), dim3(4 * grid), dim3(256), lds, s, a, small);
     return hipGetLastError();
   }
   static hipError_t vjp_tail(const VjpArgs& a, int grid, hipStream_t s) {
@@ -82,6 +98,14 @@ struct OpsImpl {
     o.f64 = std::is_same<S, double>::value ? 1 : 0;
     o.dof_max = Model::D;
     o.project_persistent = &project_persistent;
+    // with a single constraint block the cyclic mode is the stacked one
+    if constexpr (Model::NBLK > 1) {
+      o.project_persistent_cyclic = &project_persistent_cyclic;
+      o.project_tail_cyclic = std::is_same<S, float>::value ? &project_tail_cyclic : nullptr;
+    } else {
+      o.project_persistent_cyclic = &project_persistent;
+      o.project_tail_cyclic = std::is_same<S, float>::value ? &project_tail : nullptr;
+    }
     o.project_plain = &project_plain;
     o.project_tail = std::is_same<S, float>::value ? &project_tail : nullptr;
     o.check_tail = Model::broad_in_residual ? &check_tail : nullptr;

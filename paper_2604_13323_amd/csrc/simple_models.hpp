@@ -43,10 +43,13 @@ struct SphereModel {
   static constexpr int family = 0;
   static constexpr bool broad_in_residual = false;
   static constexpr int D = 3, M = 1;
+  static constexpr int NBLK = 1;
+  static constexpr uint32_t ALL = ~uint32_t(0);
+  static constexpr uint32_t block_rows_mask(int) { return ALL; }
   static constexpr bool lnz(int, int) { return true; }
   template <class S> struct SD { S dummy; };
 
-  template <class S, bool BROAD = false, class Q>
+  template <class S, bool BROAD = false, uint32_t RM = ~uint32_t(0), class Q>
   static __device__ __forceinline__ double residual(const Q& q, const Consts&, S* F, SD<S>&, bool* = nullptr) {
     const double a = q.at(0), b = q.at(1), c = q.at(2);
     const double f = a * a + b * b + c * c - 1.0;
@@ -54,13 +57,13 @@ struct SphereModel {
     return f * f;
   }
   // J = 2 q^T, so J J^T = 4 q.q and J g = 2 q.g
-  template <class S, bool WITH_V, class Q>
+  template <class S, bool WITH_V, uint32_t RM = ~uint32_t(0), class Q>
   static __device__ __forceinline__ void gram(const Q& q, const Consts&, const SD<S>&, S* G, const S* g, S* v) {
     const S a = S(q.at(0)), b = S(q.at(1)), c = S(q.at(2));
     G[0] = S(4) * (a * a + b * b + c * c);
     if constexpr (WITH_V) v[0] = S(2) * (a * g[0] + b * g[1] + c * g[2]);
   }
-  template <class S, class Q>
+  template <class S, uint32_t RM = ~uint32_t(0), class Q>
   static __device__ __forceinline__ void jty(const Q& q, const Consts&, const SD<S>&, const S* y, S* out) {
     for (int k = 0; k < 3; ++k) out[k] = S(2) * S(q.at(k)) * y[0];
   }
@@ -97,10 +100,13 @@ struct LinearModel {
   static constexpr int family = 1;
   static constexpr bool broad_in_residual = false;
   static constexpr int D = LIN_D, M = LIN_M;
+  static constexpr int NBLK = 1;
+  static constexpr uint32_t ALL = ~uint32_t(0);
+  static constexpr uint32_t block_rows_mask(int) { return ALL; }
   static constexpr bool lnz(int, int) { return true; }
   template <class S> struct SD { S dummy; };
 
-  template <class S, bool BROAD = false, class Q>
+  template <class S, bool BROAD = false, uint32_t RM = ~uint32_t(0), class Q>
   static __device__ __forceinline__ double residual(const Q& q, const Consts& P, S* F, SD<S>&, bool* = nullptr) {
     double qv[D], n2 = 0.0;
     for (int c = 0; c < D; ++c) qv[c] = q.at(c);
@@ -113,7 +119,7 @@ struct LinearModel {
     }
     return n2;
   }
-  template <class S, bool WITH_V, class Q>
+  template <class S, bool WITH_V, uint32_t RM = ~uint32_t(0), class Q>
   static __device__ __forceinline__ void gram(const Q&, const Consts& P, const SD<S>&, S* G, const S* g, S* v) {
     const TP<S>& T = tp<S>(P);
     for (int i = 0; i < M; ++i) {
@@ -129,7 +135,7 @@ struct LinearModel {
       }
     }
   }
-  template <class S, class Q>
+  template <class S, uint32_t RM = ~uint32_t(0), class Q>
   static __device__ __forceinline__ void jty(const Q&, const Consts& P, const SD<S>&, const S* y, S* out) {
     const TP<S>& T = tp<S>(P);
     for (int c = 0; c < D; ++c) {

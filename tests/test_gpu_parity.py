@@ -33,9 +33,10 @@ def run_gpu(mc, sc, q, tol, max_iter, dtype=torch.float32, **kw):
     return G, r
 
 
-def compare(P, q, r, tol, max_iter, qtol, require_iters=True, min_agree=0.98, max_band=0.05, max_step=0.0):
-    qo, st, it, rs = P.project(q, tol=tol, max_iter=max_iter, max_step=max_step)
-    band = band_mask(P, q, tol, max_iter, max_step)
+def compare(P, q, r, tol, max_iter, qtol, require_iters=True, min_agree=0.98, max_band=0.05, max_step=0.0,
+            mode="stacked"):
+    qo, st, it, rs = P.project(q, tol=tol, max_iter=max_iter, max_step=max_step, mode=mode)
+    band = band_mask(P, q, tol, max_iter, max_step, mode)
     gst = from_dev(r.status).astype(int)
     git = from_dev(r.iters).astype(int)
     gq = from_dev(r.q).T
@@ -180,6 +181,52 @@ def test_projection_parity_fp64(mc, name):
     G, r = run_gpu(mc, sc, q, tol, mi, torch.float64, geo_offsets=offs)
     stats = compare(P, q, r, tol, mi, 1e-9, require_iters=True, max_band=MAX_BAND[name])
     print(name, stats)
+
+
+@pytest.mark.parametrize("dt,qtol", [(torch.float32, 1e-4), (torch.float64, 1e-9)])
+def test_cyclic_mode_parity_humanoid(mc, dt, qtol):
+    """Cyclic mode (one step per constraint block, in order) on the 36-DoF humanoid, whose four
+    blocks (two feet poses, hands relative pose, CoM) each get their own Gram and Cholesky,
+    against the oracle's cyclic mode."""
+    sc, P, q, offs, tol, mi = config_inputs("c3", small=True)
+    # alternating steps converge linearly on this humanoid (the blocks share the floating base):
+    # at the benchmark's 1e-6 most paths need more than 40 cycles, at 1e-3 they converge in 1-9
+    G, r = run_gpu(mc, sc, q, 1e-3, mi, dtype=dt, mode="cyclic")
+    info = compare(P, q, r, 1e-3, mi, qtol, require_iters=dt == torch.float64, mode="cyclic")
+    assert info["conv"] > 0.99
+    # five full cycles at tol 1e-6 (every path still running): the iterates agree step for step
+    G, r = run_gpu(mc, sc, q, 1e-6, 5, dtype=dt, mode="cyclic")
+    qo, st, it, rs = P.project(q, tol=1e-6, max_iter=5, mode="cyclic")
+    gst = from_dev(r.status).astype(int)
+    run = (st == MAXIT) & (gst == MAXIT)
+    assert run.mean() > 0.9
+    err = np.abs(from_dev(r.q).T[run] - qo[run]).max()
+    assert err <= qtol, err
+
+
+def test_cyclic_mode_forced_fp64_tail_and_divergence(mc):
+    """Cyclic mode with every configuration sent to the FP64 tail (threshold below 1) equals FP64
+    mode; with a small max_step the diverged configurations keep their input (the test applies to
+    the whole iteration)."""
+    sc, P, q, offs, tol, mi = config_inputs("c3", small=True, max_geo=8)
+    tol = 1e-3
+    G = gpu_problem(mc, sc)
+    q32 = to_dev(q, torch.float32)
+    rf = G.project(q32, tol=tol, max_iter=mi, mode="cyclic", cond=0.5)
+    r64 = G.project(q32.double(), tol=tol, max_iter=mi, mode="cyclic")
+    rd = G.project(q32.double(), tol=tol, max_iter=mi, mode="cyclic", max_step=1e-3)
+    torch.cuda.synchronize()
+    assert torch.equal(rf.status, r64.status) and torch.equal(rf.iters, r64.iters)
+    assert torch.equal(rf.q, r64.q.float())
+    qin = from_dev(q32.double()).T
+    compare(P, qin, rd, tol, mi, 1e-9, max_step=1e-3, mode="cyclic", max_band=0.2)
+    qo, st, it, rs = P.project(qin, tol=tol, max_iter=mi, mode="cyclic", max_step=1e-3)
+    band = band_mask(P, qin, tol, mi, 1e-3, "cyclic")
+    div = (from_dev(rd.status).astype(int) == 3) & (st == 3) & ~band
+    assert div.any()
+    # a diverged configuration stays where its last iteration started
+    np.testing.assert_allclose(from_dev(rd.q).T[div], qo[div], atol=1e-9)
+    np.testing.assert_array_equal(from_dev(rd.iters).astype(int)[div], it[div])
 
 
 @pytest.mark.parametrize("dt,qtol", [(torch.float32, 1e-4), (torch.float64, 1e-9)])

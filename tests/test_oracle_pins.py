@@ -506,3 +506,76 @@ def test_pose_translation_rows_rotated_target(oracle_mod):
         p = np.array([0.3 * math.cos(q0), 0.3 * math.sin(q0), 0.0])
         np.testing.assert_allclose(F[:3], Rr.T @ (p - pref), atol=1e-14)
         np.testing.assert_allclose(F[3:], [0, 0, q0 - th], atol=1e-14)
+
+
+# ---------------------------------------------------------------- cyclic mode (Sec. IV-C, Alg. 2)
+def _two_sphere_block_scene():
+    import dataclasses
+    sc = S.sphere_scene(0)
+    return dataclasses.replace(sc, m=2, blocks=[S.Block(S.BLK_SPHERE), S.Block(S.BLK_SPHERE)])
+
+
+def test_cyclic_two_sphere_blocks_is_two_heron_steps_per_iteration(oracle_mod):
+    """Two copies of ||q||^2 - 1 as separate blocks: each block's min-norm step is one Heron step
+    r -> (r + 1/r)/2 on the radius, so a cyclic iteration takes two of them. The stacked system has
+    a rank-1 Jacobian (two equal rows) and is SINGULAR. Expected counts from the exact recurrence
+    in rationals; convergence is ||F|| = sqrt(2) |r^2 - 1| < tol."""
+    from fractions import Fraction
+    P = prob(_two_sphere_block_scene())
+    u = np.array([0.48, -0.6, 0.64])
+    tol = 1e-6
+    for r0 in (0.9, 0.5, 0.1, 3.0):
+        r, k = Fraction(r0), 0
+        while not (math.sqrt(2) * abs(float(r * r - 1)) < tol):
+            for _ in range(2):
+                r = (r + 1 / r) / 2
+            k += 1
+        qo, st, it, rs = P.project((r0 * u)[None], tol=tol, max_iter=50, mode="cyclic")
+        assert st[0] == CONV and it[0] == k, (r0, st[0], it[0], k)
+        np.testing.assert_allclose(qo[0], float(r) * u, rtol=1e-13)
+        qs, ss, _, _ = P.project((r0 * u)[None], tol=tol, max_iter=50)
+        assert ss[0] == SING
+
+
+def test_cyclic_split_rows_converge_to_analytic_ik(oracle_mod):
+    """Planar 2R arm with the tip's x and y rows as two separate blocks: the cyclic iteration ends
+    on the analytic inverse-kinematics solution (one of the two elbow branches)."""
+    import dataclasses
+    l1, l2, tgt = 0.7, 0.5, (0.55, 0.62)
+    sc = S.planar2_scene(l1, l2, tgt)
+    bx = dataclasses.replace(sc.blocks[0], mask=0x1)
+    by = dataclasses.replace(sc.blocks[0], mask=0x2)
+    P = prob(dataclasses.replace(sc, blocks=[bx, by]))
+    x, y = tgt
+    c2 = (x * x + y * y - l1 * l1 - l2 * l2) / (2 * l1 * l2)
+    sols = []
+    for sgn in (1, -1):
+        q2 = sgn * math.acos(c2)
+        q1 = math.atan2(y, x) - math.atan2(l2 * math.sin(q2), l1 + l2 * math.cos(q2))
+        sols.append(np.array([q1, q2]))
+    starts = np.array([[0.3, 0.9], [1.2, -0.8], [0.5, 1.5], [0.0, -1.2]])
+    qo, st, it, rs = P.project(starts, tol=1e-12, max_iter=500, mode="cyclic")
+    assert (st == CONV).all()
+    for q in qo:
+        wrapped = [np.abs((q - s + np.pi) % (2 * np.pi) - np.pi).max() for s in sols]
+        assert min(wrapped) < 1e-9, (q, sols)
+
+
+def test_cyclic_divergence_leaves_the_iterate(oracle_mod):
+    """The MaxDistance test applies to the whole iteration: from r = 0.1 the first cycle moves the
+    point by about 2.9 > 1, so the projection stops as DIVERGED with the input untouched."""
+    P = prob(_two_sphere_block_scene())
+    q0 = np.array([[0.1, 0.0, 0.0]])
+    qo, st, it, rs = P.project(q0, tol=1e-6, max_iter=50, max_step=1.0, mode="cyclic")
+    assert st[0] == DIV and it[0] == 0
+    np.testing.assert_array_equal(qo, q0)
+
+
+def test_cyclic_with_one_block_is_the_stacked_iteration(oracle_mod):
+    """With a single constraint block a cycle is one step of the stacked system."""
+    P = prob(S.sphere_scene(0))
+    q, _ = S.sphere_workload(0, n_seg=16)
+    a = P.project(q, tol=1e-6, max_iter=50)
+    b = P.project(q, tol=1e-6, max_iter=50, mode="cyclic")
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
