@@ -50,8 +50,8 @@ struct ProjArgs {
   int32_t* defer_ik;
   double* defer_q;
   int64_t defer_cap;
-  // Fused collision check: converged configurations whose broad-phase test (done inside the
-  // last residual pass) found a link near the obstacles are queued here for the exact check
+  // Fused collision check: converged configurations whose broad-phase test found a link near
+  // the obstacles are queued here for the exact check
   // (index in chk_idx[s], FP64 configuration at chk_q[c * defer_cap + s]).
   unsigned int* chk_count;
   int32_t* chk_idx;
@@ -193,13 +193,12 @@ __device__ __forceinline__ int apply_step(const QLds& q, const S* dq, const Proj
 // when the FP32 factorisation fails or its condition estimate exceeds the threshold (the
 // iteration is then redone with an FP64 step, and the configuration stays in FP64 until it
 // ends).
-template <class Model, class S, bool BROAD = false>
-__device__ __forceinline__ int newton_iteration(const QLds& q, int& k, const ProjArgs& a, const Consts& C, double& resid,
-                                                bool* near = nullptr) {
+template <class Model, class S>
+__device__ __forceinline__ int newton_iteration(const QLds& q, int& k, const ProjArgs& a, const Consts& C, double& resid) {
   constexpr int D = Model::D, M = Model::M;
   typename Model::template SD<S> sd;
   S F[M];
-  const double n2 = Model::template residual<S, BROAD>(q, C, F, sd, near);
+  const double n2 = Model::template residual<S>(q, C, F, sd);
   resid = sqrt(n2);
   if (!finite_t(n2)) return ST_NONFINITE;
   if (n2 < a.tol2) return ST_CONVERGED;
@@ -223,14 +222,14 @@ __device__ __forceinline__ int newton_iteration(const QLds& q, int& k, const Pro
 // (MaxDistance) applies to the displacement of the whole iteration. q0 receives the iterate at
 // the start of the iteration. In FP32 mode a failed factorisation in any block restores that
 // iterate and returns ST_DEFER (the iteration is redone in FP64).
-template <class Model, class S, bool BROAD = false>
+template <class Model, class S>
 __device__ __forceinline__ int cyclic_iteration(const QLds& q, const QLds& q0, int& k, const ProjArgs& a,
-                                                const Consts& C, double& resid, bool* near = nullptr) {
+                                                const Consts& C, double& resid) {
   constexpr int D = Model::D, M = Model::M, NB = Model::NBLK;
   constexpr bool f32 = std::is_same<S, float>::value;
   typename Model::template SD<S> sd;
   S F[M];
-  const double n2 = Model::template residual<S, BROAD>(q, C, F, sd, near);
+  const double n2 = Model::template residual<S>(q, C, F, sd);
   resid = sqrt(n2);
   if (!finite_t(n2)) return ST_NONFINITE;
   if (n2 < a.tol2) return ST_CONVERGED;
@@ -243,7 +242,7 @@ __device__ __forceinline__ int cyclic_iteration(const QLds& q, const QLds& q0, i
     constexpr uint32_t RM = Model::block_rows_mask(b);
     if (st < 0 && !failed) {
       // the first block steps from the iterate whose residual is already in F and sd
-      if constexpr (b > 0) Model::template residual<S, false, RM>(q, C, F, sd);
+      if constexpr (b > 0) Model::template residual<S, RM>(q, C, F, sd);
       S dq[D];
       if (!descent_step<Model, S, RM>(q, F, sd, C, a.lambda, f32 ? a.cond_thr : 1e300, f32 ? S(kFloorF32) : S(kFloorF64),
                                       dq)) {
@@ -285,11 +284,11 @@ __device__ __forceinline__ int cyclic_iteration(const QLds& q, const QLds& q0, i
 }
 
 // One iteration of either mode.
-template <class Model, class S, bool CYC, bool BROAD = false>
+template <class Model, class S, bool CYC>
 __device__ __forceinline__ int iteration(const QLds& q, const QLds& q0, int& k, const ProjArgs& a, const Consts& C,
-                                         double& resid, bool* near = nullptr) {
-  if constexpr (CYC) return cyclic_iteration<Model, S, BROAD>(q, q0, k, a, C, resid, near);
-  else return newton_iteration<Model, S, BROAD>(q, k, a, C, resid, near);
+                                         double& resid) {
+  if constexpr (CYC) return cyclic_iteration<Model, S>(q, q0, k, a, C, resid);
+  else return newton_iteration<Model, S>(q, k, a, C, resid);
 }
 
 // Run one configuration to the end with FP64 steps.
@@ -364,9 +363,10 @@ __device__ __forceinline__ uint8_t verdict_inline(const QLds& q, const Consts& C
 
 // Persistent projection kernel: a grid of resident waves pulls configurations from a device
 // work queue (atomic counter), one per lane, and refills a lane when its configuration ends.
-// With a verdict array the collision check is fused: tree models run the broad-phase test in
-// every residual pass, so at convergence a configuration with no link near the obstacles is
-// FREE at once, and the others are queued for the exact check (k_check_tail).
+// With a verdict array the collision check is fused: tree models walk the converged
+// configuration's link bounds once more in FP32 and test them against the box around the
+// obstacles, so a configuration with no link near the obstacles is FREE at once, and the others
+// are queued for the exact check (k_check_tail).
 // Dynamic LDS: D * blockDim doubles.
 template <class Model, class IO, class S, bool CYC = false>
 __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
@@ -386,7 +386,7 @@ __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
     if (active) {
       double resid;
       bool near = true;
-      int st = iteration<Model, S, CYC, fused>(q, q0, k, a, C, resid, &near);
+      int st = iteration<Model, S, CYC>(q, q0, k, a, C, resid);
       if (st == ST_DEFER) {
         const unsigned slot = queue_q<Model>(q, a.defer_count, a.defer_q, a.defer_cap);
         atomicAdd(a.P->fallback_counter, 1ull);
@@ -396,6 +396,8 @@ __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
         store_result<Model, IO>(a, dof, i, q, st, k, resid);
         if (a.verdict) {
           if constexpr (fused) {
+            // broad phase on the converged configuration (an FP32 walk of the link bounds)
+            if (a.check && st == ST_CONVERGED) near = Model::broad_flag(q, C);
             if (a.check && st == ST_CONVERGED && near) {
               a.chk_idx[queue_q<Model>(q, a.chk_count, a.chk_q, a.defer_cap)] = int32_t(i);
             } else {
@@ -483,7 +485,7 @@ __global__ void __launch_bounds__(64) k_project_plain(ProjArgs a) {
   constexpr bool fused = Model::broad_in_residual;
   bool near = true;
   for (;;) {
-    st = newton_iteration<Model, S, fused>(q, k, a, C, resid, &near);
+    st = newton_iteration<Model, S>(q, k, a, C, resid);
     if (st >= 0) break;
     if (st == ST_DEFER) {  // same rule as the persistent variant: FP64 steps from here on
       atomicAdd(a.P->fallback_counter, 1ull);
@@ -495,6 +497,7 @@ __global__ void __launch_bounds__(64) k_project_plain(ProjArgs a) {
   store_result<Model, IO>(a, dof, i, q, st, k, resid);
   if (a.verdict) {
     // same broad-phase rule as the persistent variant; the exact check runs in-line
+    if (fused && a.check && st == ST_CONVERGED) near = Model::broad_flag(q, C);
     const bool skip = fused && a.check && st == ST_CONVERGED && !near;
     a.verdict[a.base + i] = skip ? uint8_t(V_FREE) : verdict_inline<Model>(q, C, a, st);
   }

@@ -235,7 +235,7 @@ struct Kin {
   using KI = KInfo<Topo>;
   static constexpr int NJ = Topo::NJ, NB = Topo::NB, NF = Topo::NF, M = Topo::M, D = Topo::NJ;
   static constexpr int family = Topo::family;
-  static constexpr bool broad_in_residual = true;  // residual<S, true> reports link-near-obstacles
+  static constexpr bool broad_in_residual = true;  // broad_flag() tests the link bounds against the obstacle box
   static constexpr int NBLK = NB;                  // constraint blocks (the cyclic mode steps them in order)
   static constexpr uint32_t ALL = ~uint32_t(0);
   static constexpr uint32_t block_rows_mask(int b) { return KI::brmask(b); }
@@ -421,30 +421,15 @@ struct Kin {
   }
 
   // Residual pass in FP64: returns ||F(q)||^2 (FP64); F in the step precision S and the
-  // step data for the Jacobian passes. With BROAD, the pass also sets `near` when the
-  // bounding sphere of some link reaches into the box around all obstacles (the first test of
-  // the collision broad phase, on the frames this pass computes anyway).
-  // RM selects the rows (blocks) to evaluate; the other entries of F and sd are left untouched.
-  template <class S, bool BROAD = false, uint32_t RM = ALL, class Q>
-  static __device__ __forceinline__ double residual(const Q& q, const Consts& P, S* F, SD<S>& sd,
-                                                    bool* near = nullptr) {
+  // step data for the Jacobian passes. RM selects the rows (blocks) to evaluate; the other
+  // entries of F and sd are left untouched.
+  template <class S, uint32_t RM = ALL, class Q>
+  static __device__ __forceinline__ double residual(const Q& q, const Consts& P, S* F, SD<S>& sd) {
     Rig<double> Fr[NF];
     double cm[3] = {0.0, 0.0, 0.0};
     double n2 = 0.0;
-    int nr = 0;
     fk<double>(q, P.d, [&](auto J, const Rig<double>& X, const JP<double>& jp) {
       constexpr int j = decltype(J)::value;
-      if constexpr (BROAD && Topo::may_have_spheres(j)) {
-        const TP<double>& Pb = after_cp(P.d, X.p[2]);
-        const float4 blo = make_float4(Pb.obs_lo[0], Pb.obs_lo[1], Pb.obs_lo[2], 0.f);
-        const float4 bhi = make_float4(Pb.obs_hi[0], Pb.obs_hi[1], Pb.obs_hi[2], 0.f);
-        const float* bs = Pb.lbs[j];
-        float c[3];
-        for (int k = 0; k < 3; ++k)
-          c[k] = float(X.p[k] + X.R[3 * k] * bs[0] + X.R[3 * k + 1] * bs[1] + X.R[3 * k + 2] * bs[2]);
-        nr |= (bs[3] >= 0.f) & (box_dist2(c, blo, bhi) <= bs[3] * bs[3]);
-        asm volatile("" : "+v"(nr));  // pins the test to this point of the walk (no sinking)
-      }
       sfor<0, NF>([&](auto FI) {
         constexpr int f = decltype(FI)::value;
         if constexpr (Topo::frame_link[f] == j) frame_pose<double>(X, P.d, f, Fr[f]);
@@ -476,7 +461,6 @@ struct Kin {
         n2 += e0 * e0 + e1 * e1;
       }
     });
-    if constexpr (BROAD) *near = nr != 0;
     return n2;
   }
 
@@ -713,6 +697,27 @@ struct Kin {
       }
     });
     return ((uint64_t(__ballot(hit)) >> shift) & gmask) != 0;
+  }
+
+  // Broad-phase flag of one configuration: does the bounding sphere of some link reach into the
+  // box around all obstacles? (FP32 walk; the link bounds and the box are inflated by a margin
+  // that covers FP32 rounding, so a clear flag proves the configuration collision-free.)
+  template <class Q>
+  static __device__ __forceinline__ bool broad_flag(const Q& q, const Consts& P) {
+    int nr = 0;
+    fk<float, false>(q, P.f, [&](auto J, const Rig<float>& X, const JP<float>&) {
+      constexpr int l = decltype(J)::value;
+      if constexpr (Topo::may_have_spheres(l)) {
+        const TP<float>& T = P.f;
+        const float4 blo = make_float4(T.obs_lo[0], T.obs_lo[1], T.obs_lo[2], 0.f);
+        const float4 bhi = make_float4(T.obs_hi[0], T.obs_hi[1], T.obs_hi[2], 0.f);
+        const float* bs = T.lbs[l];
+        float c[3];
+        for (int k = 0; k < 3; ++k) c[k] = X.p[k] + X.R[3 * k] * bs[0] + X.R[3 * k + 1] * bs[1] + X.R[3 * k + 2] * bs[2];
+        nr |= (bs[3] >= 0.f) & (box_dist2(c, blo, bhi) <= bs[3] * bs[3]);
+      }
+    });
+    return nr != 0;
   }
 
   // Exhaustive minimum signed distance over all sphere pairs (and the verdict), one lane.

@@ -41,7 +41,7 @@ __device__ __forceinline__ void point_check(const float* c, float r, const CollC
 
 struct SphereModel {
   static constexpr int family = 0;
-  static constexpr bool broad_in_residual = false;
+  static constexpr bool broad_in_residual = false;  // the exact check is cheap: run it at convergence
   static constexpr int D = 3, M = 1;
   static constexpr int NBLK = 1;
   static constexpr uint32_t ALL = ~uint32_t(0);
@@ -49,8 +49,8 @@ struct SphereModel {
   static constexpr bool lnz(int, int) { return true; }
   template <class S> struct SD { S dummy; };
 
-  template <class S, bool BROAD = false, uint32_t RM = ~uint32_t(0), class Q>
-  static __device__ __forceinline__ double residual(const Q& q, const Consts&, S* F, SD<S>&, bool* = nullptr) {
+  template <class S, uint32_t RM = ~uint32_t(0), class Q>
+  static __device__ __forceinline__ double residual(const Q& q, const Consts&, S* F, SD<S>&) {
     const double a = q.at(0), b = q.at(1), c = q.at(2);
     const double f = a * a + b * b + c * c - 1.0;
     F[0] = S(f);
@@ -71,6 +71,8 @@ struct SphereModel {
   static __device__ __forceinline__ void jacobian(const Q& q, const Consts&, const SD<S>&, S* J) {
     for (int k = 0; k < 3; ++k) J[k] = S(2) * S(q.at(k));
   }
+  template <class Q>
+  static __device__ __forceinline__ bool broad_flag(const Q&, const Consts&) { return true; }
   // Point robot: every lane of the group runs the whole (cheap) test.
   template <int L, class Q>
   static __device__ __forceinline__ bool check_group(const Q& q, const Consts&, const CollConsts& K, const float4*,
@@ -98,7 +100,7 @@ struct SphereModel {
 // so they contribute nothing to the step.
 struct LinearModel {
   static constexpr int family = 1;
-  static constexpr bool broad_in_residual = false;
+  static constexpr bool broad_in_residual = false;  // the exact check is cheap: run it at convergence
   static constexpr int D = LIN_D, M = LIN_M;
   static constexpr int NBLK = 1;
   static constexpr uint32_t ALL = ~uint32_t(0);
@@ -106,8 +108,8 @@ struct LinearModel {
   static constexpr bool lnz(int, int) { return true; }
   template <class S> struct SD { S dummy; };
 
-  template <class S, bool BROAD = false, uint32_t RM = ~uint32_t(0), class Q>
-  static __device__ __forceinline__ double residual(const Q& q, const Consts& P, S* F, SD<S>&, bool* = nullptr) {
+  template <class S, uint32_t RM = ~uint32_t(0), class Q>
+  static __device__ __forceinline__ double residual(const Q& q, const Consts& P, S* F, SD<S>&) {
     double qv[D], n2 = 0.0;
     for (int c = 0; c < D; ++c) qv[c] = q.at(c);
     for (int r = 0; r < M; ++r) {
@@ -155,6 +157,8 @@ struct LinearModel {
                                                      const float4*) {
     return false;
   }
+  template <class Q>
+  static __device__ __forceinline__ bool broad_flag(const Q&, const Consts&) { return false; }
   template <class Q>
   static __device__ __forceinline__ void min_signed_distance(const Q&, const Consts&, const CollConsts&, const float4*,
                                                              bool& hit, float& minsd) {

@@ -7,8 +7,8 @@ factorisation and two triangular solves over the nonzeros of the factor, J^T y a
 update; and, once per configuration, the broad phase of the collision check (each link's
 bounding sphere moved to the world frame and tested against the box around the obstacles).
 Recomputations an implementation makes (the library re-runs the kinematics in its Gram and
-J^T y passes to save registers, and runs the broad-phase test in every residual pass, not only
-the last) are not counted; sine/cosine, square roots and reciprocals count as one FLOP each.
+J^T y passes to save registers, and once more in FP32 for the broad phase at convergence) are
+not counted; sine/cosine, square roots and reciprocals count as one FLOP each.
 """
 from __future__ import annotations
 
