@@ -347,28 +347,95 @@ __global__ void k_interpolate(int n_geo, const int32_t* offs, const IO* e, int64
   }
 }
 
+// The geodesic holding configuration i, found by one wavefront: each round, the 64 lanes probe
+// 64 evenly spaced offsets and a ballot narrows the range 64-fold (2 rounds for 4,096 geodesics,
+// against 12 dependent loads of a binary search). Call with all 64 lanes of the wave active.
+__device__ __forceinline__ int wave_find_geo(const int32_t* offs, int n_geo, int64_t i) {
+  int lo = 0, hi = n_geo;  // offs[lo] <= i < offs[hi] (or hi = n_geo)
+  const int lane = int(threadIdx.x & 63);
+  while (hi - lo > 1) {
+    const int64_t span = hi - lo;
+    const int probe = lo + int((span * lane) / 64);
+    const bool le = lane == 0 || offs[probe] <= i;  // offs[probe] <= i (lane 0 probes lo)
+    const uint64_t m = uint64_t(__ballot(le));
+    const int last = 63 - __builtin_clzll(m);        // the highest probe still <= i
+    const int nlo = lo + int((span * last) / 64);
+    const int nhi = last == 63 ? hi : lo + int((span * (last + 1)) / 64);
+    lo = nlo;
+    hi = nhi > nlo ? nhi : nlo + 1;
+  }
+  return lo;
+}
+
+// The geodesics a workgroup's configurations [i0, i1] belong to: the first wavefront finds the
+// first and last one, the workgroup stages the offsets between them in LDS (when they fit) and
+// searches there.
+constexpr int kGeoWindow = 1024;
+constexpr int kMaxD = 36;  // largest configuration dimension of the compiled families
+
 template <class IO>
-__global__ void k_path_grad(int64_t n, const IO* q, int64_t ld, const int32_t* offs, int n_geo, IO* g, IO* loss, int d) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_path_grad(int64_t n, const IO* q, int64_t ld, const int32_t* offs, int n_geo,
+                                                   IO* g, IO* loss, int d) {
+  __shared__ int32_t s_offs[kGeoWindow];
+  __shared__ int s_g[2];
+  const int64_t i0 = int64_t(blockIdx.x) * blockDim.x;
+  const int64_t i1 = (i0 + blockDim.x < n ? i0 + blockDim.x : n) - 1;
+  if (threadIdx.x < 64) {
+    const int ga = wave_find_geo(offs, n_geo, i0);
+    const int gb = wave_find_geo(offs, n_geo, i1);
+    if (threadIdx.x == 0) {
+      s_g[0] = ga;
+      s_g[1] = gb;
+    }
+  }
+  __syncthreads();
+  const int g0 = s_g[0], w = s_g[1] - g0 + 2;  // offsets g0 .. g1 + 1
+  const bool win = w <= kGeoWindow;
+  if (win)
+    for (int t = threadIdx.x; t < w; t += blockDim.x) s_offs[t] = offs[g0 + t];
+  __syncthreads();
+  const int64_t i = i0 + threadIdx.x;
   double seg = 0.0;
   if (i < n) {
-    const int gi = find_geo(offs, n_geo, i);
-    const bool has_prev = i > offs[gi], has_next = i + 1 < offs[gi + 1] && i + 1 < n;
+    int64_t lo_off, hi_off;  // the configuration's geodesic is [lo_off, hi_off)
+    if (win) {
+      int lo = 0, hi = w - 1;  // s_offs[lo] <= i < s_offs[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_offs[mid] <= i) lo = mid; else hi = mid;
+      }
+      lo_off = s_offs[lo];
+      hi_off = s_offs[lo + 1];
+    } else {
+      const int gi = find_geo(offs, n_geo, i);
+      lo_off = offs[gi];
+      hi_off = offs[gi + 1];
+    }
+    const bool has_prev = i > lo_off, has_next = i + 1 < hi_off && i + 1 < n;
+    // all loads first (one memory latency), then the arithmetic
+    IO x[kMaxD], xp[kMaxD], xn[kMaxD];
+    for (int c = 0; c < kMaxD; ++c) {
+      const int64_t k = int64_t(c) * ld + i;
+      x[c] = c < d ? q[k] : IO(0);
+      xp[c] = (c < d && has_prev) ? q[k - 1] : x[c];
+      xn[c] = (c < d && has_next) ? q[k + 1] : x[c];
+    }
     double np = 0.0, nn = 0.0;
-    for (int c = 0; c < d; ++c) {
-      const double x = double(q[c * ld + i]);
-      if (has_prev) { const double t = x - double(q[c * ld + i - 1]); np += t * t; }
-      if (has_next) { const double t = double(q[c * ld + i + 1]) - x; nn += t * t; }
+    for (int c = 0; c < kMaxD; ++c) {
+      const double tp = double(x[c]) - double(xp[c]), tn = double(xn[c]) - double(x[c]);
+      np += tp * tp;
+      nn += tn * tn;
     }
     np = sqrt(np);
     nn = sqrt(nn);
     const double ip = 1.0 / fmax(np, 1e-12), in = 1.0 / fmax(nn, 1e-12);
-    for (int c = 0; c < d; ++c) {
-      const double x = double(q[c * ld + i]);
-      double gr = 0.0;
-      if (has_prev) gr += (x - double(q[c * ld + i - 1])) * ip;  // u_{i-1}
-      if (has_next) gr -= (double(q[c * ld + i + 1]) - x) * in;  // -u_i
-      g[c * ld + i] = IO(gr);
+    for (int c = 0; c < kMaxD; ++c) {
+      if (c < d) {
+        double gr = 0.0;
+        if (has_prev) gr += (double(x[c]) - double(xp[c])) * ip;  // u_{i-1}
+        if (has_next) gr -= (double(xn[c]) - double(x[c])) * in;  // -u_i
+        g[int64_t(c) * ld + i] = IO(gr);
+      }
     }
     if (has_next) seg = nn;
   }
@@ -876,6 +943,7 @@ mc_status path_length_grad(const mc_problem* p, int64_t n, const void* q, int64_
   if (n == 0) return MC_OK;
   if (!q || !geo_offsets || !g_out || n_geo == 0) return fail(MC_ERR_INVALID_ARG, "path_length_grad: null array");
   if (ld < n) return fail(MC_ERR_INVALID_ARG, "path_length_grad: ld < n");
+  if (p->d > kMaxD) return fail(MC_ERR_UNSUPPORTED, "path_length_grad: dimension above 36");
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e;
   const dim3 g((n + 255) / 256), b(256);

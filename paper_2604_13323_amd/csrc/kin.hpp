@@ -524,8 +524,8 @@ struct Kin {
   }
 
   // Gram pass: G += J_j J_j^T over all columns (packed lower triangle), optionally v = J g.
-  template <class S, bool WITH_V, uint32_t RM = ALL, class Q>
-  static __device__ __forceinline__ void gram(const Q& q, const Consts& P, const SD<S>& sd, S* G, const S* g, S* v) {
+  template <class S, bool WITH_V, uint32_t RM = ALL, class Q, class GV = const S*>
+  static __device__ __forceinline__ void gram(const Q& q, const Consts& P, const SD<S>& sd, S* G, GV g, S* v) {
     const TP<S>& T = tp<S>(P);
     sfor<0, M>([&](auto I) {
       constexpr int i = decltype(I)::value;

@@ -57,8 +57,8 @@ struct SphereModel {
     return f * f;
   }
   // J = 2 q^T, so J J^T = 4 q.q and J g = 2 q.g
-  template <class S, bool WITH_V, uint32_t RM = ~uint32_t(0), class Q>
-  static __device__ __forceinline__ void gram(const Q& q, const Consts&, const SD<S>&, S* G, const S* g, S* v) {
+  template <class S, bool WITH_V, uint32_t RM = ~uint32_t(0), class Q, class GV = const S*>
+  static __device__ __forceinline__ void gram(const Q& q, const Consts&, const SD<S>&, S* G, GV g, S* v) {
     const S a = S(q.at(0)), b = S(q.at(1)), c = S(q.at(2));
     G[0] = S(4) * (a * a + b * b + c * c);
     if constexpr (WITH_V) v[0] = S(2) * (a * g[0] + b * g[1] + c * g[2]);
@@ -121,8 +121,8 @@ struct LinearModel {
     }
     return n2;
   }
-  template <class S, bool WITH_V, uint32_t RM = ~uint32_t(0), class Q>
-  static __device__ __forceinline__ void gram(const Q&, const Consts& P, const SD<S>&, S* G, const S* g, S* v) {
+  template <class S, bool WITH_V, uint32_t RM = ~uint32_t(0), class Q, class GV = const S*>
+  static __device__ __forceinline__ void gram(const Q&, const Consts& P, const SD<S>&, S* G, GV g, S* v) {
     const TP<S>& T = tp<S>(P);
     for (int i = 0; i < M; ++i) {
       for (int k = 0; k <= i; ++k) {
