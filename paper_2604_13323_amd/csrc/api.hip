@@ -838,8 +838,8 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
       return hip_fail(e, "project_batch: persistent launch");
     if (tail && (e = (cyc ? ops->project_tail_cyclic : ops->project_tail)(a, p->n_cu, s)) != hipSuccess)
       return hip_fail(e, "project_batch: FP64 tail launch");
-    // 2 workgroups of 4 waves per CU: 2,048 flagged configurations per round (blocks without work leave at once)
-    if (ctail && (e = ops->check_tail(a, 2 * p->n_cu, s)) != hipSuccess) return hip_fail(e, "project_batch: check tail launch");
+    // 4 workgroups of 4 waves per CU: 4,096 work items per round (blocks without work leave at once)
+    if (ctail && (e = ops->check_tail(a, 4 * p->n_cu, s)) != hipSuccess) return hip_fail(e, "project_batch: check tail launch");
   }
   if (geo_ok) {
     hipLaunchKernelGGL(k_geo_ok, dim3((n_geo + 255) / 256), dim3(256), 0, s, n_geo, geo_offsets, n, status, verdict, geo_ok);

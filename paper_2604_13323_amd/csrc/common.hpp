@@ -251,6 +251,20 @@ struct QLds {
   }
   __device__ __forceinline__ void set(int j, double v) const { base[j * 64] = v; }
 };
+// One configuration shared by the 64 lanes of a wave (D consecutive doubles; every lane reads the
+// same address, an LDS broadcast).
+struct QLdsU {
+  using LP = __attribute__((address_space(3))) double*;
+  LP base;
+  __device__ __forceinline__ double at(int j) const { return opaque(base[j]); }
+  template <class U>
+  __device__ __forceinline__ double at(int j, U dep) const {
+    LP b = base;
+    asm volatile("" : "+v"(b) : "v"(dep));
+    return opaque(b[j]);
+  }
+  __device__ __forceinline__ void set(int j, double v) const { base[j] = v; }
+};
 // The calling lane's column; smem holds blockDim.x / 64 tiles of D x 64 doubles.
 template <int D>
 __device__ __forceinline__ QLds q_lds(double* smem) {

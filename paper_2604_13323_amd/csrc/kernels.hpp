@@ -344,8 +344,8 @@ __device__ __forceinline__ unsigned queue_q(const QLds& q, unsigned* count, doub
   return slot;
 }
 
-template <class Model, class IO>
-__device__ __forceinline__ void load_queued(const double* qbuf, int64_t cap, int64_t slot, const QLds& q) {
+template <class Model, class IO, class Q>
+__device__ __forceinline__ void load_queued(const double* qbuf, int64_t cap, int64_t slot, const Q& q) {
   const double* src = qbuf + slot;
   for (int c = 0; c < Model::D; ++c) {
     q.set(c, *src);
@@ -399,6 +399,7 @@ __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
             // broad phase on the converged configuration (an FP32 walk of the link bounds)
             if (a.check && st == ST_CONVERGED) near = Model::broad_flag(q, C);
             if (a.check && st == ST_CONVERGED && near) {
+              a.verdict[i] = V_FREE;  // k_check_tail overwrites it with V_HIT if some part finds a hit
               a.chk_idx[queue_q<Model>(q, a.chk_count, a.chk_q, a.defer_cap)] = int32_t(i);
             } else {
               a.verdict[i] = (a.check && st == ST_CONVERGED) ? V_FREE : V_UNCHECKED;
@@ -422,26 +423,36 @@ __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
 // configuration while the queue is short (at most `small` entries: latency-bound, few waves) and
 // a few lanes per configuration when it is long (most configurations near the obstacles); each
 // returns at once when the queue length is not its case.
-// Dynamic LDS: D * blockDim doubles, then the robot spheres and the obstacles (float4 each).
+// Dynamic LDS: the configurations (a column per lane, or one per wave when L = 64), then the
+// robot spheres and the obstacles (float4 each).
 template <class Model, class IO, int L>
 __global__ void __launch_bounds__(256) k_check_tail(ProjArgs a, int64_t small) {
+  constexpr int D = Model::D;
   extern __shared__ double smem[];
   const Consts& C = consts_of(a.P);
   const CollConsts& K = coll_of(a.P);
   const int64_t cnt = *a.chk_count;
   if ((cnt <= small) != (L == 64)) return;                  // the other instance's case
-  if (int64_t(blockIdx.x) * blockDim.x / L >= cnt) return;  // no queued work for this block
-  const QLds q = q_lds<Model::D>(smem);
-  float4* sph = reinterpret_cast<float4*>(smem + Model::D * blockDim.x);
+  // a short queue leaves waves idle: split each configuration's links over up to 4 waves
+  int64_t parts = 1;
+  if (L == 64 && cnt > 0) parts = small / cnt < 4 ? (small / cnt < 1 ? 1 : small / cnt) : 4;
+  if (int64_t(blockIdx.x) * blockDim.x / L >= cnt * parts) return;  // no queued work for this block
+  using QT = typename std::conditional<L == 64, QLdsU, QLds>::type;
+  QT q;
+  if constexpr (L == 64) q = QLdsU{(QLdsU::LP)(smem + (threadIdx.x >> 6) * D)};
+  else q = q_lds<D>(smem);
+  float4* sph = reinterpret_cast<float4*>(smem + (L == 64 ? D * (blockDim.x >> 6) : D * blockDim.x));
   float4* obs = sph + K.n_sph;
   block_copy16(sph, K.sph, K.n_sph * 16);
   block_copy16(obs, obs_of(a.P), K.n_obs * 16);
   __syncthreads();
   const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  for (int64_t slot = gid / L; slot < cnt; slot += int64_t(gridDim.x) * blockDim.x / L) {
+  for (int64_t item = gid / L; item < cnt * parts; item += int64_t(gridDim.x) * blockDim.x / L) {
+    const int64_t slot = item / parts;
+    const int part = int(item - slot * parts);
     load_queued<Model, IO>(a.chk_q, a.defer_cap, slot, q);
-    const bool hit = Model::template check_group<L>(q, C, K, sph, obs);
-    if ((gid & (L - 1)) == 0) a.verdict[a.chk_idx[slot]] = hit ? V_HIT : V_FREE;
+    const bool hit = Model::template check_group<L>(q, C, K, sph, obs, part, int(parts));
+    if ((gid & (L - 1)) == 0 && hit) a.verdict[a.chk_idx[slot]] = V_HIT;  // queued as V_FREE
   }
 }
 

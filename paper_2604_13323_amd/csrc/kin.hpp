@@ -599,6 +599,13 @@ struct Kin {
     return n;
   }();
 
+  // Rank of link l among the links that may carry spheres.
+  static constexpr int geo_rank(int l) {
+    int n = 0;
+    for (int k = 0; k < l; ++k) n += Topo::may_have_spheres(k) ? 1 : 0;
+    return n;
+  }
+
   // Exact sphere test of one link's spheres (world frame X) against obstacles [o0, o1).
   template <bool MINSD>
   static __device__ __forceinline__ void narrow(const Rig<float>& X, const CollConsts& K, const float4* obs, int l,
@@ -629,9 +636,12 @@ struct Kin {
   // the clusters the link overlaps, and for each of those the L lanes share the exact tests of the
   // link's spheres (sph) against the cluster's obstacles (obs). sph and obs may point to LDS
   // copies. Returns the verdict (the same in all L lanes).
+  // With parts > 1 the group handles only the links of rank part, part + parts, ... (the other
+  // parts of the configuration's check run in other groups).
   template <int L, class Q>
   static __device__ __forceinline__ bool check_group(const Q& q, const Consts& P, const CollConsts& K,
-                                                     const float4* sph, const float4* obs) {
+                                                     const float4* sph, const float4* obs, int part = 0,
+                                                     int parts = 1) {
     static_assert(L >= 1 && L <= 64 && (L & (L - 1)) == 0, "L must be a power of two <= 64");
     constexpr int PB = (MAXC + L - 1) / L < 8 ? (MAXC + L - 1) / L : 8;  // boxes kept in registers
     const int lane = int(__lane_id());
@@ -654,7 +664,8 @@ struct Kin {
         const float4 bs = K.link_bs[l];
         // a group that already has its verdict skips the remaining links
         const bool done = ((uint64_t(__ballot(hit)) >> shift) & gmask) != 0;
-        if (bs.w >= 0.f && !done) {
+        const bool mine = parts == 1 || geo_rank(l) % parts == part;
+        if (bs.w >= 0.f && !done && mine) {
           const float lc[3] = {bs.x, bs.y, bs.z};
           float cb[3];
           matvec3(X.R, lc, cb);

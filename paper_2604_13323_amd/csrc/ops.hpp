@@ -56,12 +56,15 @@ struct OpsImpl {
     return hipGetLastError();
   }
   static hipError_t check_tail(const ProjArgs& a, int grid, hipStream_t s) {
-    const size_t lds = lds_bytes(256) + size_t(a.n_sph + a.n_obs) * 16;
-    const int64_t small = int64_t(grid) * 4;  // one pass of the grid at a wave per configuration
-    hipLaunchKernelGGL((k_check_tail<Model, IO, 64>), dim3(grid), dim3(256), lds, s, a, small);
+    const size_t stage = size_t(a.n_sph + a.n_obs) * 16;
+    // short queues: a wave (or part of one configuration's links) per work item, one pass of
+    // `small` work items over 4 waves per workgroup
+    const int64_t small = int64_t(grid) * 4;
+    hipLaunchKernelGGL((k_check_tail<Model, IO, 64>), dim3(grid), dim3(256), 4 * Model::D * 8 + stage, s, a, small);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_check_tail<Model, IO, kTailCheckLanesLong>), dim3(4 * grid), dim3(256), lds, s, a, small);
+    hipLaunchKernelGGL((k_check_tail<Model, IO, kTailCheckLanesLong>), dim3(grid), dim3(256), lds_bytes(256) + stage, s,
+                       a, small);
     return hipGetLastError();
   }
   static hipError_t vjp_tail(const VjpArgs& a, int grid, hipStream_t s) {
