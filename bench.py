@@ -49,17 +49,25 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def timed(fn, steps, warmup, torch):
+STEP_MEDIANS = {}
+
+
+def timed(fn, steps, warmup, torch, name=None):
+    """Mean ms per step over `steps` steps after `warmup` untimed ones (HIP events on the current
+    stream, which the library launches on); with a name, the median of the per-step times is kept
+    in STEP_MEDIANS as well."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(steps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for k in range(steps):
         fn()
-    stop.record()
+        ev[k + 1].record()
     torch.cuda.synchronize()
-    return start.elapsed_time(stop) / steps  # ms per step
+    if name:
+        STEP_MEDIANS[name] = float(np.median([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]))
+    return ev[0].elapsed_time(ev[steps]) / steps  # ms per step
 
 
 def build_batch(G, cfg, torch):
@@ -140,6 +148,21 @@ def other_workloads(M, S, FL, torch, steps):
     return rows
 
 
+def cyclic_row(G, q_in, out, kw, args, torch):
+    """The cyclic mode (one step per constraint block) on the headline batch."""
+    outc = G.project(q_in, variant="fused", mode="cyclic", **kw)
+    ms_cyc = timed(lambda: G.project(q_in, variant="fused", mode="cyclic", out=outc, **kw), args.steps, args.warmup,
+                   torch)
+    st_c = outc.status.cpu().numpy()
+    it_c = outc.iters.cpu().numpy().astype(np.int64)
+    cyclic = dict(ms_per_step=ms_cyc, value=float((st_c == 0).sum() / (ms_cyc * 1e-3)),
+                  converged_frac=float((st_c == 0).mean()), iters_mean=float(it_c.mean()),
+                  iters_p99=float(np.percentile(it_c, 99)),
+                  max_abs_diff_vs_stacked=float((outc.q - out.q).abs().max()))
+    log(f"cyclic mode: {ms_cyc:.3f} ms/step, {cyclic['value']:.4g} converged/s, iterations {cyclic['iters_mean']:.2f}")
+    return cyclic
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +179,7 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true", help="use the library's default launch shape")
     ap.add_argument("--no-others", action="store_true", help="skip the C0-C2 attribution rows")
+    ap.add_argument("--no-cyclic", action="store_true", help="skip the cyclic-mode row")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the projection shards by whole "
@@ -192,7 +216,7 @@ def main():
 
     # --- headline: fused persistent projection + collision check
     G.fallback_count(reset=True)
-    ms = timed(lambda: G.project(q_in, variant="fused", out=out, **kw), args.steps, args.warmup, torch)
+    ms = timed(lambda: G.project(q_in, variant="fused", out=out, **kw), args.steps, args.warmup, torch, "fused")
     status = out.status.cpu().numpy()
     iters = out.iters.cpu().numpy().astype(np.int64)
     verdict = out.verdict.cpu().numpy()
@@ -206,24 +230,19 @@ def main():
                              iters=torch.empty_like(out.iters), resid=torch.empty_like(out.resid),
                              verdict=None, geo_ok=None)
     ms_proj = timed(lambda: G.project(q_in, variant="fused", out=out_nc, check=False, **kw), args.steps,
-                    args.warmup, torch)
+                    args.warmup, torch, "projection")
     ms_check = timed(lambda: G.check(out.q), args.steps, args.warmup, torch)
-    flop = FL.batch_flops(sc, iters)
+    # the roofline kernel is the projection launch without the collision walk (check=False), so its
+    # work excludes the broad phase
+    flop = FL.batch_flops(sc, iters, with_broad=False)
     achieved_tflops = flop / (ms_proj * 1e-3) / 1e12
     log(f"projection kernel alone: {ms_proj:.3f} ms, {achieved_tflops:.2f} TFLOP/s algorithmic; "
         f"check alone {ms_check:.3f} ms")
 
     # --- the paper's composition rule: cyclic steps over the constraint blocks (same batch)
-    outc = G.project(q_in, variant="fused", mode="cyclic", **kw)
-    ms_cyc = timed(lambda: G.project(q_in, variant="fused", mode="cyclic", out=outc, **kw), args.steps, args.warmup,
-                   torch)
-    st_c = outc.status.cpu().numpy()
-    it_c = outc.iters.cpu().numpy().astype(np.int64)
-    cyclic = dict(ms_per_step=ms_cyc, value=float((st_c == 0).sum() / (ms_cyc * 1e-3)),
-                  converged_frac=float((st_c == 0).mean()), iters_mean=float(it_c.mean()),
-                  iters_p99=float(np.percentile(it_c, 99)),
-                  max_abs_diff_vs_stacked=float((outc.q - out.q).abs().max()))
-    log(f"cyclic mode: {ms_cyc:.3f} ms/step, {cyclic['value']:.4g} converged/s, iterations {cyclic['iters_mean']:.2f}")
+    cyclic = None
+    if not args.no_cyclic:
+        cyclic = cyclic_row(G, q_in, out, kw, args, torch)
 
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "traffic_projection_humanoid36.json")
@@ -270,7 +289,7 @@ def main():
             g, _ = G.path_length_grad(o4.q, offs4)
             G.vjp(o4.q, o4.status, g)
 
-        ms4 = timed(fwd_vjp, args.steps, args.warmup, torch)
+        ms4 = timed(fwd_vjp, args.steps, args.warmup, torch, "fwd_vjp")
         fv = dict(value=n4 / (ms4 * 1e-3), unit="configurations/s", ms_per_step=ms4, configs=n4,
                   geodesics=len(cfg4["geo_offsets"]) - 1)
         log(f"fwd+vjp: {ms4:.3f} ms/step, {fv['value']:.4g} configurations/s")
@@ -323,6 +342,8 @@ def main():
                   "fp64_fallbacks_per_step": fallbacks / max(1, args.steps + args.warmup),
                   "check_batch_ms": ms_check, "projection_ms": ms_proj,
                   "launch_shape": {k: kw[k] for k in ("waves_per_block", "blocks_per_cu")},
+                  "median_ms_per_step": dict(STEP_MEDIANS),
+                  "cus": torch.cuda.get_device_properties(0).multi_processor_count,
                   "autotune": tuning["table"] if tuning else None,
                   "gpu": torch.cuda.get_device_name(0)},
     }

@@ -146,8 +146,10 @@ def iteration_flops(sc: S.Scene) -> dict:
     return dict(per_iter=sum(it.values()), final=fk + frames + res + broad, parts=dict(it, broad_once=broad))
 
 
-def batch_flops(sc: S.Scene, iters: np.ndarray) -> float:
-    """Algorithmic FLOPs of projecting a batch whose per-configuration step counts are `iters`."""
+def batch_flops(sc: S.Scene, iters: np.ndarray, with_broad: bool = True) -> float:
+    """Algorithmic FLOPs of projecting a batch whose per-configuration step counts are `iters`
+    (with_broad: including the collision broad phase of each configuration)."""
     f = iteration_flops(sc)
     iters = np.asarray(iters, np.int64)
-    return float(f["per_iter"] * iters.sum() + f["final"] * iters.size)
+    final = f["final"] - (0 if with_broad else f["parts"].get("broad_once", 0))
+    return float(f["per_iter"] * iters.sum() + final * iters.size)

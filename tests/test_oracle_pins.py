@@ -34,6 +34,20 @@ def test_sphere_closed_form_and_heron_counts(oracle_mod):
         assert rs[0] < 1e-6
 
 
+def test_sphere_heron_counts_match_golden_fixture(oracle_mod):
+    """The stored table (tests/golden/heron_counts.txt, written from the recurrence in exact
+    rationals by tests/golden/make_golden.py) against the oracle."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "heron_counts.txt")
+    P = prob(S.sphere_scene(0))
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 5
+    u = np.array([0.6, 0.0, 0.8])
+    for r0, k in rows:
+        qo, st, it, rs = P.project((float(r0) * u)[None], tol=1e-6, max_iter=50)
+        assert st[0] == CONV and it[0] == int(k), (r0, it[0], k)
+
+
 def test_sphere_random_batch_matches_normalisation(oracle_mod):
     P = prob(S.sphere_scene(0))
     q, _ = S.sphere_workload(0, n_seg=32)
