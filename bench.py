@@ -163,6 +163,34 @@ def cyclic_row(G, q_in, out, kw, args, torch):
     return cyclic
 
 
+def extend_row(M, S, G, torch, steps):
+    """Alg. 2 ConstrainedExtend batched (extend_batch) on the humanoid: 8,192 extensions of 8
+    particles each (65,536 particle projections, as many lanes as the headline batch), then the
+    interpolation and refinement levels of every surviving extension."""
+    w = S.extend_workload("c3", 8192)
+    raw = torch.from_numpy(np.ascontiguousarray(w["starts"].T)).to("cuda", torch.float32)
+    rs = G.project(raw, tol=1e-9, max_iter=100, check=False)
+    keep = (rs.status == 0).nonzero().flatten()
+    qs = rs.q.index_select(1, keep).contiguous()
+    qt = torch.from_numpy(np.ascontiguousarray(w["targets"].T)).to("cuda", torch.float32).index_select(1, keep)
+    qt = qt.contiguous()
+    eps = torch.from_numpy(w["eps"]).to("cuda", torch.float32).index_select(0, keep).contiguous()
+    E = qs.shape[1]
+    call = lambda: G.extend(qs, qt, eps, w["r"], w["delta"], tol=w["tol"], max_iter=w["max_iter"])
+    r = call()
+    ms = timed(call, steps, 1, torch, "extend")
+    code = r.result.cpu().numpy()
+    npts = r.n_points.cpu().numpy()
+    ok = code == M.EXT_OK
+    row = dict(extensions=E, particles=int(E * w["eps"].shape[1]), ms_per_call=ms,
+               extensions_per_s=E / (ms * 1e-3), successful_per_s=float(ok.sum() / (ms * 1e-3)),
+               codes={int(c): int((code == c).sum()) for c in np.unique(code)},
+               mean_chain_points_ok=float(npts[ok].mean()) if ok.any() else None,
+               r=w["r"], delta=w["delta"], n=w["n"], sigma=w["sigma"])
+    log(f"extend: {E} extensions in {ms:.3f} ms ({row['extensions_per_s']:.4g}/s), codes {row['codes']}")
+    return row
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,6 +208,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="use the library's default launch shape")
     ap.add_argument("--no-others", action="store_true", help="skip the C0-C2 attribution rows")
     ap.add_argument("--no-cyclic", action="store_true", help="skip the cyclic-mode row")
+    ap.add_argument("--no-extend", action="store_true", help="skip the ConstrainedExtend row")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the projection shards by whole "
@@ -301,6 +330,7 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
+    ext = None if args.no_extend else extend_row(M, S, G, torch, min(args.steps, 10))
     others = None if args.no_others else other_workloads(M, S, FL, torch, args.steps)
 
     cpu = None
@@ -335,6 +365,7 @@ def main():
         "fused_vs_plain": (value / plain["value"]) if plain else None,
         "fwd_vjp": fv,
         "cyclic_mode": cyclic,
+        "extend": ext,
         "other_workloads": others,
         "stats": {"converged_frac": n_conv / n, "iters_mean": float(iters.mean()),
                   "iters_p99": float(np.percentile(iters, 99)), "iters_max": int(iters.max()),

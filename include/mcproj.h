@@ -197,6 +197,57 @@ mc_status path_length_grad(const mc_problem* p, int64_t n, const void* q, int64_
 mc_status mc_eval_residual_jacobian(const mc_problem* p, int64_t n, const void* q, int64_t ld,
                                     mc_dtype dtype, void* F, void* J, void* stream);
 
+/* Outcome of one extension (extend_batch `result` values), in the order the steps test them. */
+enum {
+  MC_EXT_OK = 0,               /* q_out holds q_proj; the validated chain meets the resolution    */
+  MC_EXT_ZERO = 1,             /* q_target == q_start: no direction to extend along              */
+  MC_EXT_NO_PARTICLE = 2,      /* no particle projection converged                                */
+  MC_EXT_COLLISION = 3,        /* the selected particle's projection is in collision              */
+  MC_EXT_TOO_FAR = 4,          /* ||q_proj - q_start|| > 2 dist (first early exit)                */
+  MC_EXT_INTERP_FAILED = 5,    /* an interpolated or refined point did not converge               */
+  MC_EXT_INTERP_COLLISION = 6, /* an interpolated or refined point is in collision                */
+  MC_EXT_GAP = 7               /* two adjacent projected points lie farther apart than the level's
+                                  bound (second early exit)                                       */
+};
+
+typedef struct {
+  double r;      /* extension range: q_steer lies min(||q_target - q_start||, r) from q_start, > 0 */
+  double delta;  /* motion-validation resolution: refinement stops once every gap of the chain
+                    is <= delta, > 0                                                           */
+  int32_t n;     /* particles, and interpolated points, per extension: 1..64                      */
+} mc_extend_opts;
+
+/* extend_batch — Alg. 2 ConstrainedExtend for E independent extensions (Sec. IV-A: steer,
+   particles, two-stage projection, recursive refinement; Sec. IV-B: early exits), each step batched over
+   all extensions still alive and run by the projection kernels of project_batch (opts as
+   there; check_collision is forced on). For extension e, with s = q_start[:, e],
+   t = q_target[:, e], L = ||t - s||:
+     dist = min(L, r); v = (t - s) / L; q_steer = s + dist v;
+     particles p_i = q_steer + eps[e * n + i] v, i < n (eps: the N(0, sigma^2) draws, supplied
+       by the caller), all projected;
+     q_proj = the CONVERGED particle with the fewest steps (ties: lowest i), else NO_PARTICLE;
+       COLLISION if it collides, TOO_FAR if ||q_proj - s|| > 2 dist;
+     level 0: the chain s, c_1..c_n, q_proj with c_k = projection of s + k/(n+1) (q_proj - s);
+     level l >= 1 (while some gap of the chain exceeds delta): the projected midpoint of every
+       gap is inserted;
+     a level fails with INTERP_FAILED (a new point not CONVERGED), else INTERP_COLLISION (a new
+       point collides), else GAP (a gap next to a new point longer than r / (n 2^l)).
+   The number of levels is at most the smallest l with r / (n 2^l) <= delta, which must be
+   <= 12, and (n + 1) 2^l + 1 <= 65536.
+   Arrays (device, caller-owned): q_start, q_target [d][ld] and eps [E * n] of opts->dtype;
+   q_out [d][ld_out] (written for MC_EXT_OK only); result int8[E] (MC_EXT_*); particle
+   int32[E] (selected particle index, -1 before selection); n_points int32[E] (points of the
+   validated chain including both ends, 0 when the extension failed before level 0).
+   Workspace: particle, chain and level buffers owned by the problem, grown to the largest call
+   (synchronising the device when they grow). The call synchronises `stream` once per level to
+   read how many points the level emits (not capturable into a graph).
+   Errors: MC_ERR_INVALID_ARG for null required pointers, E < 0, ld < E, ld_out < E, r <= 0,
+   delta <= 0, n outside 1..64, too many levels, and every project_batch option error. */
+mc_status extend_batch(const mc_problem* p, int64_t E, const void* q_start, const void* q_target,
+                       int64_t ld, const void* eps, const mc_extend_opts* xopts,
+                       const mc_project_opts* opts, void* q_out, int64_t ld_out, int8_t* result,
+                       int32_t* particle, int32_t* n_points, void* stream);
+
 /* mc_fallback_count — number of configurations moved to FP64 (projections that switched to FP64
    steps, VJPs redone in FP64) by the calls enqueued on this problem since it was created or last
    reset (reset = 1 zeroes it after reading). Synchronises the device. */

@@ -21,6 +21,8 @@ MC_F32, MC_F64 = 0, 1
 CONVERGED, MAX_ITER, SINGULAR, DIVERGED, NONFINITE = range(5)
 FREE, COLLIDES, UNCHECKED = 0, 1, 2
 VARIANTS = {"auto": 0, "plain": 1, "fused": 2}
+(EXT_OK, EXT_ZERO, EXT_NO_PARTICLE, EXT_COLLISION, EXT_TOO_FAR, EXT_INTERP_FAILED, EXT_INTERP_COLLISION,
+ EXT_GAP) = range(8)
 
 
 class McError(RuntimeError):
@@ -35,11 +37,15 @@ class Opts(ctypes.Structure):
                 ("mode", ctypes.c_int32)]
 
 
+class ExtendOpts(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_double), ("delta", ctypes.c_double), ("n", ctypes.c_int32)]
+
+
 _lib = None
 
 EXPORTS = ["mc_default_opts", "mc_problem_create", "mc_problem_destroy", "mc_problem_dof", "mc_problem_rows",
            "mc_problem_family", "mc_last_error", "project_batch", "check_batch", "project_vjp",
-           "interpolate_geodesics", "path_length_grad", "mc_eval_residual_jacobian", "mc_fallback_count"]
+           "interpolate_geodesics", "path_length_grad", "mc_eval_residual_jacobian", "mc_fallback_count", "extend_batch"]
 
 
 def lib():
@@ -68,6 +74,8 @@ def lib():
     L.path_length_grad.argtypes = [P, I64, P, I64, P, I32, P, P, ctypes.c_int, P]
     L.mc_eval_residual_jacobian.argtypes = [P, I64, P, I64, ctypes.c_int, P, P, P]
     L.mc_fallback_count.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
+    L.extend_batch.argtypes = [P, I64, P, P, I64, P, ctypes.POINTER(ExtendOpts), ctypes.POINTER(Opts), P, I64, P, P,
+                               P, P]
     for f in EXPORTS:
         if f not in ("mc_default_opts", "mc_problem_destroy", "mc_problem_dof", "mc_problem_rows",
                      "mc_problem_family", "mc_last_error"):
@@ -127,6 +135,14 @@ def make_opts(dtype=MC_F32, tol=1e-6, max_iter=50, alpha=1.0, lam=0.0, max_step=
     o.blocks_per_cu = blocks_per_cu
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     return o
+
+
+@dataclass
+class ExtendResult:
+    q: torch.Tensor          # [d, E] q_proj of the selected particle (where particle >= 0)
+    result: torch.Tensor     # int8 [E], EXT_*
+    particle: torch.Tensor   # int32 [E], selected particle or -1
+    n_points: torch.Tensor   # int32 [E], points of the validated chain (EXT_OK)
 
 
 @dataclass
@@ -203,6 +219,28 @@ class Problem:
                                  None if offs_host is None else offs_host.ctypes.data_as(ctypes.c_void_p),
                                  n_geo, _ptr(out.geo_ok) if geo_ok else None, ctypes.byref(o), _stream())
         _check(rc, "project_batch")
+        return out
+
+    def extend(self, q_start: torch.Tensor, q_target: torch.Tensor, eps: torch.Tensor, r: float, delta: float,
+               tol=1e-6, max_iter=50, max_step=0.0, cond=1e6, mode="stacked") -> ExtendResult:
+        """ConstrainedExtend for E extensions: q_start, q_target [d, E] (same dtype and strides), eps [E, n] the
+        particle offsets along the extension direction (the N(0, sigma^2) draws)."""
+        E, ld = _soa(q_start, self.d, "extend")
+        if q_target.shape != q_start.shape or q_target.stride() != q_start.stride() or q_target.dtype != q_start.dtype:
+            raise McError("extend: q_target must match q_start in shape, strides and dtype")
+        if eps.dim() != 2 or eps.shape[0] != E or not eps.is_contiguous() or eps.dtype != q_start.dtype:
+            raise McError("extend: eps must be a contiguous [E, n] tensor of q_start's dtype")
+        n = eps.shape[1]
+        dev = q_start.device
+        out = ExtendResult(q=torch.empty((self.d, E), dtype=q_start.dtype, device=dev),
+                           result=torch.empty(E, dtype=torch.int8, device=dev),
+                           particle=torch.empty(E, dtype=torch.int32, device=dev),
+                           n_points=torch.empty(E, dtype=torch.int32, device=dev))
+        xo = ExtendOpts(r=float(r), delta=float(delta), n=int(n))
+        o = make_opts(_dtype_code(q_start), tol, max_iter, max_step=max_step, cond=cond, mode=mode)
+        _check(lib().extend_batch(self._h, E, _ptr(q_start), _ptr(q_target), ld, _ptr(eps), ctypes.byref(xo),
+                                  ctypes.byref(o), _ptr(out.q), out.q.stride(0), _ptr(out.result), _ptr(out.particle),
+                                  _ptr(out.n_points), _stream()), "extend_batch")
         return out
 
     def check(self, q: torch.Tensor, min_signed_dist=False):

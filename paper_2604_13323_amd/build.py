@@ -25,14 +25,19 @@ FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
          "-Wno-unused-command-line-argument", f"-I{INCLUDE}"]
 
 
-def _headers():
-    return glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(INCLUDE, "*.h"))
+def _headers(src: str):
+    """The headers a source depends on: every csrc header, and the public header where it is included."""
+    deps = glob.glob(os.path.join(CSRC, "*.hpp"))
+    with open(src) as f:
+        if "mcproj.h" in f.read():
+            deps += glob.glob(os.path.join(INCLUDE, "*.h"))
+    return deps
 
 
 def _compile(src: str, force: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     if not force and os.path.exists(obj):
-        newest = max(os.path.getmtime(p) for p in [src] + _headers())
+        newest = max(os.path.getmtime(p) for p in [src] + _headers(src))
         if os.path.getmtime(obj) >= newest:
             return obj
     cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj + ".tmp"]

@@ -463,6 +463,199 @@ __global__ void k_geo_ok(int n_geo, const int32_t* offs, int64_t n, const int8_t
   ok[g] = r;
 }
 
+
+// ------------------------------------------------------------ ConstrainedExtend
+// Alg. 2 ConstrainedExtend batched over independent extensions. Each extension keeps a chain of
+// K = (n + 1) 2^Lmax + 1 slots ([d][E K], slot e K + pos): level 0 fills positions k 2^Lmax,
+// level l the odd multiples of 2^(Lmax - l). The projections run in project_batch; these kernels
+// build the batches and take the decisions.
+constexpr int kExtRunning = -1;
+constexpr int kExtNone = 127;  // no failure recorded at this level
+
+__device__ __forceinline__ double ext_norm_diff(const double* a, const double* b, int d) {
+  double s = 0.0;
+  for (int c = 0; c < d; ++c) {
+    const double t = a[c] - b[c];
+    s += t * t;
+  }
+  return sqrt(s);
+}
+
+// particles p_i = q_steer + eps_i v (one thread per particle)
+template <class T>
+__global__ void k_ext_particles(int64_t E, int n, int d, const T* qs, const T* qt, int64_t ld, const T* eps, double r,
+                                T* part, int64_t ldp, double* dist, int8_t* result, int32_t* particle, int32_t* npts) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= E * n) return;
+  const int64_t e = g / n;
+  double L2 = 0.0;
+  for (int c = 0; c < d; ++c) {
+    const double t = double(qt[c * ld + e]) - double(qs[c * ld + e]);
+    L2 += t * t;
+  }
+  const double L = sqrt(L2);
+  const double ds = L < r ? L : r;
+  const double ep = double(eps[g]);
+  for (int c = 0; c < d; ++c) {
+    const double a = double(qs[c * ld + e]);
+    const double v = L > 0.0 ? (double(qt[c * ld + e]) - a) / L : 0.0;
+    part[c * ldp + g] = T(a + ds * v + ep * v);
+  }
+  if (g % n == 0) {
+    dist[e] = ds;
+    result[e] = L > 0.0 ? int8_t(kExtRunning) : int8_t(MC_EXT_ZERO);
+    particle[e] = -1;
+    npts[e] = 0;
+  }
+}
+
+// earliest converged particle, its collision verdict and distance test; seeds the chain ends
+template <class T>
+__global__ void k_ext_select(int64_t E, int n, int d, const T* qs, int64_t ld, const T* pout, int64_t ldp,
+                             const int8_t* st, const int8_t* it, const uint8_t* vd, const double* dist, int8_t* result,
+                             int32_t* particle, T* q_out, int64_t ld_out, double* chain, int64_t K, int64_t H) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= E || result[e] != kExtRunning) return;
+  int best = -1, best_it = 1 << 30;
+  for (int i = 0; i < n; ++i) {
+    const int64_t g = e * n + i;
+    if (st[g] == ST_CONVERGED && int(it[g]) < best_it) {
+      best = i;
+      best_it = it[g];
+    }
+  }
+  if (best < 0) {
+    result[e] = MC_EXT_NO_PARTICLE;
+    return;
+  }
+  particle[e] = best;
+  const int64_t g = e * n + best;
+  double* c0 = chain + e * K;
+  double* c1 = chain + e * K + (n + 1) * H;
+  double s2 = 0.0;
+  for (int c = 0; c < d; ++c) {
+    const double a = double(qs[c * ld + e]), b = double(pout[c * ldp + g]);
+    c0[c * E * K] = a;
+    c1[c * E * K] = b;
+    q_out[c * ld_out + e] = pout[c * ldp + g];
+    s2 += (b - a) * (b - a);
+  }
+  if (vd[g] != V_FREE) result[e] = MC_EXT_COLLISION;
+  else if (sqrt(s2) > 2.0 * dist[e]) result[e] = MC_EXT_TOO_FAR;
+}
+
+// Level bookkeeping, one thread per extension: applies the previous level's failure code, ends
+// extensions whose chain meets the resolution, and gives each extension that goes on a slot of
+// the level's batch (wave-aggregated atomic).
+__global__ void k_ext_level(int64_t E, int n, int level, int lmax, double delta, int8_t* result, int32_t* npts,
+                            int32_t* code, unsigned long long* maxgap, int32_t* slot_ext, unsigned int* count) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  bool alive = false;
+  if (e < E && result[e] == kExtRunning) {
+    if (level > 0) {
+      if (code[e] != kExtNone) {
+        result[e] = int8_t(code[e]);
+      } else if (__longlong_as_double((long long)maxgap[e]) <= delta || level > lmax) {
+        result[e] = MC_EXT_OK;
+        npts[e] = int32_t((int64_t(n) + 1) << (level - 1)) + 1;
+      } else {
+        alive = true;
+      }
+    } else {
+      alive = true;
+    }
+    if (level > lmax) alive = false;
+    if (alive) {
+      code[e] = kExtNone;
+      maxgap[e] = 0ull;
+    }
+  }
+  const uint64_t m = uint64_t(__ballot(alive));
+  if (m == 0) return;
+  const int lane = int(threadIdx.x & 63);
+  const int leader = __builtin_ctzll(m);
+  unsigned int base = 0;
+  if (lane == leader) base = atomicAdd(count, (unsigned int)__builtin_popcountll(m));
+  base = __shfl(base, leader);
+  if (alive) slot_ext[base + __builtin_popcountll(m & ((1ull << lane) - 1ull))] = int32_t(e);
+}
+
+// where point j of a level sits in the chain, and its two neighbours
+__device__ __forceinline__ void ext_positions(int level, int64_t H, int64_t j, int64_t& pos, int64_t& lo, int64_t& hi) {
+  if (level == 0) {
+    pos = (j + 1) * H;
+    lo = j * H;
+    hi = (j + 2) * H;
+  } else {
+    const int64_t h = H >> level;
+    pos = (2 * j + 1) * h;
+    lo = 2 * j * h;
+    hi = (2 * j + 2) * h;
+  }
+}
+
+// the level's new points: level 0 interpolates s + k/(n+1) (q_proj - s), later levels take the
+// midpoint of every gap
+template <class T>
+__global__ void k_ext_emit(int64_t total, int64_t per, int n, int d, int level, int64_t E, const double* chain,
+                           int64_t K, int64_t H, const int32_t* slot_ext, T* pts, int64_t ldx) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int64_t e = slot_ext[g / per], j = g % per;
+  int64_t pos, lo, hi;
+  ext_positions(level, H, j, pos, lo, hi);
+  const double* c = chain + e * K;
+  const int64_t cs = E * K;
+  if (level == 0) {
+    const double t = double(j + 1) / double(n + 1);
+    const int64_t end = (int64_t(n) + 1) * H;
+    for (int k = 0; k < d; ++k) {
+      const double a = c[k * cs], b = c[k * cs + end];
+      pts[k * ldx + g] = T(a + t * (b - a));
+    }
+  } else {
+    for (int k = 0; k < d; ++k) pts[k * ldx + g] = T(0.5 * (c[k * cs + lo] + c[k * cs + hi]));
+  }
+}
+
+// projected points into the chain, with their convergence and collision failures
+template <class T>
+__global__ void k_ext_store(int64_t total, int64_t per, int d, int level, int64_t E, double* chain, int64_t K,
+                            int64_t H, const int32_t* slot_ext, const T* pout, int64_t ldx, const int8_t* st,
+                            const uint8_t* vd, int32_t* code) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int64_t e = slot_ext[g / per], j = g % per;
+  int64_t pos, lo, hi;
+  ext_positions(level, H, j, pos, lo, hi);
+  for (int k = 0; k < d; ++k) chain[k * E * K + e * K + pos] = double(pout[k * ldx + g]);
+  if (st[g] != ST_CONVERGED) atomicMin(code + e, int32_t(MC_EXT_INTERP_FAILED));
+  else if (vd[g] != V_FREE) atomicMin(code + e, int32_t(MC_EXT_INTERP_COLLISION));
+}
+
+// the two gaps next to each new point against the level's bound r / (n 2^level); the longest
+// gap of each extension (non-negative doubles order like their bit patterns)
+__global__ void k_ext_gaps(int64_t total, int64_t per, int d, int level, int64_t E, const double* chain, int64_t K,
+                           int64_t H, const int32_t* slot_ext, double bound, int32_t* code, unsigned long long* maxgap) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int64_t e = slot_ext[g / per], j = g % per;
+  int64_t pos, lo, hi;
+  ext_positions(level, H, j, pos, lo, hi);
+  const double* c = chain + e * K;
+  const int64_t cs = E * K;
+  double a2 = 0.0, b2 = 0.0;
+  for (int k = 0; k < d; ++k) {
+    const double x = c[k * cs + pos];
+    const double u = x - c[k * cs + lo], w = c[k * cs + hi] - x;
+    a2 += u * u;
+    b2 += w * w;
+  }
+  const double gap = fmax(sqrt(a2), sqrt(b2));
+  if (gap > bound) atomicMin(code + e, int32_t(MC_EXT_GAP));
+  atomicMax(maxgap + e, (unsigned long long)__double_as_longlong(gap));
+}
+
 }  // namespace
 
 struct mc_problem {
@@ -486,6 +679,10 @@ struct mc_problem {
   // resident workgroups per CU of the persistent kernel, by (FP64 mode, waves per block = 1, 2, 4);
   // queried once, so later calls (and calls under stream capture) make no runtime query
   mutable int occ[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  // extend_batch workspace (particle and level batches, chains, per-extension state), grown to
+  // the largest call
+  mutable unsigned char* x_arena = nullptr;
+  mutable size_t x_bytes = 0;
 };
 
 // Grow a tail queue to hold n entries (synchronises the device when it reallocates).
@@ -552,6 +749,7 @@ void mc_problem_destroy(mc_problem* p) {
   hipFree(p->chk_q);
   hipFree(p->chk_idx);
   hipFree(p->vjp_idx);
+  hipFree(p->x_arena);
   delete p;
 }
 
@@ -973,6 +1171,147 @@ mc_status mc_eval_residual_jacobian(const mc_problem* p, int64_t n, const void* 
   hipError_t e = ops->eval_fj(p->dev, n, q, ld, F, J, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "mc_eval_residual_jacobian: launch");
   return MC_OK;
+}
+
+}  // extern "C"
+
+// extend_batch workspace: every buffer 256-byte aligned inside one arena
+struct ExtWs {
+  double *pin, *pout, *chain, *rs, *dist;
+  int8_t *st, *it;
+  uint8_t* vd;
+  int32_t *code, *slot_ext;
+  unsigned long long* maxgap;
+  unsigned int* count;
+};
+static size_t ext_layout(int64_t E, int64_t EK, int d, unsigned char* base, ExtWs* w) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* ptr = base ? base + off : nullptr;
+    off += (bytes + 255) & ~size_t(255);
+    return ptr;
+  };
+  unsigned char* pin = take(size_t(d) * EK * 8);
+  unsigned char* pout = take(size_t(d) * EK * 8);
+  unsigned char* chain = take(size_t(d) * EK * 8);
+  unsigned char* rs = take(size_t(EK) * 8);
+  unsigned char* dist = take(size_t(E) * 8);
+  unsigned char* st = take(size_t(EK));
+  unsigned char* it = take(size_t(EK));
+  unsigned char* vd = take(size_t(EK));
+  unsigned char* code = take(size_t(E) * 4);
+  unsigned char* slot = take(size_t(E) * 4);
+  unsigned char* mg = take(size_t(E) * 8);
+  unsigned char* cnt = take(4);
+  if (w) {
+    w->pin = reinterpret_cast<double*>(pin);
+    w->pout = reinterpret_cast<double*>(pout);
+    w->chain = reinterpret_cast<double*>(chain);
+    w->rs = reinterpret_cast<double*>(rs);
+    w->dist = reinterpret_cast<double*>(dist);
+    w->st = reinterpret_cast<int8_t*>(st);
+    w->it = reinterpret_cast<int8_t*>(it);
+    w->vd = reinterpret_cast<uint8_t*>(vd);
+    w->code = reinterpret_cast<int32_t*>(code);
+    w->slot_ext = reinterpret_cast<int32_t*>(slot);
+    w->maxgap = reinterpret_cast<unsigned long long*>(mg);
+    w->count = reinterpret_cast<unsigned int*>(cnt);
+  }
+  return off;
+}
+
+template <class T>
+static mc_status extend_impl(const mc_problem* p, int64_t E, const T* qs, const T* qt, int64_t ld, const T* eps,
+                             const mc_extend_opts* xo, const mc_project_opts* opts, T* q_out, int64_t ld_out,
+                             int8_t* result, int32_t* particle, int32_t* npts, int lmax, hipStream_t s) {
+  const int n = xo->n, d = p->d;
+  const int64_t H = int64_t(1) << lmax, K = (int64_t(n) + 1) * H + 1, EK = E * K;
+  const size_t need = ext_layout(E, EK, d, nullptr, nullptr);
+  hipError_t e;
+  if (need > p->x_bytes) {
+    if (p->x_arena && (e = hipFree(p->x_arena)) != hipSuccess) return hip_fail(e, "extend_batch: free workspace");
+    p->x_arena = nullptr;
+    p->x_bytes = 0;
+    if ((e = hipMalloc((void**)&p->x_arena, need)) != hipSuccess) return hip_fail(e, "extend_batch: workspace");
+    p->x_bytes = need;
+  }
+  ExtWs w;
+  ext_layout(E, EK, d, p->x_arena, &w);
+  T* pin = reinterpret_cast<T*>(w.pin);
+  T* pout = reinterpret_cast<T*>(w.pout);
+  mc_project_opts o = *opts;
+  o.check_collision = 1;
+  o.variant = 2;
+  const int64_t np = E * n;
+  hipLaunchKernelGGL(k_ext_particles<T>, dim3((np + 255) / 256), dim3(256), 0, s, E, n, d, qs, qt, ld, eps, xo->r,
+                     pin, EK, w.dist, result, particle, npts);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "extend_batch: particles");
+  mc_status st = project_batch(p, np, pin, EK, pout, EK, w.st, w.it, w.rs, w.vd, nullptr, nullptr, 0, nullptr, &o, s);
+  if (st != MC_OK) return st;
+  hipLaunchKernelGGL(k_ext_select<T>, dim3((E + 255) / 256), dim3(256), 0, s, E, n, d, qs, ld, pout, EK, w.st, w.it,
+                     w.vd, w.dist, result, particle, q_out, ld_out, w.chain, K, H);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "extend_batch: select");
+  for (int level = 0; level <= lmax + 1; ++level) {
+    hipLaunchKernelGGL(k_reset_u32, dim3(1), dim3(64), 0, s, w.count, 1);
+    hipLaunchKernelGGL(k_ext_level, dim3((E + 255) / 256), dim3(256), 0, s, E, n, level, lmax, xo->delta, result, npts,
+                       w.code, w.maxgap, w.slot_ext, w.count);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "extend_batch: level");
+    if (level > lmax) break;
+    unsigned int alive = 0;
+    if ((e = hipMemcpyAsync(&alive, w.count, sizeof alive, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return hip_fail(e, "extend_batch: read level size");
+    if (alive == 0) break;
+    const int64_t per = level == 0 ? int64_t(n) : (int64_t(n) + 1) << (level - 1);
+    const int64_t total = int64_t(alive) * per;
+    const dim3 g((total + 255) / 256), b(256);
+    hipLaunchKernelGGL(k_ext_emit<T>, g, b, 0, s, total, per, n, d, level, E, w.chain, K, H, w.slot_ext, pin, EK);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "extend_batch: emit");
+    st = project_batch(p, total, pin, EK, pout, EK, w.st, w.it, w.rs, w.vd, nullptr, nullptr, 0, nullptr, &o, s);
+    if (st != MC_OK) return st;
+    hipLaunchKernelGGL(k_ext_store<T>, g, b, 0, s, total, per, d, level, E, w.chain, K, H, w.slot_ext, pout, EK, w.st,
+                       w.vd, w.code);
+    const double bound = xo->r / (double(n) * double(int64_t(1) << level));
+    hipLaunchKernelGGL(k_ext_gaps, g, b, 0, s, total, per, d, level, E, w.chain, K, H, w.slot_ext, bound, w.code,
+                       w.maxgap);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "extend_batch: validate");
+  }
+  return MC_OK;
+}
+
+extern "C" {
+
+mc_status extend_batch(const mc_problem* p, int64_t E, const void* q_start, const void* q_target, int64_t ld,
+                       const void* eps, const mc_extend_opts* xo, const mc_project_opts* opts, void* q_out,
+                       int64_t ld_out, int8_t* result, int32_t* particle, int32_t* n_points, void* stream) {
+  g_err.clear();
+  if (!p) return fail(MC_ERR_INVALID_ARG, "extend_batch: null problem");
+  if (E < 0) return fail(MC_ERR_INVALID_ARG, "extend_batch: E < 0");
+  mc_status st = check_opts(p, opts);
+  if (st != MC_OK) return st;
+  if (!xo) return fail(MC_ERR_INVALID_ARG, "extend_batch: null extend options");
+  if (!(xo->r > 0) || !std::isfinite(xo->r)) return fail(MC_ERR_INVALID_ARG, "extend_batch: r must be > 0");
+  if (!(xo->delta > 0) || !std::isfinite(xo->delta)) return fail(MC_ERR_INVALID_ARG, "extend_batch: delta must be > 0");
+  if (xo->n < 1 || xo->n > 64) return fail(MC_ERR_INVALID_ARG, "extend_batch: n must be in 1..64");
+  int lmax = 0;
+  while (xo->r / (double(xo->n) * double(int64_t(1) << lmax)) > xo->delta) {
+    if (++lmax > 12) return fail(MC_ERR_INVALID_ARG, "extend_batch: r / (n delta) needs more than 12 levels");
+  }
+  if ((int64_t(xo->n) + 1) << lmax > 65535) return fail(MC_ERR_INVALID_ARG, "extend_batch: chain longer than 65536");
+  if (E == 0) return MC_OK;
+  if (!q_start || !q_target || !eps || !q_out || !result || !particle || !n_points)
+    return fail(MC_ERR_INVALID_ARG, "extend_batch: null array");
+  if (ld < E || ld_out < E) return fail(MC_ERR_INVALID_ARG, "extend_batch: ld < E");
+  const int64_t K = ((int64_t(xo->n) + 1) << lmax) + 1;
+  if (E * K > (int64_t(1) << 31) - 1) return fail(MC_ERR_INVALID_ARG, "extend_batch: E times the chain length too large");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (opts->dtype == MC_F64)
+    return extend_impl<double>(p, E, static_cast<const double*>(q_start), static_cast<const double*>(q_target), ld,
+                               static_cast<const double*>(eps), xo, opts, static_cast<double*>(q_out), ld_out, result,
+                               particle, n_points, lmax, s);
+  return extend_impl<float>(p, E, static_cast<const float*>(q_start), static_cast<const float*>(q_target), ld,
+                            static_cast<const float*>(eps), xo, opts, static_cast<float*>(q_out), ld_out, result,
+                            particle, n_points, lmax, s);
 }
 
 mc_status mc_fallback_count(const mc_problem* p, int reset, uint64_t* count) {

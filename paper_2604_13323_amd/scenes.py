@@ -22,7 +22,7 @@ in the equality-to-centroid form) plus the synthetic sphere, axis-alignment
 and linear constraints used for closed-form checks.
 
 RNG: numpy PCG64 seeded with [config_id, stream]; streams 0 robot, 1 obstacles,
-2 workload, 3 finite-difference sample.
+2 workload, 3 finite-difference sample, 4 geodesic lengths, 5 extension particle draws.
 """
 from __future__ import annotations
 
@@ -512,3 +512,47 @@ def make_config(name: str, small: bool = False):
                     endpoints=raw_endpoints(sc, 4, n_geo, humanoid_noise_sigma()),
                     geo_offsets=geodesic_lengths(4, n_geo, 8, 64))
     raise ValueError(name)
+
+
+# ---- ConstrainedExtend workloads --------------------------------------------
+# Extension parameters per configuration: range r, resolution delta, particles n, particle spread
+# sigma (the paper tunes r and sigma per robot and does not list the values; these keep the
+# steer point within a few Newton steps of the manifold).
+EXTEND_PARAMS = {
+    "c0": dict(r=0.5, delta=0.05, n=8, sigma=0.1),
+    "c1": dict(r=0.4, delta=0.05, n=8, sigma=0.05),
+    "c3": dict(r=0.3, delta=0.02, n=8, sigma=0.05),
+}
+
+
+def extend_workload(name: str, E: int):
+    """Raw inputs of E extensions on configuration `name`: starts [E, d] (raw: the consumer projects
+    them onto the manifold first, except on the sphere where they are unit vectors already),
+    targets [E, d] (ambient points, like RRT's random samples) and the particle draws eps [E, n]
+    ~ N(0, sigma^2). Returns dict(scene, starts, targets, eps, starts_on_manifold, **EXTEND_PARAMS)."""
+    prm = EXTEND_PARAMS[name]
+    cid = CONFIG_IDS[name]
+    r5 = rng_for(cid, 5)
+    if name == "c0":
+        sc = sphere_scene(0)
+        r2 = rng_for(cid, 2)
+        starts = _uniform_sphere_points(r2, E)
+        dirs = _uniform_sphere_points(r2, E)
+        targets = starts + dirs * r2.uniform(0.2, 1.5, (E, 1))
+        on = True
+    elif name == "c1":
+        sc = arm7_axis_scene(1)
+        r2 = rng_for(cid, 2)
+        starts = r2.uniform(-np.pi, np.pi, (E, 7))
+        targets = starts + r2.normal(0.0, 0.5, (E, 7))
+        on = False
+    elif name == "c3":
+        sc = humanoid36_scene(3)
+        ends = raw_endpoints(sc, 3, E, humanoid_noise_sigma())
+        starts, targets = ends[:, 0], ends[:, 1]
+        on = False
+    else:
+        raise ValueError(name)
+    eps = r5.normal(0.0, prm["sigma"], (E, prm["n"]))
+    return dict(name=name, scene=sc, starts=np.ascontiguousarray(starts), targets=np.ascontiguousarray(targets),
+                eps=eps, starts_on_manifold=on, tol=1e-6, max_iter={"c0": 50, "c1": 30, "c3": 40}[name], **prm)

@@ -35,7 +35,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("project_batch", "check_batch", "project_vjp", "mc_problem_create", "mc_problem_destroy",
               "mc_last_error", "mc_default_opts", "interpolate_geodesics", "path_length_grad",
-              "mc_eval_residual_jacobian", "mc_fallback_count"):
+              "mc_eval_residual_jacobian", "mc_fallback_count", "extend_batch"):
         assert n in names, n
 
 
@@ -76,6 +76,9 @@ def test_calls_reject_a_null_problem(L):
                            ctypes.byref(o), None) == MC_ERR_INVALID_ARG
     assert L.check_batch(None, 8, None, 8, 0, None, None, None) == MC_ERR_INVALID_ARG
     assert L.project_vjp(None, 8, None, 8, None, None, None, ctypes.byref(o), None) == MC_ERR_INVALID_ARG
+    xo = binding.ExtendOpts(r=0.5, delta=0.05, n=8)
+    assert L.extend_batch(None, 8, None, None, 8, None, ctypes.byref(xo), ctypes.byref(o), None, 8, None, None, None,
+                          None) == MC_ERR_INVALID_ARG
     assert L.mc_problem_dof(None) == -1 and L.mc_problem_rows(None) == -1
 
 
