@@ -302,6 +302,14 @@ __device__ __forceinline__ int finish_fp64(const QLds& q, const QLds& q0, int& k
   return st;
 }
 
+// Configuration dimension: a compile-time constant where the model fixes it (the per-coordinate
+// guards of the load and store loops then fold away), else the scene's value.
+template <class Model>
+__device__ __forceinline__ int dof_of(const Consts& C) {
+  if constexpr (Model::fixed_dof) return Model::D;
+  else return C.dof;
+}
+
 // Column c of configuration i in a [D][ld] array sits at (c ld + i); the pointer is bumped by
 // an opaque ld so the D addresses are formed one after another rather than all up front.
 template <class Model, class IO>
@@ -372,7 +380,7 @@ template <class Model, class IO, class S, bool CYC = false>
 __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
   extern __shared__ double smem[];
   const Consts& C = consts_of(a.P);
-  const int dof = C.dof;
+  const int dof = dof_of<Model>(C);
   const QLds q = q_lds<Model::D>(smem);
   const QLds q0 = q_lds<Model::D>(smem + (CYC ? Model::D * blockDim.x : 0));  // cyclic: iterate at iteration start
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -463,7 +471,7 @@ template <class Model, class IO, bool CYC = false>
 __global__ void __launch_bounds__(64) k_project_tail(ProjArgs a) {
   extern __shared__ double smem[];
   const Consts& C = consts_of(a.P);
-  const int dof = C.dof;
+  const int dof = dof_of<Model>(C);
   const QLds q = q_lds<Model::D>(smem);
   const QLds q0 = q_lds<Model::D>(smem + (CYC ? Model::D * blockDim.x : 0));
   const int64_t cnt = *a.defer_count;
@@ -486,7 +494,7 @@ template <class Model, class IO, class S>
 __global__ void __launch_bounds__(64) k_project_plain(ProjArgs a) {
   extern __shared__ double smem[];
   const Consts& C = consts_of(a.P);
-  const int dof = C.dof;
+  const int dof = dof_of<Model>(C);
   const QLds q = q_lds<Model::D>(smem);
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
@@ -536,7 +544,7 @@ __global__ void __launch_bounds__(256) k_check(CheckArgs a) {
     if (lead) a.verdict[i] = V_UNCHECKED;
     return;
   }
-  const QGlob<IO> q{static_cast<const IO*>(a.q), a.ld, i, C.dof};
+  const QGlob<IO> q{static_cast<const IO*>(a.q), a.ld, i, dof_of<Model>(C)};
   if constexpr (MINSD) {
     static_assert(L == 1, "the exhaustive distance runs one lane per configuration");
     bool hit;
@@ -617,7 +625,7 @@ __global__ void __launch_bounds__(256) k_vjp(VjpArgs a) {
   const QLds q = q_lds<Model::D>(smem);
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  const int dof = C.dof;
+  const int dof = dof_of<Model>(C);
   double out[D];
   if (a.status[i] != ST_CONVERGED) {
     for (int c = 0; c < D; ++c) out[c] = 0.0;
@@ -654,7 +662,7 @@ __global__ void __launch_bounds__(64) k_vjp_tail(VjpArgs a) {
   constexpr int D = Model::D;
   extern __shared__ double smem[];
   const Consts& C = consts_of(a.P);
-  const int dof = C.dof;
+  const int dof = dof_of<Model>(C);
   const QLds q = q_lds<Model::D>(smem);
   const int64_t cnt = *a.defer_count;
   for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < cnt; s += int64_t(gridDim.x) * blockDim.x) {

@@ -234,6 +234,7 @@ template <class Topo>
 struct Kin {
   using KI = KInfo<Topo>;
   static constexpr int NJ = Topo::NJ, NB = Topo::NB, NF = Topo::NF, M = Topo::M, D = Topo::NJ;
+  static constexpr bool fixed_dof = true;  // a scene of this family has exactly D coordinates
   static constexpr int family = Topo::family;
   static constexpr bool broad_in_residual = true;  // broad_flag() tests the link bounds against the obstacle box
   static constexpr int NBLK = NB;                  // constraint blocks (the cyclic mode steps them in order)
@@ -438,7 +439,9 @@ struct Kin {
         if constexpr (!Topo::massless(j)) {
           double t[3];
           matvec3(X.R, jp.mc, t);
-          for (int k = 0; k < 3; ++k) cm[k] += t[k] + jp.m * X.p[k];
+          // accumulated here, at its joint: the link's mass constants are then dead at once
+          // instead of being kept (spilled) until the CoM rows at the end of the walk
+          for (int k = 0; k < 3; ++k) cm[k] = opaque(cm[k] + t[k] + jp.m * X.p[k]);
         }
         if constexpr (KI::end_needed(j + 1)) {
           for (int k = 0; k < 3; ++k) sd.Qe[j + 1][k] = S(cm[k]);

@@ -43,6 +43,7 @@ struct SphereModel {
   static constexpr int family = 0;
   static constexpr bool broad_in_residual = false;  // the exact check is cheap: run it at convergence
   static constexpr int D = 3, M = 1;
+  static constexpr bool fixed_dof = false;  // the scene's d (at most D) is read at run time
   static constexpr int NBLK = 1;
   static constexpr uint32_t ALL = ~uint32_t(0);
   static constexpr uint32_t block_rows_mask(int) { return ALL; }
@@ -103,6 +104,7 @@ struct LinearModel {
   static constexpr int family = 1;
   static constexpr bool broad_in_residual = false;  // the exact check is cheap: run it at convergence
   static constexpr int D = LIN_D, M = LIN_M;
+  static constexpr bool fixed_dof = false;  // the scene's d (at most D) is read at run time
   static constexpr int NBLK = 1;
   static constexpr uint32_t ALL = ~uint32_t(0);
   static constexpr uint32_t block_rows_mask(int) { return ALL; }
