@@ -466,28 +466,22 @@ __global__ void k_geo_ok(int n_geo, const int32_t* offs, int64_t n, const int8_t
 
 // ------------------------------------------------------------ ConstrainedExtend
 // Alg. 2 ConstrainedExtend batched over independent extensions. Each extension keeps a chain of
-// K = (n + 1) 2^Lmax + 1 slots ([d][E K], slot e K + pos): level 0 fills positions k 2^Lmax,
-// level l the odd multiples of 2^(Lmax - l). The projections run in project_batch; these kernels
-// build the batches and take the decisions.
+// K = (n + 1) 2^Lmax + 1 points in the call's element type (every chain point is a start or a
+// projected point of that type), stored position-major ([d][K][E]: coordinate k of position pos
+// of extension e at (k K + pos) E + e, so threads of neighbouring extensions touch neighbouring
+// addresses): level 0 fills positions k 2^Lmax, level l the odd multiples of 2^(Lmax - l).
+// Particles are numbered i E + e. The projections run in project_batch; these kernels build the
+// batches and take the decisions.
 constexpr int kExtRunning = -1;
 constexpr int kExtNone = 127;  // no failure recorded at this level
 
-__device__ __forceinline__ double ext_norm_diff(const double* a, const double* b, int d) {
-  double s = 0.0;
-  for (int c = 0; c < d; ++c) {
-    const double t = a[c] - b[c];
-    s += t * t;
-  }
-  return sqrt(s);
-}
-
-// particles p_i = q_steer + eps_i v (one thread per particle)
+// particles p_i = q_steer + eps_i v (one thread per particle, particle i of extension e at i E + e)
 template <class T>
 __global__ void k_ext_particles(int64_t E, int n, int d, const T* qs, const T* qt, int64_t ld, const T* eps, double r,
                                 T* part, int64_t ldp, double* dist, int8_t* result, int32_t* particle, int32_t* npts) {
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (g >= E * n) return;
-  const int64_t e = g / n;
+  const int64_t i = g / E, e = g - i * E;
   double L2 = 0.0;
   for (int c = 0; c < d; ++c) {
     const double t = double(qt[c * ld + e]) - double(qs[c * ld + e]);
@@ -495,13 +489,13 @@ __global__ void k_ext_particles(int64_t E, int n, int d, const T* qs, const T* q
   }
   const double L = sqrt(L2);
   const double ds = L < r ? L : r;
-  const double ep = double(eps[g]);
+  const double ep = double(eps[e * n + i]);
   for (int c = 0; c < d; ++c) {
     const double a = double(qs[c * ld + e]);
     const double v = L > 0.0 ? (double(qt[c * ld + e]) - a) / L : 0.0;
     part[c * ldp + g] = T(a + ds * v + ep * v);
   }
-  if (g % n == 0) {
+  if (i == 0) {
     dist[e] = ds;
     result[e] = L > 0.0 ? int8_t(kExtRunning) : int8_t(MC_EXT_ZERO);
     particle[e] = -1;
@@ -513,12 +507,12 @@ __global__ void k_ext_particles(int64_t E, int n, int d, const T* qs, const T* q
 template <class T>
 __global__ void k_ext_select(int64_t E, int n, int d, const T* qs, int64_t ld, const T* pout, int64_t ldp,
                              const int8_t* st, const int8_t* it, const uint8_t* vd, const double* dist, int8_t* result,
-                             int32_t* particle, T* q_out, int64_t ld_out, double* chain, int64_t K, int64_t H) {
+                             int32_t* particle, T* q_out, int64_t ld_out, T* chain, int64_t K, int64_t H) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= E || result[e] != kExtRunning) return;
   int best = -1, best_it = 1 << 30;
   for (int i = 0; i < n; ++i) {
-    const int64_t g = e * n + i;
+    const int64_t g = int64_t(i) * E + e;
     if (st[g] == ST_CONVERGED && int(it[g]) < best_it) {
       best = i;
       best_it = it[g];
@@ -529,15 +523,15 @@ __global__ void k_ext_select(int64_t E, int n, int d, const T* qs, int64_t ld, c
     return;
   }
   particle[e] = best;
-  const int64_t g = e * n + best;
-  double* c0 = chain + e * K;
-  double* c1 = chain + e * K + (n + 1) * H;
+  const int64_t g = int64_t(best) * E + e;
+  const int64_t cs = E * K, end = (int64_t(n) + 1) * H * E;
   double s2 = 0.0;
   for (int c = 0; c < d; ++c) {
-    const double a = double(qs[c * ld + e]), b = double(pout[c * ldp + g]);
-    c0[c * E * K] = a;
-    c1[c * E * K] = b;
-    q_out[c * ld_out + e] = pout[c * ldp + g];
+    const T qa = qs[c * ld + e], qb = pout[c * ldp + g];
+    const double a = double(qa), b = double(qb);
+    chain[c * cs + e] = qa;
+    chain[c * cs + end + e] = qb;
+    q_out[c * ld_out + e] = qb;
     s2 += (b - a) * (b - a);
   }
   if (vd[g] != V_FREE) result[e] = MC_EXT_COLLISION;
@@ -580,80 +574,86 @@ __global__ void k_ext_level(int64_t E, int n, int level, int lmax, double delta,
   if (alive) slot_ext[base + __builtin_popcountll(m & ((1ull << lane) - 1ull))] = int32_t(e);
 }
 
-// where point j of a level sits in the chain, and its two neighbours
-__device__ __forceinline__ void ext_positions(int level, int64_t H, int64_t j, int64_t& pos, int64_t& lo, int64_t& hi) {
+// Point g of a level's batch: new point j of the extension in slot s, numbered g = j alive + s
+// (neighbouring threads: the same point of neighbouring extensions). Its chain position and the
+// positions of its two neighbours.
+struct ExtPoint {
+  int64_t e, j, pos, lo, hi;
+};
+__device__ __forceinline__ ExtPoint ext_point(int64_t g, int64_t alive, int level, int64_t H, const int32_t* slot_ext) {
+  ExtPoint p;
+  p.j = g / alive;
+  p.e = slot_ext[g - p.j * alive];
   if (level == 0) {
-    pos = (j + 1) * H;
-    lo = j * H;
-    hi = (j + 2) * H;
+    p.pos = (p.j + 1) * H;
+    p.lo = p.j * H;
+    p.hi = (p.j + 2) * H;
   } else {
     const int64_t h = H >> level;
-    pos = (2 * j + 1) * h;
-    lo = 2 * j * h;
-    hi = (2 * j + 2) * h;
+    p.pos = (2 * p.j + 1) * h;
+    p.lo = 2 * p.j * h;
+    p.hi = (2 * p.j + 2) * h;
   }
+  return p;
 }
 
 // the level's new points: level 0 interpolates s + k/(n+1) (q_proj - s), later levels take the
 // midpoint of every gap
 template <class T>
-__global__ void k_ext_emit(int64_t total, int64_t per, int n, int d, int level, int64_t E, const double* chain,
+__global__ void k_ext_emit(int64_t total, int64_t alive, int n, int d, int level, int64_t E, const T* chain,
                            int64_t K, int64_t H, const int32_t* slot_ext, T* pts, int64_t ldx) {
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (g >= total) return;
-  const int64_t e = slot_ext[g / per], j = g % per;
-  int64_t pos, lo, hi;
-  ext_positions(level, H, j, pos, lo, hi);
-  const double* c = chain + e * K;
+  const ExtPoint p = ext_point(g, alive, level, H, slot_ext);
+  const T* c = chain + p.e;
   const int64_t cs = E * K;
   if (level == 0) {
-    const double t = double(j + 1) / double(n + 1);
-    const int64_t end = (int64_t(n) + 1) * H;
+    const double t = double(p.j + 1) / double(n + 1);
+    const int64_t end = (int64_t(n) + 1) * H * E;
     for (int k = 0; k < d; ++k) {
-      const double a = c[k * cs], b = c[k * cs + end];
+      const double a = double(c[k * cs]), b = double(c[k * cs + end]);
       pts[k * ldx + g] = T(a + t * (b - a));
     }
   } else {
-    for (int k = 0; k < d; ++k) pts[k * ldx + g] = T(0.5 * (c[k * cs + lo] + c[k * cs + hi]));
+    for (int k = 0; k < d; ++k)
+      pts[k * ldx + g] = T(0.5 * (double(c[k * cs + p.lo * E]) + double(c[k * cs + p.hi * E])));
   }
 }
 
 // projected points into the chain, with their convergence and collision failures
 template <class T>
-__global__ void k_ext_store(int64_t total, int64_t per, int d, int level, int64_t E, double* chain, int64_t K,
+__global__ void k_ext_store(int64_t total, int64_t alive, int d, int level, int64_t E, T* chain, int64_t K,
                             int64_t H, const int32_t* slot_ext, const T* pout, int64_t ldx, const int8_t* st,
                             const uint8_t* vd, int32_t* code) {
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (g >= total) return;
-  const int64_t e = slot_ext[g / per], j = g % per;
-  int64_t pos, lo, hi;
-  ext_positions(level, H, j, pos, lo, hi);
-  for (int k = 0; k < d; ++k) chain[k * E * K + e * K + pos] = double(pout[k * ldx + g]);
-  if (st[g] != ST_CONVERGED) atomicMin(code + e, int32_t(MC_EXT_INTERP_FAILED));
-  else if (vd[g] != V_FREE) atomicMin(code + e, int32_t(MC_EXT_INTERP_COLLISION));
+  const ExtPoint p = ext_point(g, alive, level, H, slot_ext);
+  const int64_t cs = E * K;
+  for (int k = 0; k < d; ++k) chain[k * cs + p.pos * E + p.e] = pout[k * ldx + g];
+  if (st[g] != ST_CONVERGED) atomicMin(code + p.e, int32_t(MC_EXT_INTERP_FAILED));
+  else if (vd[g] != V_FREE) atomicMin(code + p.e, int32_t(MC_EXT_INTERP_COLLISION));
 }
 
 // the two gaps next to each new point against the level's bound r / (n 2^level); the longest
 // gap of each extension (non-negative doubles order like their bit patterns)
-__global__ void k_ext_gaps(int64_t total, int64_t per, int d, int level, int64_t E, const double* chain, int64_t K,
+template <class T>
+__global__ void k_ext_gaps(int64_t total, int64_t alive, int d, int level, int64_t E, const T* chain, int64_t K,
                            int64_t H, const int32_t* slot_ext, double bound, int32_t* code, unsigned long long* maxgap) {
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (g >= total) return;
-  const int64_t e = slot_ext[g / per], j = g % per;
-  int64_t pos, lo, hi;
-  ext_positions(level, H, j, pos, lo, hi);
-  const double* c = chain + e * K;
+  const ExtPoint p = ext_point(g, alive, level, H, slot_ext);
+  const T* c = chain + p.e;
   const int64_t cs = E * K;
   double a2 = 0.0, b2 = 0.0;
   for (int k = 0; k < d; ++k) {
-    const double x = c[k * cs + pos];
-    const double u = x - c[k * cs + lo], w = c[k * cs + hi] - x;
+    const double x = double(c[k * cs + p.pos * E]);
+    const double u = x - double(c[k * cs + p.lo * E]), w = double(c[k * cs + p.hi * E]) - x;
     a2 += u * u;
     b2 += w * w;
   }
   const double gap = fmax(sqrt(a2), sqrt(b2));
-  if (gap > bound) atomicMin(code + e, int32_t(MC_EXT_GAP));
-  atomicMax(maxgap + e, (unsigned long long)__double_as_longlong(gap));
+  if (gap > bound) atomicMin(code + p.e, int32_t(MC_EXT_GAP));
+  atomicMax(maxgap + p.e, (unsigned long long)__double_as_longlong(gap));
 }
 
 }  // namespace
@@ -1239,6 +1239,7 @@ static mc_status extend_impl(const mc_problem* p, int64_t E, const T* qs, const 
   ext_layout(E, EK, d, p->x_arena, &w);
   T* pin = reinterpret_cast<T*>(w.pin);
   T* pout = reinterpret_cast<T*>(w.pout);
+  T* chain = reinterpret_cast<T*>(w.chain);
   mc_project_opts o = *opts;
   o.check_collision = 1;
   o.variant = 2;
@@ -1249,7 +1250,7 @@ static mc_status extend_impl(const mc_problem* p, int64_t E, const T* qs, const 
   mc_status st = project_batch(p, np, pin, EK, pout, EK, w.st, w.it, w.rs, w.vd, nullptr, nullptr, 0, nullptr, &o, s);
   if (st != MC_OK) return st;
   hipLaunchKernelGGL(k_ext_select<T>, dim3((E + 255) / 256), dim3(256), 0, s, E, n, d, qs, ld, pout, EK, w.st, w.it,
-                     w.vd, w.dist, result, particle, q_out, ld_out, w.chain, K, H);
+                     w.vd, w.dist, result, particle, q_out, ld_out, chain, K, H);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "extend_batch: select");
   for (int level = 0; level <= lmax + 1; ++level) {
     hipLaunchKernelGGL(k_reset_u32, dim3(1), dim3(64), 0, s, w.count, 1);
@@ -1265,15 +1266,16 @@ static mc_status extend_impl(const mc_problem* p, int64_t E, const T* qs, const 
     const int64_t per = level == 0 ? int64_t(n) : (int64_t(n) + 1) << (level - 1);
     const int64_t total = int64_t(alive) * per;
     const dim3 g((total + 255) / 256), b(256);
-    hipLaunchKernelGGL(k_ext_emit<T>, g, b, 0, s, total, per, n, d, level, E, w.chain, K, H, w.slot_ext, pin, EK);
+    hipLaunchKernelGGL(k_ext_emit<T>, g, b, 0, s, total, int64_t(alive), n, d, level, E, chain, K, H, w.slot_ext,
+                       pin, EK);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "extend_batch: emit");
     st = project_batch(p, total, pin, EK, pout, EK, w.st, w.it, w.rs, w.vd, nullptr, nullptr, 0, nullptr, &o, s);
     if (st != MC_OK) return st;
-    hipLaunchKernelGGL(k_ext_store<T>, g, b, 0, s, total, per, d, level, E, w.chain, K, H, w.slot_ext, pout, EK, w.st,
-                       w.vd, w.code);
+    hipLaunchKernelGGL(k_ext_store<T>, g, b, 0, s, total, int64_t(alive), d, level, E, chain, K, H, w.slot_ext, pout,
+                       EK, w.st, w.vd, w.code);
     const double bound = xo->r / (double(n) * double(int64_t(1) << level));
-    hipLaunchKernelGGL(k_ext_gaps, g, b, 0, s, total, per, d, level, E, w.chain, K, H, w.slot_ext, bound, w.code,
-                       w.maxgap);
+    hipLaunchKernelGGL(k_ext_gaps<T>, g, b, 0, s, total, int64_t(alive), d, level, E, chain, K, H, w.slot_ext, bound,
+                       w.code, w.maxgap);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "extend_batch: validate");
   }
   return MC_OK;
