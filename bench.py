@@ -163,7 +163,7 @@ def cyclic_row(G, q_in, out, kw, args, torch):
     return cyclic
 
 
-def extend_row(M, S, G, torch, steps):
+def extend_row(M, S, G, torch, steps, shape):
     """Alg. 2 ConstrainedExtend batched (extend_batch) on the humanoid: 8,192 extensions of 8
     particles each (65,536 particle projections, as many lanes as the headline batch), then the
     interpolation and refinement levels of every surviving extension."""
@@ -176,7 +176,7 @@ def extend_row(M, S, G, torch, steps):
     qt = qt.contiguous()
     eps = torch.from_numpy(w["eps"]).to("cuda", torch.float32).index_select(0, keep).contiguous()
     E = qs.shape[1]
-    call = lambda: G.extend(qs, qt, eps, w["r"], w["delta"], tol=w["tol"], max_iter=w["max_iter"])
+    call = lambda: G.extend(qs, qt, eps, w["r"], w["delta"], tol=w["tol"], max_iter=w["max_iter"], **shape)
     r = call()
     ms = timed(call, steps, 1, torch, "extend")
     code = r.result.cpu().numpy()
@@ -330,7 +330,8 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
-    ext = None if args.no_extend else extend_row(M, S, G, torch, min(args.steps, 10))
+    ext = None if args.no_extend else extend_row(M, S, G, torch, min(args.steps, 10),
+                                                 {k: kw[k] for k in ("waves_per_block", "blocks_per_cu")})
     others = None if args.no_others else other_workloads(M, S, FL, torch, args.steps)
 
     cpu = None

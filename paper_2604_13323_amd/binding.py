@@ -222,7 +222,8 @@ class Problem:
         return out
 
     def extend(self, q_start: torch.Tensor, q_target: torch.Tensor, eps: torch.Tensor, r: float, delta: float,
-               tol=1e-6, max_iter=50, max_step=0.0, cond=1e6, mode="stacked") -> ExtendResult:
+               tol=1e-6, max_iter=50, max_step=0.0, cond=1e6, mode="stacked", waves_per_block=0,
+               blocks_per_cu=0) -> ExtendResult:
         """ConstrainedExtend for E extensions: q_start, q_target [d, E] (same dtype and strides), eps [E, n] the
         particle offsets along the extension direction (the N(0, sigma^2) draws)."""
         E, ld = _soa(q_start, self.d, "extend")
@@ -237,7 +238,8 @@ class Problem:
                            particle=torch.empty(E, dtype=torch.int32, device=dev),
                            n_points=torch.empty(E, dtype=torch.int32, device=dev))
         xo = ExtendOpts(r=float(r), delta=float(delta), n=int(n))
-        o = make_opts(_dtype_code(q_start), tol, max_iter, max_step=max_step, cond=cond, mode=mode)
+        o = make_opts(_dtype_code(q_start), tol, max_iter, max_step=max_step, cond=cond, mode=mode,
+                      waves_per_block=waves_per_block, blocks_per_cu=blocks_per_cu)
         _check(lib().extend_batch(self._h, E, _ptr(q_start), _ptr(q_target), ld, _ptr(eps), ctypes.byref(xo),
                                   ctypes.byref(o), _ptr(out.q), out.q.stride(0), _ptr(out.result), _ptr(out.particle),
                                   _ptr(out.n_points), _stream()), "extend_batch")

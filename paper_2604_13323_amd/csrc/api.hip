@@ -475,26 +475,35 @@ __global__ void k_geo_ok(int n_geo, const int32_t* offs, int64_t n, const int8_t
 constexpr int kExtRunning = -1;
 constexpr int kExtNone = 127;  // no failure recorded at this level
 
+// The glue kernels below read every coordinate they need into registers first (a fixed trip
+// count of kMaxD with guards, fully unrolled), so each thread waits for memory once.
+
 // particles p_i = q_steer + eps_i v (one thread per particle, particle i of extension e at i E + e)
 template <class T>
-__global__ void k_ext_particles(int64_t E, int n, int d, const T* qs, const T* qt, int64_t ld, const T* eps, double r,
+__global__ void __launch_bounds__(256) k_ext_particles(int64_t E, int n, int d, const T* qs, const T* qt, int64_t ld, const T* eps, double r,
                                 T* part, int64_t ldp, double* dist, int8_t* result, int32_t* particle, int32_t* npts) {
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (g >= E * n) return;
   const int64_t i = g / E, e = g - i * E;
+  double a[kMaxD], v[kMaxD];
+#pragma unroll
+  for (int c = 0; c < kMaxD; ++c) {
+    a[c] = c < d ? double(qs[c * ld + e]) : 0.0;
+    v[c] = c < d ? double(qt[c * ld + e]) : 0.0;
+  }
+  const double ep = double(eps[e * n + i]);
   double L2 = 0.0;
-  for (int c = 0; c < d; ++c) {
-    const double t = double(qt[c * ld + e]) - double(qs[c * ld + e]);
-    L2 += t * t;
+#pragma unroll
+  for (int c = 0; c < kMaxD; ++c) {
+    v[c] -= a[c];
+    L2 += v[c] * v[c];
   }
   const double L = sqrt(L2);
   const double ds = L < r ? L : r;
-  const double ep = double(eps[e * n + i]);
-  for (int c = 0; c < d; ++c) {
-    const double a = double(qs[c * ld + e]);
-    const double v = L > 0.0 ? (double(qt[c * ld + e]) - a) / L : 0.0;
-    part[c * ldp + g] = T(a + ds * v + ep * v);
-  }
+  const double f = L > 0.0 ? (ds + ep) / L : 0.0;
+#pragma unroll
+  for (int c = 0; c < kMaxD; ++c)
+    if (c < d) part[c * ldp + g] = T(a[c] + f * v[c]);
   if (i == 0) {
     dist[e] = ds;
     result[e] = L > 0.0 ? int8_t(kExtRunning) : int8_t(MC_EXT_ZERO);
@@ -505,7 +514,7 @@ __global__ void k_ext_particles(int64_t E, int n, int d, const T* qs, const T* q
 
 // earliest converged particle, its collision verdict and distance test; seeds the chain ends
 template <class T>
-__global__ void k_ext_select(int64_t E, int n, int d, const T* qs, int64_t ld, const T* pout, int64_t ldp,
+__global__ void __launch_bounds__(256) k_ext_select(int64_t E, int n, int d, const T* qs, int64_t ld, const T* pout, int64_t ldp,
                              const int8_t* st, const int8_t* it, const uint8_t* vd, const double* dist, int8_t* result,
                              int32_t* particle, T* q_out, int64_t ld_out, T* chain, int64_t K, int64_t H) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -525,14 +534,22 @@ __global__ void k_ext_select(int64_t E, int n, int d, const T* qs, int64_t ld, c
   particle[e] = best;
   const int64_t g = int64_t(best) * E + e;
   const int64_t cs = E * K, end = (int64_t(n) + 1) * H * E;
+  T qa[kMaxD], qb[kMaxD];
+#pragma unroll
+  for (int c = 0; c < kMaxD; ++c) {
+    qa[c] = c < d ? qs[c * ld + e] : T(0);
+    qb[c] = c < d ? pout[c * ldp + g] : T(0);
+  }
   double s2 = 0.0;
-  for (int c = 0; c < d; ++c) {
-    const T qa = qs[c * ld + e], qb = pout[c * ldp + g];
-    const double a = double(qa), b = double(qb);
-    chain[c * cs + e] = qa;
-    chain[c * cs + end + e] = qb;
-    q_out[c * ld_out + e] = qb;
-    s2 += (b - a) * (b - a);
+#pragma unroll
+  for (int c = 0; c < kMaxD; ++c) {
+    if (c < d) {
+      chain[c * cs + e] = qa[c];
+      chain[c * cs + end + e] = qb[c];
+      q_out[c * ld_out + e] = qb[c];
+    }
+    const double t = double(qb[c]) - double(qa[c]);
+    s2 += t * t;
   }
   if (vd[g] != V_FREE) result[e] = MC_EXT_COLLISION;
   else if (sqrt(s2) > 2.0 * dist[e]) result[e] = MC_EXT_TOO_FAR;
@@ -541,7 +558,7 @@ __global__ void k_ext_select(int64_t E, int n, int d, const T* qs, int64_t ld, c
 // Level bookkeeping, one thread per extension: applies the previous level's failure code, ends
 // extensions whose chain meets the resolution, and gives each extension that goes on a slot of
 // the level's batch (wave-aggregated atomic).
-__global__ void k_ext_level(int64_t E, int n, int level, int lmax, double delta, int8_t* result, int32_t* npts,
+__global__ void __launch_bounds__(256) k_ext_level(int64_t E, int n, int level, int lmax, double delta, int8_t* result, int32_t* npts,
                             int32_t* code, unsigned long long* maxgap, int32_t* slot_ext, unsigned int* count) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   bool alive = false;
@@ -600,36 +617,44 @@ __device__ __forceinline__ ExtPoint ext_point(int64_t g, int64_t alive, int leve
 // the level's new points: level 0 interpolates s + k/(n+1) (q_proj - s), later levels take the
 // midpoint of every gap
 template <class T>
-__global__ void k_ext_emit(int64_t total, int64_t alive, int n, int d, int level, int64_t E, const T* chain,
+__global__ void __launch_bounds__(256) k_ext_emit(int64_t total, int64_t alive, int n, int d, int level, int64_t E, const T* chain,
                            int64_t K, int64_t H, const int32_t* slot_ext, T* pts, int64_t ldx) {
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const ExtPoint p = ext_point(g, alive, level, H, slot_ext);
   const T* c = chain + p.e;
   const int64_t cs = E * K;
-  if (level == 0) {
-    const double t = double(p.j + 1) / double(n + 1);
-    const int64_t end = (int64_t(n) + 1) * H * E;
-    for (int k = 0; k < d; ++k) {
-      const double a = double(c[k * cs]), b = double(c[k * cs + end]);
-      pts[k * ldx + g] = T(a + t * (b - a));
-    }
-  } else {
-    for (int k = 0; k < d; ++k)
-      pts[k * ldx + g] = T(0.5 * (double(c[k * cs + p.lo * E]) + double(c[k * cs + p.hi * E])));
+  // level 0: the chain's two ends and the chord fraction; later levels: the gap's two ends, halved
+  const int64_t ia = level == 0 ? 0 : p.lo * E, ib = level == 0 ? (int64_t(n) + 1) * H * E : p.hi * E;
+  const double t = level == 0 ? double(p.j + 1) / double(n + 1) : 0.5;
+  T xa[kMaxD], xb[kMaxD];
+#pragma unroll
+  for (int k = 0; k < kMaxD; ++k) {
+    xa[k] = k < d ? c[k * cs + ia] : T(0);
+    xb[k] = k < d ? c[k * cs + ib] : T(0);
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxD; ++k) {
+    const double a = double(xa[k]), b = double(xb[k]);
+    if (k < d) pts[k * ldx + g] = T(level == 0 ? a + t * (b - a) : t * (a + b));
   }
 }
 
 // projected points into the chain, with their convergence and collision failures
 template <class T>
-__global__ void k_ext_store(int64_t total, int64_t alive, int d, int level, int64_t E, T* chain, int64_t K,
+__global__ void __launch_bounds__(256) k_ext_store(int64_t total, int64_t alive, int d, int level, int64_t E, T* chain, int64_t K,
                             int64_t H, const int32_t* slot_ext, const T* pout, int64_t ldx, const int8_t* st,
                             const uint8_t* vd, int32_t* code) {
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const ExtPoint p = ext_point(g, alive, level, H, slot_ext);
   const int64_t cs = E * K;
-  for (int k = 0; k < d; ++k) chain[k * cs + p.pos * E + p.e] = pout[k * ldx + g];
+  T x[kMaxD];
+#pragma unroll
+  for (int k = 0; k < kMaxD; ++k) x[k] = k < d ? pout[k * ldx + g] : T(0);
+#pragma unroll
+  for (int k = 0; k < kMaxD; ++k)
+    if (k < d) chain[k * cs + p.pos * E + p.e] = x[k];
   if (st[g] != ST_CONVERGED) atomicMin(code + p.e, int32_t(MC_EXT_INTERP_FAILED));
   else if (vd[g] != V_FREE) atomicMin(code + p.e, int32_t(MC_EXT_INTERP_COLLISION));
 }
@@ -637,17 +662,24 @@ __global__ void k_ext_store(int64_t total, int64_t alive, int d, int level, int6
 // the two gaps next to each new point against the level's bound r / (n 2^level); the longest
 // gap of each extension (non-negative doubles order like their bit patterns)
 template <class T>
-__global__ void k_ext_gaps(int64_t total, int64_t alive, int d, int level, int64_t E, const T* chain, int64_t K,
+__global__ void __launch_bounds__(256) k_ext_gaps(int64_t total, int64_t alive, int d, int level, int64_t E, const T* chain, int64_t K,
                            int64_t H, const int32_t* slot_ext, double bound, int32_t* code, unsigned long long* maxgap) {
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const ExtPoint p = ext_point(g, alive, level, H, slot_ext);
   const T* c = chain + p.e;
   const int64_t cs = E * K;
+  T x[kMaxD], xl[kMaxD], xh[kMaxD];
+#pragma unroll
+  for (int k = 0; k < kMaxD; ++k) {
+    x[k] = k < d ? c[k * cs + p.pos * E] : T(0);
+    xl[k] = k < d ? c[k * cs + p.lo * E] : T(0);
+    xh[k] = k < d ? c[k * cs + p.hi * E] : T(0);
+  }
   double a2 = 0.0, b2 = 0.0;
-  for (int k = 0; k < d; ++k) {
-    const double x = double(c[k * cs + p.pos * E]);
-    const double u = x - double(c[k * cs + p.lo * E]), w = double(c[k * cs + p.hi * E]) - x;
+#pragma unroll
+  for (int k = 0; k < kMaxD; ++k) {
+    const double u = double(x[k]) - double(xl[k]), w = double(xh[k]) - double(x[k]);
     a2 += u * u;
     b2 += w * w;
   }
@@ -1295,6 +1327,7 @@ mc_status extend_batch(const mc_problem* p, int64_t E, const void* q_start, cons
   if (!(xo->r > 0) || !std::isfinite(xo->r)) return fail(MC_ERR_INVALID_ARG, "extend_batch: r must be > 0");
   if (!(xo->delta > 0) || !std::isfinite(xo->delta)) return fail(MC_ERR_INVALID_ARG, "extend_batch: delta must be > 0");
   if (xo->n < 1 || xo->n > 64) return fail(MC_ERR_INVALID_ARG, "extend_batch: n must be in 1..64");
+  if (p->d > kMaxD) return fail(MC_ERR_UNSUPPORTED, "extend_batch: configuration dimension above 36");
   int lmax = 0;
   while (xo->r / (double(xo->n) * double(int64_t(1) << lmax)) > xo->delta) {
     if (++lmax > 12) return fail(MC_ERR_INVALID_ARG, "extend_batch: r / (n delta) needs more than 12 levels");

@@ -111,3 +111,11 @@ def test_flop_model_structure():
     assert 0 < f["parts"]["gram"] < dense_gram
     s0 = F.iteration_flops(S.sphere_scene(0))
     assert s0["per_iter"] > 0 and s0["final"] == 6
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asking for more exits with a message before touching a device."""
+    r = subprocess.run([os.sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
