@@ -35,14 +35,15 @@ def config_inputs(name: str, small: bool = True, max_geo: int | None = None):
     return sc, P, q, offs, cfg["tol"], cfg["max_iter"]
 
 
-def band_mask(P, q, tol, max_iter, max_step=0.0, mode="stacked"):
+def band_mask(P, q, tol, max_iter, max_step=0.0, mode="stacked", alpha=1.0, lam=0.0):
     """Configurations whose oracle outcome is not a well-posed target for exact comparison:
     the residual sequence crosses tol within +-0.1%; at least max_iter - 1 steps; an
     ill-conditioned path (sigma_min(J) < 1e-3 at some step, or a step longer than 1, where the
     linear model is far off and rounding differences send the iteration elsewhere on the
     manifold); or (with the divergence exit) a step within 1% of max_step."""
-    lo = P.project(q, tol=tol * 0.999, max_iter=max_iter, max_step=max_step, mode=mode)
-    hi = P.project(q, tol=tol * 1.001, max_iter=max_iter, max_step=max_step, path_info=True, mode=mode)
+    lo = P.project(q, tol=tol * 0.999, max_iter=max_iter, max_step=max_step, mode=mode, alpha=alpha, lam=lam)
+    hi = P.project(q, tol=tol * 1.001, max_iter=max_iter, max_step=max_step, path_info=True, mode=mode,
+                   alpha=alpha, lam=lam)
     pi = hi[4]
     band = (lo[1] != hi[1]) | (lo[2] != hi[2]) | (hi[2] >= max_iter - 1)
     band |= pi[:, 0] < 1e-3

@@ -32,10 +32,11 @@ def mc():
 _CACHE = {}
 
 
-def inputs(name, E):
+def inputs(name, E, max_step=0.0):
     """Starts on the manifold (oracle FP64 projection of the raw starts, converged ones kept),
-    targets, particle draws, and the oracle's extension results."""
-    key = (name, E)
+    targets, particle draws, and the oracle's extension results (max_step > 0: Alg. 2's MaxDistance
+    exit inside every projection)."""
+    key = (name, E, max_step)
     if key in _CACHE:
         return _CACHE[key]
     w = S.extend_workload(name, E)
@@ -47,27 +48,27 @@ def inputs(name, E):
         qs, qt, eps = qp[keep], qt[keep], eps[keep]
     qt = qt.copy()
     qt[0] = qs[0]  # one degenerate extension: target == start
-    ref = OX.extend(P, qs, qt, eps, w["r"], w["delta"], tol=w["tol"], max_iter=w["max_iter"])
+    ref = OX.extend(P, qs, qt, eps, w["r"], w["delta"], tol=w["tol"], max_iter=w["max_iter"], max_step=max_step)
     out = (w, P, qs, qt, eps, ref)
     _CACHE[key] = out
     return out
 
 
-def particle_band(P, w, qs, qt, eps):
+def particle_band(P, w, qs, qt, eps, max_step=0.0):
     """Extensions with a particle in the oracle's band."""
     E, n = eps.shape
     L = np.linalg.norm(qt - qs, axis=1)
     v = (qt - qs) / np.where(L > 0, L, 1.0)[:, None]
     dist = np.minimum(L, w["r"])
     parts = (qs + dist[:, None] * v)[:, None, :] + eps[:, :, None] * v[:, None, :]
-    band = band_mask(P, parts.reshape(E * n, -1), w["tol"], w["max_iter"])
+    band = band_mask(P, parts.reshape(E * n, -1), w["tol"], w["max_iter"], max_step)
     return band.reshape(E, n).any(axis=1)
 
 
-def run_gpu(mc, w, qs, qt, eps, dtype):
+def run_gpu(mc, w, qs, qt, eps, dtype, max_step=0.0):
     G = mc.Problem(w["scene"].to_blob())
     r = G.extend(to_dev(qs, dtype), to_dev(qt, dtype), torch.from_numpy(eps).to("cuda", dtype).contiguous(),
-                 w["r"], w["delta"], tol=w["tol"], max_iter=w["max_iter"])
+                 w["r"], w["delta"], tol=w["tol"], max_iter=w["max_iter"], max_step=max_step)
     torch.cuda.synchronize()
     return G, dict(code=r.result.cpu().numpy().astype(np.int8), particle=r.particle.cpu().numpy(),
                    n_points=r.n_points.cpu().numpy(), q=from_dev(r.q).T)
@@ -112,6 +113,23 @@ def test_extend_fp32_matches_oracle(mc, name, E):
     assert np.all(got["n_points"][agree_ok] == ref["n_points"][agree_ok])
     sel = same & (ref["particle"] >= 0)
     np.testing.assert_allclose(got["q"][sel], ref["q"][sel], atol=1e-4, rtol=0)
+
+
+def test_extend_fp64_with_divergence_exit(mc):
+    """Arm extensions with the MaxDistance exit on (max_step 0.3): particles that take a long step stop
+    as DIVERGED, which makes many extensions end without a particle; FP64 decisions must match."""
+    w, P, qs, qt, eps, ref = inputs("c1", 128, max_step=0.3)
+    _, got = run_gpu(mc, w, qs, qt, eps, torch.float64, max_step=0.3)
+    same = (got["code"] == ref["code"]) & (got["particle"] == ref["particle"]) & (got["n_points"] == ref["n_points"])
+    bad = np.flatnonzero(~same)
+    if bad.size:
+        band = particle_band(P, w, qs, qt, eps, 0.3)
+        unexplained = [int(e) for e in bad if not band[e]]
+        assert not unexplained, (unexplained[:8], got["code"][unexplained[:8]], ref["code"][unexplained[:8]])
+        assert bad.size <= 2
+    assert (ref["code"] == OX.NO_PARTICLE).sum() >= 10 and (ref["code"] == OX.OK).sum() >= 10
+    sel = same & (ref["particle"] >= 0)
+    np.testing.assert_allclose(got["q"][sel], ref["q"][sel], atol=1e-9, rtol=0)
 
 
 def test_extend_workspace_reuse_and_empty_batch(mc):

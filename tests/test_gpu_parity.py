@@ -34,9 +34,9 @@ def run_gpu(mc, sc, q, tol, max_iter, dtype=torch.float32, **kw):
 
 
 def compare(P, q, r, tol, max_iter, qtol, require_iters=True, min_agree=0.98, max_band=0.05, max_step=0.0,
-            mode="stacked"):
-    qo, st, it, rs = P.project(q, tol=tol, max_iter=max_iter, max_step=max_step, mode=mode)
-    band = band_mask(P, q, tol, max_iter, max_step, mode)
+            mode="stacked", alpha=1.0, lam=0.0):
+    qo, st, it, rs = P.project(q, tol=tol, max_iter=max_iter, max_step=max_step, mode=mode, alpha=alpha, lam=lam)
+    band = band_mask(P, q, tol, max_iter, max_step, mode, alpha=alpha, lam=lam)
     gst = from_dev(r.status).astype(int)
     git = from_dev(r.iters).astype(int)
     gq = from_dev(r.q).T
@@ -237,6 +237,18 @@ def test_c1_with_divergence_exit(mc, dt, qtol):
     G, r = run_gpu(mc, sc, q, tol, mi, dt, max_step=0.5)
     stats = compare(P, q, r, tol, mi, qtol, require_iters=dt == torch.float64, max_band=0.25, max_step=0.5)
     print("c1 max_step 0.5", stats)
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+@pytest.mark.parametrize("dt,qtol", [(torch.float64, 1e-9), (torch.float32, 1e-4)])
+def test_damped_steps_parity(mc, name, dt, qtol):
+    """Alg. 2's damped step alpha J^T (J J^T + lambda I)^-1 F (lambda 1e-3, alpha 0.9) against the oracle."""
+    sc, P, q, offs, tol, mi = config_inputs(name, small=True, max_geo=16)
+    G = mc.Problem(sc.to_blob())
+    r = G.project(to_dev(q, dt), tol=tol, max_iter=mi, lam=1e-3, alpha=0.9)
+    torch.cuda.synchronize()
+    info = compare(P, q, r, tol, mi, qtol, require_iters=(dt == torch.float64), alpha=0.9, lam=1e-3)
+    assert info["conv"] > 0.9, info
 
 
 @pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3"])

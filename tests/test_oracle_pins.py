@@ -103,6 +103,22 @@ def test_linear_damped_step(oracle_mod):
     np.testing.assert_allclose(qo[0], q0[0] - step, atol=1e-12)
 
 
+def test_damped_step_equals_the_outer_pseudo_inverse_form(oracle_mod):
+    """Alg. 2 offers the step with the inner pseudo-inverse, J^T (J J^T + lambda I)^-1 d, or the outer one,
+    (J^T J + lambda I)^-1 J^T d. For lambda > 0 they are the same vector (push-through identity), so the
+    library's inner form also gives the outer form's step; here the oracle's damped step is compared with the
+    d x d outer system solved directly."""
+    rng = np.random.default_rng(14)
+    A = rng.standard_normal((3, 6))
+    b = rng.standard_normal(3)
+    P = prob(S.linear_scene(A, b))
+    q0 = rng.standard_normal((1, 6))
+    lam = 0.05
+    qo, _, _, _ = P.project(q0, tol=1e-30, max_iter=1, lam=lam)
+    outer = np.linalg.solve(A.T @ A + lam * np.eye(6), A.T @ (A @ q0[0] - b))
+    np.testing.assert_allclose(qo[0], q0[0] - outer, atol=1e-12)
+
+
 def test_linear_vjp_is_pinv_projector(oracle_mod):
     rng = np.random.default_rng(5)
     A = rng.standard_normal((3, 7))
