@@ -388,12 +388,28 @@ __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
   int k = 0;
   if (i < a.n) load_q<Model, IO>(a, dof, i, q);
   constexpr bool fused = Model::broad_in_residual;
+  // A converged lane that needs the broad phase waits (pending) until no lane of the wave is
+  // still iterating or half the wave is waiting, so one FP32 walk serves all of them instead of
+  // one walk per iteration count.
+  bool pending = false;
   for (;;) {
-    const bool active = i < a.n;
-    if (!__any(active)) break;
+    const bool active = i < a.n && !pending;
+    const bool any_active = __any(active);
+    if (!any_active && !__any(pending)) break;
+    if (fused && (!any_active || __builtin_popcountll(uint64_t(__ballot(pending))) >= 32)) {
+      if (pending) {
+        // broad phase on the converged configurations (an FP32 walk of the link bounds)
+        a.verdict[i] = V_FREE;  // k_check_tail overwrites it with V_HIT if some part finds a hit
+        if (Model::broad_flag(q, C)) a.chk_idx[queue_q<Model>(q, a.chk_count, a.chk_q, a.defer_cap)] = int32_t(i);
+        pending = false;
+        i = a.n_static + int64_t(atomicAdd(a.counter, 1u));
+        k = 0;
+        if (i < a.n) load_q<Model, IO>(a, dof, i, q);
+      }
+      continue;
+    }
     if (active) {
       double resid;
-      bool near = true;
       int st = iteration<Model, S, CYC>(q, q0, k, a, C, resid);
       if (st == ST_DEFER) {
         const unsigned slot = queue_q<Model>(q, a.defer_count, a.defer_q, a.defer_cap);
@@ -404,20 +420,14 @@ __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
         store_result<Model, IO>(a, dof, i, q, st, k, resid);
         if (a.verdict) {
           if constexpr (fused) {
-            // broad phase on the converged configuration (an FP32 walk of the link bounds)
-            if (a.check && st == ST_CONVERGED) near = Model::broad_flag(q, C);
-            if (a.check && st == ST_CONVERGED && near) {
-              a.verdict[i] = V_FREE;  // k_check_tail overwrites it with V_HIT if some part finds a hit
-              a.chk_idx[queue_q<Model>(q, a.chk_count, a.chk_q, a.defer_cap)] = int32_t(i);
-            } else {
-              a.verdict[i] = (a.check && st == ST_CONVERGED) ? V_FREE : V_UNCHECKED;
-            }
+            if (a.check && st == ST_CONVERGED) pending = true;  // the verdict comes with the wave's walk
+            else a.verdict[i] = V_UNCHECKED;
           } else {
             a.verdict[i] = verdict_inline<Model>(q, C, a, st);
           }
         }
       }
-      if (st >= 0 || st == ST_DEFER) {
+      if ((st >= 0 || st == ST_DEFER) && !pending) {
         i = a.n_static + int64_t(atomicAdd(a.counter, 1u));
         k = 0;
         if (i < a.n) load_q<Model, IO>(a, dof, i, q);

@@ -654,6 +654,12 @@ struct Kin {
     const int ncl = K.n_clus;
     const int nb = (ncl + L - 1) / L;  // cluster slots per lane
     float4 blo[PB], bhi[PB];
+    // one wave per configuration with at most 64 clusters: each lane also keeps its cluster's
+    // obstacle range, so the pair loop below fetches it with a cross-lane read instead of a
+    // dependent scalar load per overlapping cluster
+    const bool ranges_in_lanes = L == 64 && ncl <= 64;
+    int2 my_rg = make_int2(0, 0);
+    if (ranges_in_lanes && t < ncl) my_rg = K.clus_range[t];
     sfor<0, PB>([&](auto BI) {
       constexpr int bi = decltype(BI)::value;
       const int c = bi * L + t;
@@ -681,7 +687,13 @@ struct Kin {
             while (m) {  // the same list in all L lanes
               const int cc = b * L + __builtin_ctzll(m);
               m &= m - 1;
-              const int2 rg = K.clus_range[cc];
+              int2 rg;
+              if (ranges_in_lanes) {
+                rg.x = __shfl(my_rg.x, cc);
+                rg.y = __shfl(my_rg.y, cc);
+              } else {
+                rg = K.clus_range[cc];
+              }
               const int no = rg.y - rg.x, np = ns * no;
               for (int pi = t; pi < np; pi += L) {
                 const int si = pi / no, oi = pi - si * no;
