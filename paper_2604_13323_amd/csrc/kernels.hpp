@@ -436,30 +436,25 @@ __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
   }
 }
 
-// Exact collision check of the configurations queued by k_project_persistent: L lanes per
-// configuration (grid-stride over the queue). Two instances are launched: a wave per
-// configuration while the queue is short (at most `small` entries: latency-bound, few waves) and
-// a few lanes per configuration when it is long (most configurations near the obstacles); each
-// returns at once when the queue length is not its case.
-// Dynamic LDS: the configurations (a column per lane, or one per wave when L = 64), then the
+// Exact collision check of the configurations queued by k_project_persistent, L lanes per
+// configuration (grid-stride over the queue): a wave per configuration while the queue is short
+// (at most `small` entries: latency-bound, few waves; each configuration's links may be split over
+// up to 4 waves), 4 lanes per configuration when it is long (most configurations near the
+// obstacles). One launch serves both cases; the queue length picks the path.
+// Dynamic LDS: one configuration per lane group (D doubles each, 64 groups at most), then the
 // robot spheres and the obstacles (float4 each).
+constexpr int kTailCheckLanesLong = 4;  // lanes per configuration on a long queue
+
 template <class Model, class IO, int L>
-__global__ void __launch_bounds__(256) k_check_tail(ProjArgs a, int64_t small) {
+__device__ __forceinline__ void check_tail_body(const ProjArgs& a, int64_t small, int64_t cnt, double* smem) {
   constexpr int D = Model::D;
-  extern __shared__ double smem[];
   const Consts& C = consts_of(a.P);
   const CollConsts& K = coll_of(a.P);
-  const int64_t cnt = *a.chk_count;
-  if ((cnt <= small) != (L == 64)) return;                  // the other instance's case
-  // a short queue leaves waves idle: split each configuration's links over up to 4 waves
   int64_t parts = 1;
   if (L == 64 && cnt > 0) parts = small / cnt < 4 ? (small / cnt < 1 ? 1 : small / cnt) : 4;
   if (int64_t(blockIdx.x) * blockDim.x / L >= cnt * parts) return;  // no queued work for this block
-  using QT = typename std::conditional<L == 64, QLdsU, QLds>::type;
-  QT q;
-  if constexpr (L == 64) q = QLdsU{(QLdsU::LP)(smem + (threadIdx.x >> 6) * D)};
-  else q = q_lds<D>(smem);
-  float4* sph = reinterpret_cast<float4*>(smem + (L == 64 ? D * (blockDim.x >> 6) : D * blockDim.x));
+  const QLdsU q{(QLdsU::LP)(smem + (threadIdx.x / L) * D)};
+  float4* sph = reinterpret_cast<float4*>(smem + D * (blockDim.x / L));
   float4* obs = sph + K.n_sph;
   block_copy16(sph, K.sph, K.n_sph * 16);
   block_copy16(obs, obs_of(a.P), K.n_obs * 16);
@@ -472,6 +467,14 @@ __global__ void __launch_bounds__(256) k_check_tail(ProjArgs a, int64_t small) {
     const bool hit = Model::template check_group<L>(q, C, K, sph, obs, part, int(parts));
     if ((gid & (L - 1)) == 0 && hit) a.verdict[a.chk_idx[slot]] = V_HIT;  // queued as V_FREE
   }
+}
+
+template <class Model, class IO>
+__global__ void __launch_bounds__(256) k_check_tail(ProjArgs a, int64_t small) {
+  extern __shared__ double smem[];
+  const int64_t cnt = *a.chk_count;
+  if (cnt <= small) check_tail_body<Model, IO, 64>(a, small, cnt, smem);
+  else check_tail_body<Model, IO, kTailCheckLanesLong>(a, small, cnt, smem);
 }
 
 // FP64 tail of the persistent variant: the configurations deferred by the FP32 kernel, one per

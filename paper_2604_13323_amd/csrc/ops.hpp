@@ -28,7 +28,6 @@ struct FamilyOps {
 inline unsigned blocks_for(int64_t n, int block) { return unsigned((n + block - 1) / block); }
 
 constexpr int kCheckLanes = 4;       // check_batch: lanes per configuration
-constexpr int kTailCheckLanesLong = 4;  // exact check of a long queue of flagged configurations
 
 template <class Model, class IO, class S>
 struct OpsImpl {
@@ -58,13 +57,11 @@ struct OpsImpl {
   static hipError_t check_tail(const ProjArgs& a, int grid, hipStream_t s) {
     const size_t stage = size_t(a.n_sph + a.n_obs) * 16;
     // short queues: a wave (or part of one configuration's links) per work item, one pass of
-    // `small` work items over 4 waves per workgroup
+    // `small` work items over 4 waves per workgroup; the LDS covers the long-queue path's 64
+    // lane groups of 4
     const int64_t small = int64_t(grid) * 4;
-    hipLaunchKernelGGL((k_check_tail<Model, IO, 64>), dim3(grid), dim3(256), 4 * Model::D * 8 + stage, s, a, small);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_check_tail<Model, IO, kTailCheckLanesLong>), dim3(grid), dim3(256), lds_bytes(256) + stage, s,
-                       a, small);
+    const size_t cols = size_t(256 / kTailCheckLanesLong) * Model::D * sizeof(double);
+    hipLaunchKernelGGL((k_check_tail<Model, IO>), dim3(grid), dim3(256), cols + stage, s, a, small);
     return hipGetLastError();
   }
   static hipError_t vjp_tail(const VjpArgs& a, int grid, hipStream_t s) {
