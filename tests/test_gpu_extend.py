@@ -132,6 +132,31 @@ def test_extend_fp64_with_divergence_exit(mc):
     np.testing.assert_allclose(got["q"][sel], ref["q"][sel], atol=1e-9, rtol=0)
 
 
+@pytest.mark.parametrize("n,r,delta", [(1, 0.5, 0.6), (64, 0.5, 0.005), (4, 0.5, 0.01), (3, 0.3, 0.0009)])
+def test_extend_edge_shapes_fp64(mc, n, r, delta):
+    """Edge shapes on the sphere: a single particle and no refinement level (n 1, delta > r), the most
+    particles (n 64), and chains of several refinement levels (up to 7: r / (n 2^l) <= delta first at
+    l = 7 for n 3, r 0.3, delta 9e-4); FP64 decisions and chain lengths must match the oracle."""
+    w = S.extend_workload("c0", 96)
+    P = oracle.Problem(w["scene"].to_blob())
+    rng = np.random.default_rng([0, 5, n])
+    eps = rng.normal(0.0, 0.1, (96, n))
+    qs, qt = w["starts"], w["targets"]
+    ref = OX.extend(P, qs, qt, eps, r, delta, tol=w["tol"], max_iter=w["max_iter"])
+    G = mc.Problem(w["scene"].to_blob())
+    x = G.extend(to_dev(qs, torch.float64), to_dev(qt, torch.float64), torch.from_numpy(eps).cuda().contiguous(),
+                 r, delta, tol=w["tol"], max_iter=w["max_iter"])
+    torch.cuda.synchronize()
+    code, part, npts = x.result.cpu().numpy(), x.particle.cpu().numpy(), x.n_points.cpu().numpy()
+    same = (code == ref["code"]) & (part == ref["particle"]) & (npts == ref["n_points"])
+    assert same.mean() >= 0.98, (n, np.flatnonzero(~same)[:8], code[~same][:8], ref["code"][~same][:8])
+    ok = same & (ref["code"] == OX.OK)
+    assert ok.sum() >= 10
+    levels = np.log2((npts[ok] - 1) / (n + 1))
+    assert np.allclose(levels, np.round(levels))  # (n + 1) 2^l + 1 points
+    np.testing.assert_allclose(from_dev(x.q).T[same & (part >= 0)], ref["q"][same & (part >= 0)], atol=1e-9)
+
+
 def test_extend_workspace_reuse_and_empty_batch(mc):
     """A larger call, then a smaller one on the same problem (reused workspace), must give what a
     fresh problem gives; E = 0 is a no-op."""
