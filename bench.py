@@ -163,6 +163,19 @@ def cyclic_row(G, q_in, out, kw, args, torch):
     return cyclic
 
 
+def peak_clock_mhz():
+    """The device's peak shader clock (hipDeviceAttributeClockRate = 5, in kHz), or None."""
+    import ctypes
+    try:
+        hip = ctypes.CDLL("libamdhip64.so")
+        v = ctypes.c_int(0)
+        if hip.hipDeviceGetAttribute(ctypes.byref(v), 5, 0) == 0 and v.value > 0:
+            return v.value / 1000.0
+    except OSError:
+        pass
+    return None
+
+
 def extend_row(M, S, G, torch, steps, shape):
     """Alg. 2 ConstrainedExtend batched (extend_batch) on the humanoid: 8,192 extensions of 8
     particles each (65,536 particle projections, as many lanes as the headline batch), then the
@@ -376,6 +389,7 @@ def main():
                   "launch_shape": {k: kw[k] for k in ("waves_per_block", "blocks_per_cu")},
                   "median_ms_per_step": dict(STEP_MEDIANS),
                   "cus": torch.cuda.get_device_properties(0).multi_processor_count,
+                  "peak_clock_mhz": peak_clock_mhz(),
                   "autotune": tuning["table"] if tuning else None,
                   "gpu": torch.cuda.get_device_name(0)},
     }
