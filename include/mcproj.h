@@ -235,9 +235,9 @@ typedef struct {
    The number of levels is at most the smallest l with r / (n 2^l) <= delta, which must be
    <= 12, and (n + 1) 2^l + 1 <= 65536.
    Arrays (device, caller-owned): q_start, q_target [d][ld] and eps [E * n] of opts->dtype;
-   q_out [d][ld_out] (written for MC_EXT_OK only); result int8[E] (MC_EXT_*); particle
-   int32[E] (selected particle index, -1 before selection); n_points int32[E] (points of the
-   validated chain including both ends, 0 when the extension failed before level 0).
+   q_out [d][ld_out] (q_proj, written where a particle was selected: particle >= 0); result
+   int8[E] (MC_EXT_*); particle int32[E] (selected particle index, -1 when none was selected);
+   n_points int32[E] (points of the validated chain including both ends for MC_EXT_OK, else 0).
    Workspace: particle, chain and level buffers owned by the problem, grown to the largest call
    (synchronising the device when they grow). The call synchronises `stream` once per level to
    read how many points the level emits (not capturable into a graph).
