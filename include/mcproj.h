@@ -91,7 +91,9 @@ typedef struct {
                                  2 fused (persistent work-queue kernel over the whole batch)     */
   int32_t waves_per_block;    /* fused variant: 1, 2 or 4 wavefronts per workgroup (0 = auto)   */
   int32_t blocks_per_cu;      /* fused variant: resident workgroups per CU for the persistent
-                                 grid (0 = auto)                                                */
+                                 grid (0 = auto; with auto, a stacked-mode batch larger than the
+                                 lanes of the one-wave-per-SIMD launch of the 36-DoF family runs
+                                 in its two-waves-per-SIMD build, same results)                  */
   int32_t mode;               /* 0 stacked: one min-norm step on all constraint rows together;
                                  1 cyclic (Sec. IV-C, Alg. 2 getDescentStep): one min-norm step
                                  per constraint block, in the scene's block order, each from the

@@ -711,6 +711,7 @@ struct mc_problem {
   // resident workgroups per CU of the persistent kernel, by (FP64 mode, waves per block = 1, 2, 4);
   // queried once, so later calls (and calls under stream capture) make no runtime query
   mutable int occ[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  mutable int occ_wide = 0;  // resident 256-thread workgroups per CU of the two-wave launch
   // extend_batch workspace (particle and level batches, chains, per-extension state), grown to
   // the largest call
   mutable unsigned char* x_arena = nullptr;
@@ -960,6 +961,8 @@ mc_status mc_problem_create(const void* blob, size_t nbytes, mc_problem** out) {
   return MC_OK;
 }
 
+static bool lds_ok(const mc_problem* p, size_t bytes) { return bytes <= p->max_lds_per_block; }
+
 static mc_status check_opts(const mc_problem* p, const mc_project_opts* o) {
   if (!o) return fail(MC_ERR_INVALID_ARG, "null opts");
   if (o->dtype != MC_F32 && o->dtype != MC_F64) return fail(MC_ERR_INVALID_ARG, "bad dtype");
@@ -1045,10 +1048,19 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
       bpc = c;
     }
     int64_t grid = int64_t(p->n_cu) * bpc;
-    grid = std::min<int64_t>(grid, (n + block - 1) / block);
+    // a batch beyond the lanes of the one-wave launch, with the launch shape left to the library:
+    // the two-wave launch where the family has one
+    const bool wide = !cyc && ops->project_persistent_wide != nullptr && opts->blocks_per_cu == 0 &&
+                      n > grid * block && lds_ok(p, ops->lds_bytes(256));
+    if (wide) {
+      if (p->occ_wide <= 0) p->occ_wide = ops->persistent_wide_blocks_per_cu();
+      grid = int64_t(p->n_cu) * p->occ_wide;
+    }
+    const int lblock = wide ? 256 : block;
+    grid = std::min<int64_t>(grid, (n + lblock - 1) / lblock);
     a.base = 0;
     a.n = n;
-    a.n_static = std::min<int64_t>(n, grid * block);
+    a.n_static = std::min<int64_t>(n, grid * lblock);
     const bool tail = ops->project_tail != nullptr;
     const bool ctail = verdict && opts->check_collision && ops->check_tail != nullptr;
     if (tail || ctail) {
@@ -1064,8 +1076,9 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
     a.verdict = verdict;
     hipLaunchKernelGGL(k_reset_u32, dim3(1), dim3(64), 0, s, p->counter, 4);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "project_batch: reset");
-    if ((e = (cyc ? ops->project_persistent_cyclic : ops->project_persistent)(a, int(grid), block, s)) != hipSuccess)
-      return hip_fail(e, "project_batch: persistent launch");
+    if (wide) e = ops->project_persistent_wide(a, int(grid), s);
+    else e = (cyc ? ops->project_persistent_cyclic : ops->project_persistent)(a, int(grid), block, s);
+    if (e != hipSuccess) return hip_fail(e, "project_batch: persistent launch");
     if (tail && (e = (cyc ? ops->project_tail_cyclic : ops->project_tail)(a, p->n_cu, s)) != hipSuccess)
       return hip_fail(e, "project_batch: FP64 tail launch");
     // 4 workgroups of 4 waves per CU: 4,096 work items per round (blocks without work leave at once)

@@ -376,9 +376,8 @@ __device__ __forceinline__ uint8_t verdict_inline(const QLds& q, const Consts& C
 // obstacles, so a configuration with no link near the obstacles is FREE at once, and the others
 // are queued for the exact check (k_check_tail).
 // Dynamic LDS: D * blockDim doubles.
-template <class Model, class IO, class S, bool CYC = false>
-__global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
-  extern __shared__ double smem[];
+template <class Model, class IO, class S, bool CYC>
+__device__ __forceinline__ void persistent_body(const ProjArgs& a, double* smem) {
   const Consts& C = consts_of(a.P);
   const int dof = dof_of<Model>(C);
   const QLds q = q_lds<Model::D>(smem);
@@ -434,6 +433,22 @@ __global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
       }
     }
   }
+}
+
+
+template <class Model, class IO, class S, bool CYC = false>
+__global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
+  extern __shared__ double smem[];
+  persistent_body<Model, IO, S, CYC>(a, smem);
+}
+
+// The same kernel compiled for two resident waves per SIMD (registers capped at 256 per lane, the
+// rest spilled): for batches larger than the lanes one wave per SIMD offers, where a second
+// round of the work queue would otherwise run with nothing to hide its latency.
+template <class Model, class IO, class S>
+__global__ void __launch_bounds__(256, 2) k_project_persistent_wide(ProjArgs a) {
+  extern __shared__ double smem[];
+  persistent_body<Model, IO, S, false>(a, smem);
 }
 
 // Exact collision check of the configurations queued by k_project_persistent, L lanes per

@@ -13,6 +13,10 @@ struct FamilyOps {
   int dof_max;  // compiled D (padded for the linear family)
   hipError_t (*project_persistent)(const ProjArgs& a, int grid, int block, hipStream_t s);
   hipError_t (*project_persistent_cyclic)(const ProjArgs& a, int grid, int block, hipStream_t s);
+  // two waves per SIMD (256-thread blocks), for batches beyond the lanes of the one-wave launch;
+  // null where one wave per SIMD is not the register limit
+  hipError_t (*project_persistent_wide)(const ProjArgs& a, int grid, hipStream_t s);
+  int (*persistent_wide_blocks_per_cu)();
   hipError_t (*project_tail_cyclic)(const ProjArgs& a, int grid, hipStream_t s);  // FP32 mode only
   hipError_t (*project_plain)(const ProjArgs& a, hipStream_t s);
   hipError_t (*project_tail)(const ProjArgs& a, int grid, hipStream_t s);  // FP32 mode only
@@ -85,6 +89,17 @@ struct OpsImpl {
     hipLaunchKernelGGL((k_eval_fj<Model, IO, S>), dim3(blocks_for(n, 64)), dim3(64), 0, s, P, n, q, ld, F, J);
     return hipGetLastError();
   }
+  static hipError_t project_persistent_wide(const ProjArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_project_persistent_wide<Model, IO, S>), dim3(grid), dim3(256), lds_bytes(256), s, a);
+    return hipGetLastError();
+  }
+  static int persistent_wide_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_project_persistent_wide<Model, IO, S>),
+                                                     256, lds_bytes(256)) != hipSuccess)
+      return 1;
+    return nb > 0 ? nb : 1;
+  }
   static int persistent_blocks_per_cu(int block) {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_project_persistent<Model, IO, S>),
@@ -105,6 +120,15 @@ struct OpsImpl {
     } else {
       o.project_persistent_cyclic = &project_persistent;
       o.project_tail_cyclic = std::is_same<S, float>::value ? &project_tail : nullptr;
+    }
+    // the 36-DoF tree in FP32 mode needs more than 256 registers per lane: its one-wave launch
+    // leaves half the wave slots empty, which the wide launch fills on large batches
+    if constexpr (Model::D > 16 && std::is_same<S, float>::value) {
+      o.project_persistent_wide = &project_persistent_wide;
+      o.persistent_wide_blocks_per_cu = &persistent_wide_blocks_per_cu;
+    } else {
+      o.project_persistent_wide = nullptr;
+      o.persistent_wide_blocks_per_cu = nullptr;
     }
     o.project_plain = &project_plain;
     o.project_tail = std::is_same<S, float>::value ? &project_tail : nullptr;
