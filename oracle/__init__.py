@@ -55,6 +55,7 @@ def lib():
         L.oracle_check.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, P, ctypes.c_int]
         L.oracle_vjp.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, P, P, P, ctypes.c_int]
         L.oracle_path_length.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_int32, P, P]
+        L.oracle_kappa_est.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, ctypes.c_double, P, P, ctypes.c_int]
         L.oracle_max_threads.argtypes = []
         _lib = L
     return _lib
@@ -106,17 +107,19 @@ class Problem:
 
     def project(self, q, tol=1e-6, max_iter=50, alpha=1.0, lam=0.0, max_step=0.0, threads: int = 0,
                 path_info: bool = False, mode: str = "stacked"):
-        """Returns (q_out, status, iters, resid) and, with path_info, an [n, 2] array holding the
-        smallest sigma_min(J) along each path and its longest step (the longest iteration
-        displacement in cyclic mode). mode: "stacked" (one system per step) or "cyclic" (one step
-        per constraint block, in order)."""
+        """Returns (q_out, status, iters, resid) and, with path_info, an [n, 4] path record: the
+        smallest sigma_min(J) along each path, its longest step (the longest iteration displacement
+        in cyclic mode), the largest rotation angle of a pose error at any residual evaluation, and
+        the smallest multiplicative distance max(||F|| / tol, tol / ||F||) of a convergence test to
+        the tolerance. mode: "stacked" (one system per step) or "cyclic" (one step per constraint
+        block, in order)."""
         q = np.ascontiguousarray(q, np.float64).reshape(-1, self.d)
         n = q.shape[0]
         qo = np.zeros_like(q)
         st = np.zeros(n, np.int8)
         it = np.zeros(n, np.int32)
         rs = np.zeros(n, np.float64)
-        pi = np.zeros((n, 2)) if path_info else None
+        pi = np.zeros((n, 4)) if path_info else None
         rc = lib().oracle_project(*self._args(), n, _p(q), _p(qo), _p(st), _p(it), _p(rs), float(tol),
                                   int(max_iter), float(alpha), float(lam), float(max_step), threads,
                                   None if pi is None else _p(pi), {"stacked": 0, "cyclic": 1}[mode])
@@ -141,6 +144,15 @@ class Problem:
         assert lib().oracle_vjp(*self._args(), n, _p(q), None if st is None else _p(st), _p(g), _p(gi),
                                 _p(kap), threads) == 0
         return gi, kap
+
+    def kappa_est(self, q, lam=0.0, threads: int = 0):
+        """(kappa_est, kappa2) per configuration: (max L_ii / min L_ii)^2 of the FP64 Cholesky factor
+        of J J^T + lam I (+inf when a pivot is not positive), and (sigma_max / sigma_min)^2 of J."""
+        q = np.ascontiguousarray(q, np.float64).reshape(-1, self.d)
+        ke = np.zeros(q.shape[0])
+        k2 = np.zeros(q.shape[0])
+        assert lib().oracle_kappa_est(*self._args(), q.shape[0], _p(q), float(lam), _p(ke), _p(k2), threads) == 0
+        return ke, k2
 
 
 def so3_log(R):

@@ -215,7 +215,8 @@ template <class T> Tf<T> frame_pose(const Scene& s, const std::vector<Tf<T>>& li
 
 // SO(3) logarithm, vee form. v = vee(R - R^T)/2 = sin(theta) * axis, c = cos(theta).
 // Near theta = 0 the factor theta / sin(theta) takes its first-order Taylor form 1 + s^2/6.
-template <class T> void so3_log(const T R[3][3], T w[3]) {
+// theta (nullable) receives the rotation angle atan2(|v|, c) in [0, pi].
+template <class T> void so3_log(const T R[3][3], T w[3], double* theta = nullptr) {
   T v[3] = {(R[2][1] - R[1][2]) * T(0.5), (R[0][2] - R[2][0]) * T(0.5), (R[1][0] - R[0][1]) * T(0.5)};
   T s2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
   T c = (R[0][0] + R[1][1] + R[2][2] - T(1.0)) * T(0.5);
@@ -227,12 +228,16 @@ template <class T> void so3_log(const T R[3][3], T w[3]) {
     f = atan2(s, c) / s;
   }
   for (int i = 0; i < 3; ++i) w[i] = f * v[i];
+  if (theta) *theta = std::atan2(std::sqrt(val(s2)), val(c));
 }
 
-// error rows [t; log(R)] of a pose error transform, selected by a 6-bit mask
-template <class T> int pose_rows(const Tf<T>& e, int mask, T* out) {
+// error rows [t; log(R)] of a pose error transform, selected by a 6-bit mask; max_theta (nullable)
+// is raised to the error's rotation angle
+template <class T> int pose_rows(const Tf<T>& e, int mask, T* out, double* max_theta = nullptr) {
   T w[3];
-  so3_log(e.R, w);
+  double th = 0.0;
+  so3_log(e.R, w, &th);
+  if (max_theta && th > *max_theta) *max_theta = th;
   T all[6] = {e.p[0], e.p[1], e.p[2], w[0], w[1], w[2]};
   int r = 0;
   for (int i = 0; i < 6; ++i) if ((mask >> i) & 1) out[r++] = all[i];
@@ -257,8 +262,9 @@ Targets make_targets(const Scene& s) {
   return t;
 }
 
-// Stacked residual F(q) (rows in block order).
-template <class T> void residual(const Scene& s, const Targets& tg, const T* q, T* F) {
+// Stacked residual F(q) (rows in block order). max_theta (nullable) is raised to the largest
+// rotation angle of the pose and relative-pose errors.
+template <class T> void residual(const Scene& s, const Targets& tg, const T* q, T* F, double* max_theta = nullptr) {
   std::vector<Tf<T>> link;
   if (!s.joints.empty()) forward_kinematics<T>(s, q, link);
   int r = 0;
@@ -268,12 +274,12 @@ template <class T> void residual(const Scene& s, const Targets& tg, const T* q, 
     for (int i = 0; i < 3; ++i) { for (int c = 0; c < 3; ++c) Tref.R[i][c] = T(tg.T[k].R[i][c]); Tref.p[i] = T(tg.T[k].p[i]); }
     switch (b.type) {
       case B_POSE: {  // Eq. 1: T_err = T_ref^-1 T_frame
-        r += pose_rows(tf_mul(tf_inv(Tref), frame_pose(s, link, b.fa)), b.mask, F + r);
+        r += pose_rows(tf_mul(tf_inv(Tref), frame_pose(s, link, b.fa)), b.mask, F + r, max_theta);
         break;
       }
       case B_REL: {   // Eq. 2: T_err = T_ref^-1 (T_a^-1 T_b)
         Tf<T> rel = tf_mul(tf_inv(frame_pose(s, link, b.fa)), frame_pose(s, link, b.fb));
-        r += pose_rows(tf_mul(tf_inv(Tref), rel), b.mask, F + r);
+        r += pose_rows(tf_mul(tf_inv(Tref), rel), b.mask, F + r, max_theta);
         break;
       }
       case B_AXIS: {  // frame z-axis parallel to world z: x and y components of R e_z
@@ -447,6 +453,22 @@ bool descent_step(int m, int d, const double* J, const double* F, double lambda,
 
 double norm2(const double* x, int n) { double a = 0; for (int i = 0; i < n; ++i) a += x[i] * x[i]; return std::sqrt(a); }
 
+// Path record of one projection (nullable), used by the parity tests to recognise outcomes that are
+// not well posed for an exact comparison: [0] smallest sigma_min(J) over the steps taken, [1] longest
+// step, [2] largest rotation angle of a pose error at any residual evaluation, [3] smallest
+// multiplicative distance max(||F|| / tol, tol / ||F||) of a convergence test to the tolerance.
+constexpr int kPathCols = 4;
+void path_init(double* path) {
+  if (!path) return;
+  path[0] = INFINITY; path[1] = 0.0; path[2] = 0.0; path[3] = INFINITY;
+}
+void path_note_test(double* path, double nF, double tol, double theta) {
+  if (!path) return;
+  const double ratio = nF > tol ? nF / tol : tol / nF;  // +inf for nF = 0
+  path[3] = std::min(path[3], ratio);
+  path[2] = std::max(path[2], theta);
+}
+
 // Cyclic mode of ParallelProject (Alg. 2 with getDescentStep looping over the constraints,
 // Sec. IV-C): each iteration first evaluates the whole stacked residual for the convergence
 // test, then, for each constraint block in the scene's order, takes the min-norm step of that
@@ -458,10 +480,12 @@ void project_one_cyclic(const Scene& s, const Targets& tg, const Opts& o, const 
   const int d = s.d, m = s.m;
   std::vector<double> F(m), J(size_t(m) * d), delta(d), qs(d);
   for (int j = 0; j < d; ++j) q[j] = q0[j];
-  if (path) { path[0] = INFINITY; path[1] = 0.0; }
+  path_init(path);
   for (int k = 0;; ++k) {
-    residual<double>(s, tg, q, F.data());
+    double theta = 0.0;
+    residual<double>(s, tg, q, F.data(), &theta);
     double nF = norm2(F.data(), m);
+    path_note_test(path, nF, o.tol, theta);
     *resid = nF;
     *iters = k;
     if (!all_finite(F.data(), m) || !all_finite(q, d)) { *status = ST_NONFINITE; return; }
@@ -471,7 +495,9 @@ void project_one_cyclic(const Scene& s, const Targets& tg, const Opts& o, const 
     int r0 = 0;
     for (const auto& b : s.blocks) {
       const int mb = block_rows(b, s);
-      residual<double>(s, tg, q, F.data());
+      double theta_b = 0.0;
+      residual<double>(s, tg, q, F.data(), &theta_b);
+      if (path) path[2] = std::max(path[2], theta_b);
       jacobian(s, tg, q, J.data());
       if (!all_finite(J.data() + size_t(r0) * d, mb * d)) { *status = ST_NONFINITE; return; }
       double smin = 0.0;
@@ -496,17 +522,18 @@ void project_one_cyclic(const Scene& s, const Targets& tg, const Opts& o, const 
 }
 
 // ParallelProject for one configuration (Alg. 2), per-configuration termination.
-// path (nullable) receives {smallest sigma_min(J) over the steps taken, longest step}, used by
-// the parity tests to recognise ill-conditioned projection paths.
+// path (nullable): the path record described at path_init.
 void project_one(const Scene& s, const Targets& tg, const Opts& o, const double* q0, double* q,
                  int8_t* status, int32_t* iters, double* resid, double* path = nullptr) {
   const int d = s.d, m = s.m;
   std::vector<double> F(m), J(size_t(m) * d), delta(d);
   for (int j = 0; j < d; ++j) q[j] = q0[j];
-  if (path) { path[0] = INFINITY; path[1] = 0.0; }
+  path_init(path);
   for (int k = 0;; ++k) {
-    residual<double>(s, tg, q, F.data());
+    double theta = 0.0;
+    residual<double>(s, tg, q, F.data(), &theta);
     double nF = norm2(F.data(), m);
+    path_note_test(path, nF, o.tol, theta);
     *resid = nF;
     *iters = k;
     if (!all_finite(F.data(), m) || !all_finite(q, d)) { *status = ST_NONFINITE; return; }
@@ -628,7 +655,7 @@ int oracle_jacobian(const void* blob, size_t nbytes, int64_t n, const double* q,
 }
 
 // Projection of n configurations (row-major [n][d]).
-// path_info (nullable) [n][2]: smallest sigma_min(J) along the path, longest step.
+// path_info (nullable) [n][4]: the path record described at path_init.
 // mode 0: stacked system per step; mode 1: cyclic over the constraint blocks.
 int oracle_project(const void* blob, size_t nbytes, int64_t n, const double* q_in, double* q_out,
                    int8_t* status, int32_t* iters, double* resid, double tol, int32_t max_iter,
@@ -640,7 +667,7 @@ int oracle_project(const void* blob, size_t nbytes, int64_t n, const double* q_i
   Opts o{tol, max_iter, alpha, lambda, max_step, mode};
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads_or_default(nthreads))
   for (int64_t i = 0; i < n; ++i) {
-    double* pi = path_info ? path_info + 2 * i : nullptr;
+    double* pi = path_info ? path_info + kPathCols * i : nullptr;
     if (mode == 1)
       project_one_cyclic(s, tg, o, q_in + i * s.d, q_out + i * s.d, status + i, iters + i, resid + i, pi);
     else
@@ -690,6 +717,55 @@ int oracle_vjp(const void* blob, size_t nbytes, int64_t n, const double* q, cons
     for (int j = m; j < d; ++j) w[j] = 0.0;                                              // keep Q^T g
     for (int k = m - 1; k >= 0; --k) apply_reflector(d, k, At.data(), tau.data(), w.data());  // w = Q Q^T g
     for (int j = 0; j < d; ++j) out[j] = gc[j] - w[j];
+  }
+  return 0;
+}
+
+// Condition estimate of J J^T + lambda I that decides the FP32 -> FP64 switch: the Cholesky factor
+// L (textbook row-by-row algorithm, FP64) gives kappa_est = (max L_ii / min L_ii)^2, a lower bound
+// of the spectral condition number; kappa_est = +inf when a pivot is not positive. kappa2 (nullable)
+// receives (sigma_max / sigma_min)^2 of J from the singular values.
+int oracle_kappa_est(const void* blob, size_t nbytes, int64_t n, const double* q, double lambda, double* kappa_est,
+                     double* kappa2, int nthreads) {
+  Scene s;
+  if (!parse(blob, nbytes, s)) return 1;
+  Targets tg = make_targets(s);
+  const int d = s.d, m = s.m;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads_or_default(nthreads))
+  for (int64_t c = 0; c < n; ++c) {
+    std::vector<double> J(size_t(m) * d), G(size_t(m) * m, 0.0), L(size_t(m) * m, 0.0);
+    jacobian(s, tg, q + c * d, J.data());
+    for (int i = 0; i < m; ++i)
+      for (int k = 0; k < m; ++k) {
+        double acc = i == k ? lambda : 0.0;
+        for (int j = 0; j < d; ++j) acc += J[size_t(i) * d + j] * J[size_t(k) * d + j];
+        G[size_t(i) * m + k] = acc;
+      }
+    bool ok = true;
+    double lmin = INFINITY, lmax = 0.0;
+    for (int i = 0; i < m && ok; ++i) {
+      for (int k = 0; k <= i; ++k) {
+        double acc = G[size_t(i) * m + k];
+        for (int j = 0; j < k; ++j) acc -= L[size_t(i) * m + j] * L[size_t(k) * m + j];
+        if (i == k) {
+          if (!(acc > 0.0)) { ok = false; break; }
+          L[size_t(i) * m + i] = std::sqrt(acc);
+          lmin = std::min(lmin, L[size_t(i) * m + i]);
+          lmax = std::max(lmax, L[size_t(i) * m + i]);
+        } else {
+          L[size_t(i) * m + k] = acc / L[size_t(k) * m + k];
+        }
+      }
+    }
+    kappa_est[c] = ok ? (lmax / lmin) * (lmax / lmin) : INFINITY;
+    if (kappa2) {
+      std::vector<double> At(size_t(d) * m), sv(m);
+      for (int i = 0; i < m; ++i) for (int j = 0; j < d; ++j) At[size_t(i) * d + j] = J[size_t(i) * d + j];
+      jacobi_singular_values(d, m, At.data(), sv.data());
+      double smax = 0, smin = INFINITY;
+      for (double x : sv) { smax = std::max(smax, x); smin = std::min(smin, x); }
+      kappa2[c] = (smax / smin) * (smax / smin);
+    }
   }
   return 0;
 }

@@ -197,3 +197,14 @@ def test_linear_off_manifold_particles_take_one_textbook_step():
     assert code == OX.OK
     gaps = np.linalg.norm(chain[1:] - chain[:-1], axis=1)
     np.testing.assert_allclose(gaps, D / (chain.shape[0] - 1), rtol=1e-10)
+
+
+def test_sphere_interpolated_point_at_the_origin_fails():
+    """Target opposite the start with r = 2: the steer point is the antipode itself (on the sphere, no
+    step), q_proj = -s passes both first exits (||q_proj - s|| = 2 <= 2 dist = 4), and with n = 3 the
+    middle interpolated point s + (q_proj - s) / 2 is the origin, where the Jacobian 2q vanishes and
+    no step exists: INTERP_FAILED, with the particle selected."""
+    P = sphere_problem()
+    code, best, qp, chain = OX.extend_one(P, S0, -S0, np.zeros(3), r=2.0, delta=0.1, tol=1e-8, max_iter=50)
+    assert code == OX.INTERP_FAILED and best == 0 and chain is None
+    np.testing.assert_array_equal(qp, -S0)

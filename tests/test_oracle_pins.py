@@ -609,3 +609,117 @@ def test_cyclic_with_one_block_is_the_stacked_iteration(oracle_mod):
     b = P.project(q, tol=1e-6, max_iter=50, mode="cyclic")
     for x, y in zip(a, b):
         np.testing.assert_array_equal(x, y)
+
+
+# ---------------------------------------------------------------- interpolation (Alg. 2, interpolation step)
+def test_interpolate_interior_points_are_equally_spaced_chord_points(oracle_mod):
+    """Geodesic g with L_g points: the points lie on the chord a -> b, strictly inside it, spaced
+    (b - a) / (L_g + 1) apart from a on, and the last one sits (b - a) / (L_g + 1) before b; an empty
+    geodesic contributes nothing. Checked against exact rationals for a small integer case."""
+    from fractions import Fraction
+    import oracle
+    rng = np.random.default_rng(4)
+    e = rng.standard_normal((4, 2, 5))
+    offs = np.array([0, 3, 3, 10, 11], np.int32)  # lengths 3, 0, 7, 1
+    out = oracle.interpolate_interior(e, offs)
+    assert out.shape == (11, 5)
+    for g in range(4):
+        L = offs[g + 1] - offs[g]
+        pts = out[offs[g]:offs[g + 1]]
+        a, b = e[g, 0], e[g, 1]
+        if L == 0:
+            continue
+        step = (b - a) / (L + 1)
+        np.testing.assert_allclose(pts[0] - a, step, atol=1e-14)
+        np.testing.assert_allclose(b - pts[-1], step, atol=1e-14)
+        np.testing.assert_allclose(np.diff(pts, axis=0), np.broadcast_to(step, (L - 1, 5)), atol=1e-14)
+    # integers: a = (0, 3), b = (4, -1), 3 points at t = 1/4, 2/4, 3/4
+    e2 = np.array([[[0.0, 3.0], [4.0, -1.0]]])
+    got = oracle.interpolate_interior(e2, np.array([0, 3]))
+    want = [[float(Fraction(4 * k, 4)), float(3 - Fraction(4 * k, 4))] for k in (1, 2, 3)]
+    np.testing.assert_array_equal(got, want)
+
+
+# ---------------------------------------------------------------- path record used by the parity band
+def test_path_record_tolerance_distance_follows_heron(oracle_mod):
+    """On the sphere the convergence tests see |r_k^2 - 1| of the Heron radii: the record's column 3
+    is the smallest max(t / tol, tol / t) over them; no pose block, so column 2 stays 0; the longest
+    step is the longest radial step and the smallest singular value 2 min r_k over the steps taken."""
+    P = prob(S.sphere_scene(0))
+    u = np.array([0.0, 0.6, 0.8])
+    for r0 in (0.5, 0.9, 2.0):
+        r, tests, steps, radii = r0, [], [], []
+        while True:
+            tests.append(abs(r * r - 1.0))
+            if tests[-1] < 1e-6:
+                break
+            rn = 0.5 * (r + 1.0 / r)
+            steps.append(abs(rn - r))
+            radii.append(r)
+            r = rn
+        want = min(max(t / 1e-6, 1e-6 / t) for t in tests)
+        _, st, it, _, pi = P.project((r0 * u)[None], tol=1e-6, max_iter=50, path_info=True)
+        assert st[0] == CONV
+        np.testing.assert_allclose(pi[0, 3], want, rtol=1e-7)  # r^2 - 1 cancels near r = 1
+        assert pi[0, 2] == 0.0
+        np.testing.assert_allclose(pi[0, 1], max(steps), rtol=1e-12)
+        np.testing.assert_allclose(pi[0, 0], 2 * min(radii), rtol=1e-9)  # sigma(J) = 2 ||q|| at each step
+
+
+def test_path_record_rotation_angle_of_a_pose_error(oracle_mod):
+    """One revolute joint about z carrying a frame with a full pose block whose target rotation is
+    theta_ref about z: the rotation error at q0 is |q0 - theta_ref| (wrapped to [0, pi]) and the
+    iteration only reduces it, so the record's column 2 is the initial angle."""
+    I = np.eye(3)
+    th = 0.4
+    Rr = Rotation.from_rotvec([0, 0, th]).as_matrix()
+    joints = [S.Joint(-1, S.JOINT_REV, 2, I, np.zeros(3))] + \
+        [S.Joint(k, S.JOINT_REV, 2, I, np.array([0.5, 0, 0])) for k in range(5)]
+    blk = S.Block(S.BLK_POSE, fa=0, mask=0x3F, R=Rr, p=np.zeros(3))
+    sc = S.Scene(family=S.FAMILY_PLANAR2, d=6, m=6, joints=joints, masses=np.ones(6), coms=np.zeros((6, 3)),
+                 frames=[S.Frame(0, I, np.zeros(3))], blocks=[blk], spheres=np.zeros((0, 5)),
+                 obstacles=np.zeros((0, 4)))
+    P = prob(sc)
+    for q0, ang in ((3.2, 2.8), (-2.3, 2.7), (1.0, 0.6)):
+        q = np.array([[q0, 0.7, 0.1, 0.2, 0.3, 0.4]])
+        _, st, _, _, pi = P.project(q, tol=1e-9, max_iter=50, lam=1e-3, path_info=True)
+        np.testing.assert_allclose(pi[0, 2], ang, rtol=1e-12)
+
+
+# ---------------------------------------------------------------- condition estimate of the FP64 switch
+def test_kappa_est_linear_closed_forms(oracle_mod):
+    """F = A q - b has J = A. Orthogonal rows of norms 1, 3, 10: J J^T = diag(1, 9, 100), so the
+    Cholesky diagonal is (1, 3, 10) and kappa_est = 100 = kappa_2. General A: kappa_est equals the
+    ratio from numpy's Cholesky of A A^T, and never exceeds kappa_2 (numpy's singular values)."""
+    Q, _ = np.linalg.qr(np.random.default_rng(2).standard_normal((6, 6)))
+    A = np.diag([1.0, 3.0, 10.0]) @ Q[:3]
+    P = prob(S.linear_scene(A, np.zeros(3)))
+    ke, k2 = P.kappa_est(np.zeros((1, 6)))
+    np.testing.assert_allclose([ke[0], k2[0]], [100.0, 100.0], rtol=1e-12)
+    rng = np.random.default_rng(9)
+    for m, d in ((2, 5), (4, 8), (6, 8)):
+        A = rng.standard_normal((m, d)) * rng.uniform(0.1, 10.0, (m, 1))
+        P = prob(S.linear_scene(A, np.zeros(m)))
+        ke, k2 = P.kappa_est(rng.standard_normal((3, d)))
+        L = np.linalg.cholesky(A @ A.T)
+        dg = np.diag(L)
+        np.testing.assert_allclose(ke, (dg.max() / dg.min()) ** 2, rtol=1e-10)
+        sv = np.linalg.svd(A, compute_uv=False)
+        np.testing.assert_allclose(k2, (sv.max() / sv.min()) ** 2, rtol=1e-9)
+        assert (ke <= k2 * (1 + 1e-12)).all()
+    # a rank-deficient Gram: a pivot is not positive
+    A = np.array([[1.0, 2.0, 0.0], [2.0, 4.0, 0.0]])
+    ke, _ = prob(S.linear_scene(A, np.zeros(2))).kappa_est(np.zeros((1, 3)))
+    assert ke[0] == np.inf or ke[0] > 1e28
+
+
+@pytest.mark.parametrize("name", ["c1", "c3"])
+def test_kappa_est_is_a_lower_bound_of_kappa2(oracle_mod, name):
+    """(max L_ii / min L_ii)^2 <= kappa_2(J J^T) for any SPD Gram (the diagonal of L is bounded by the
+    extreme singular values), on the robots' own Jacobians."""
+    from parity import config_inputs
+    sc, P, q, offs, tol, mi = config_inputs(name, small=True, max_geo=4)
+    ke, k2 = P.kappa_est(q)
+    fin = np.isfinite(ke)
+    assert fin.mean() > 0.99
+    assert (ke[fin] <= k2[fin] * (1 + 1e-9)).all()
