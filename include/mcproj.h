@@ -87,7 +87,10 @@ typedef struct {
                                  the step is redone in FP64 and that configuration takes FP64
                                  steps until it terminates                                     */
   int32_t check_collision;    /* 1: collision-check CONVERGED configurations into `verdict`      */
-  int32_t variant;            /* 0 auto (autotuned), 1 plain (one launch per geodesic),
+  int32_t variant;            /* 0 auto: the fused variant, with the launch shape that
+                                 mc_autotune_project stored in the problem for this dtype and mode
+                                 (where the shape fields below are left at 0), else the library's
+                                 default shape; 1 plain (one launch per geodesic);
                                  2 fused (persistent work-queue kernel over the whole batch)     */
   int32_t waves_per_block;    /* fused variant: 1, 2 or 4 wavefronts per workgroup (0 = auto)   */
   int32_t blocks_per_cu;      /* fused variant: resident workgroups per CU for the persistent
@@ -99,10 +102,13 @@ typedef struct {
                                  per constraint block, in the scene's block order, each from the
                                  configuration the previous one left; an iteration is one cycle
                                  and max_step bounds its total displacement. Fused variant only. */
+  int32_t lanes_per_config;   /* lanes that share one configuration in the projection kernels:
+                                 0 = auto, 1 = one configuration per lane (the only build of the
+                                 projection kernels; the check kernels pick their own lane groups) */
 } mc_project_opts;
 
 /* Default options (tol 1e-6, max_iter 50, alpha 1, lambda 0, max_step off, threshold 1e6,
-   check on, variant auto, stacked mode). */
+   check on, variant auto, stacked mode, launch shape auto). */
 void mc_default_opts(mc_project_opts* opts);
 
 /* Create a problem from a scene blob (magic 'MCCS', version 1: the little-endian layout written
@@ -139,11 +145,16 @@ const char* mc_last_error(void);
      resid  dtype      ||F|| at the last evaluation
      verdict uint8     nullable; MC_FREE / MC_COLLIDES, MC_UNCHECKED when not CONVERGED or
                        check_collision == 0
-   geo_offsets (nullable, int32[n_geo + 1], device) describes the batch as n_geo geodesics
-   (CSR offsets, geo_offsets[0] = 0, geo_offsets[n_geo] = n). The plain variant needs it on the
-   HOST as well: pass geo_offsets_host (nullable) with the same content. geo_ok (nullable,
-   uint8[n_geo], device) receives 1 when every configuration of the geodesic converged and is
-   collision-free (the early exit of Alg. 2 as a per-geodesic flag).
+   In MC_F32 mode the iterate is held in FP64 on the device: status, iters, resid and verdict
+   describe that FP64 iterate, and q_out is its rounding to float (whose residual can exceed tol
+   by up to ||J|| ||q|| 2^-24).
+   geo_offsets (nullable, int32[n_geo + 1], DEVICE pointer) describes the batch as n_geo geodesics
+   (CSR offsets, geo_offsets[0] = 0, geo_offsets[n_geo] = n). geo_offsets_host (nullable, int32
+   [n_geo + 1]) is the one HOST pointer of the call, read synchronously before the call returns:
+   the plain variant launches one kernel per geodesic and needs every geodesic's bounds on the host
+   (it is required there and ignored by the fused variant). geo_ok (nullable, uint8[n_geo], device)
+   receives 1 when every configuration of the geodesic converged and is collision-free (the early
+   exit of Alg. 2 as a per-geodesic flag).
    Workspace: in MC_F32 mode the fused variant hands configurations that need FP64 steps to a
    second kernel through a queue owned by the problem; a call with a larger n than any before
    grows it (hipFree + hipMalloc, which synchronise the device). Calls on one problem must not
@@ -179,10 +190,13 @@ mc_status project_vjp(const mc_problem* p, int64_t n, const void* q_proj, int64_
 /* interpolate_geodesics — the interpolation step of Alg. 2: geodesic g gets
    L_g = geo_offsets[g+1] - geo_offsets[g] interior points q_a + t_k (q_b - q_a),
    t_k = k / (L_g + 1), k = 1..L_g, written to q_out[:, geo_offsets[g] + k - 1].
-   endpoints [d][2 * n_geo] (column 2g = q_a, 2g+1 = q_b), ld_e >= 2 n_geo. */
+   endpoints [d][2 * n_geo] (column 2g = q_a, 2g+1 = q_b), ld_e >= 2 n_geo. total is the
+   caller's geo_offsets[n_geo] (the number of interior points; the call reads nothing back from the
+   device, so it is asynchronous and capturable); points past min(total, geo_offsets[n_geo]) are
+   not written. ld_out >= total. */
 mc_status interpolate_geodesics(const mc_problem* p, int32_t n_geo, const int32_t* geo_offsets,
-                                const void* endpoints, int64_t ld_e, void* q_out, int64_t ld_out,
-                                mc_dtype dtype, void* stream);
+                                const void* endpoints, int64_t ld_e, int64_t total, void* q_out,
+                                int64_t ld_out, mc_dtype dtype, void* stream);
 
 /* path_length_grad — path-length loss over geodesics and its gradient:
    L = sum_g sum_i ||q_{i+1} - q_i||, g_out[:, i] = u_{i-1} - u_i with u = delta / max(||delta||, 1e-12)
@@ -249,6 +263,55 @@ mc_status extend_batch(const mc_problem* p, int64_t E, const void* q_start, cons
                        int64_t ld, const void* eps, const mc_extend_opts* xopts,
                        const mc_project_opts* opts, void* q_out, int64_t ld_out, int8_t* result,
                        int32_t* particle, int32_t* n_points, void* stream);
+
+/* mc_eval_condition — diagnostic: the condition estimate that decides the FP32 -> FP64 switch,
+   kappa_est = (max L_ii / min L_ii)^2 of the Cholesky factor of J J^T + lambda I, computed as the
+   projection kernels compute it (MC_F32: FP32 Jacobian columns, Gram and factorisation; MC_F64:
+   FP64), or +inf where the factorisation fails. q [d][ld] and kappa [n] are of dtype. */
+mc_status mc_eval_condition(const mc_problem* p, int64_t n, const void* q, int64_t ld, mc_dtype dtype,
+                            double lambda, void* kappa, void* stream);
+
+/* mc_queue_counts — diagnostic: the problem's four device queue counters after the last call
+   (synchronises the device): [0] work items taken from the persistent kernel's queue beyond the
+   static share, [1] projections continued in FP64, [2] VJPs redone in FP64, [3] configurations
+   queued for the exact collision check. */
+mc_status mc_queue_counts(const mc_problem* p, uint32_t counts[4]);
+
+/* mc_set_kernel_timing — diagnostic: when on, project_batch brackets its main projection launch
+   (the persistent kernel of the fused variant, all per-geodesic launches of the plain one) and
+   project_vjp its main VJP launch with HIP events on the call's stream; mc_last_kernel_ms waits for
+   the last such call and returns the time between its two events (which = 0: projection, 1: VJP).
+   The time excludes the queue reset and the FP64 and exact-check tail launches. Off by default;
+   turning it on creates the events (not under stream capture). */
+mc_status mc_set_kernel_timing(mc_problem* p, int32_t on);
+mc_status mc_last_kernel_ms(const mc_problem* p, int32_t which, float* ms);
+
+/* Launch shape of the fused projection. */
+typedef struct {
+  int32_t waves_per_block;  /* 1, 2 or 4                                        */
+  int32_t blocks_per_cu;    /* 0 = occupancy limit, else 1..64                  */
+  int32_t lanes_per_config; /* 1                                                */
+} mc_launch_shape;
+
+/* mc_autotune_candidates — number of launch shapes mc_autotune_project tries; shapes (nullable)
+   receives them in the order their timings are reported. */
+int32_t mc_autotune_candidates(mc_launch_shape* shapes);
+
+/* mc_autotune_project — the library's launch-shape autotuner: runs the fused projection of the
+   batch q_in (opts as for project_batch; variant and shape fields are ignored) once per candidate
+   shape to warm up and then `reps` times under HIP events on `stream`, checks that every candidate
+   gives bit-identical outputs (q_out, status, iters, resid, verdict; else MC_ERR_HIP with a message
+   naming the shape), and stores the fastest shape in the problem for opts->dtype and opts->mode.
+   best (nullable) receives it, ms (nullable, float[mc_autotune_candidates()]) the mean time per
+   call of every candidate. The batch itself is only read. Allocates temporary outputs and
+   synchronises the device (a set-up call, not for the hot loop). reps in 1..1000. */
+mc_status mc_autotune_project(mc_problem* p, int64_t n, const void* q_in, int64_t ld_in,
+                              const mc_project_opts* opts, int32_t reps, void* stream,
+                              mc_launch_shape* best, float* ms);
+
+/* mc_tuned_shape — the shape stored by mc_autotune_project for (dtype, mode); MC_ERR_INVALID_ARG
+   when none is stored. */
+mc_status mc_tuned_shape(const mc_problem* p, mc_dtype dtype, int32_t mode, mc_launch_shape* out);
 
 /* mc_fallback_count — number of configurations moved to FP64 (projections that switched to FP64
    steps, VJPs redone in FP64) by the calls enqueued on this problem since it was created or last

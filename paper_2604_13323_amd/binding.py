@@ -34,7 +34,16 @@ class Opts(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("lambda_", ctypes.c_double), ("max_step", ctypes.c_double),
                 ("fp64_cond_threshold", ctypes.c_double), ("check_collision", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("mode", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("lanes_per_config", ctypes.c_int32)]
+
+
+class LaunchShape(ctypes.Structure):
+    _fields_ = [("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("lanes_per_config", ctypes.c_int32)]
+
+    def as_dict(self):
+        return dict(waves_per_block=self.waves_per_block, blocks_per_cu=self.blocks_per_cu,
+                    lanes_per_config=self.lanes_per_config)
 
 
 class ExtendOpts(ctypes.Structure):
@@ -45,7 +54,9 @@ _lib = None
 
 EXPORTS = ["mc_default_opts", "mc_problem_create", "mc_problem_destroy", "mc_problem_dof", "mc_problem_rows",
            "mc_problem_family", "mc_last_error", "project_batch", "check_batch", "project_vjp",
-           "interpolate_geodesics", "path_length_grad", "mc_eval_residual_jacobian", "mc_fallback_count", "extend_batch"]
+           "interpolate_geodesics", "path_length_grad", "mc_eval_residual_jacobian", "mc_fallback_count", "extend_batch",
+           "mc_eval_condition", "mc_queue_counts", "mc_autotune_candidates", "mc_autotune_project", "mc_tuned_shape",
+           "mc_set_kernel_timing", "mc_last_kernel_ms"]
 
 
 def lib():
@@ -70,15 +81,24 @@ def lib():
     L.project_batch.argtypes = [P, I64, P, I64, P, I64, P, P, P, P, P, P, I32, P, ctypes.POINTER(Opts), P]
     L.check_batch.argtypes = [P, I64, P, I64, ctypes.c_int, P, P, P]
     L.project_vjp.argtypes = [P, I64, P, I64, P, P, P, ctypes.POINTER(Opts), P]
-    L.interpolate_geodesics.argtypes = [P, I32, P, P, I64, P, I64, ctypes.c_int, P]
+    L.interpolate_geodesics.argtypes = [P, I32, P, P, I64, I64, P, I64, ctypes.c_int, P]
     L.path_length_grad.argtypes = [P, I64, P, I64, P, I32, P, P, ctypes.c_int, P]
     L.mc_eval_residual_jacobian.argtypes = [P, I64, P, I64, ctypes.c_int, P, P, P]
     L.mc_fallback_count.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
     L.extend_batch.argtypes = [P, I64, P, P, I64, P, ctypes.POINTER(ExtendOpts), ctypes.POINTER(Opts), P, I64, P, P,
                                P, P]
+    L.mc_eval_condition.argtypes = [P, I64, P, I64, ctypes.c_int, ctypes.c_double, P, P]
+    L.mc_queue_counts.argtypes = [P, ctypes.POINTER(ctypes.c_uint32)]
+    L.mc_autotune_candidates.argtypes = [ctypes.POINTER(LaunchShape)]
+    L.mc_autotune_candidates.restype = I32
+    L.mc_autotune_project.argtypes = [P, I64, P, I64, ctypes.POINTER(Opts), I32, P, ctypes.POINTER(LaunchShape),
+                                      ctypes.POINTER(ctypes.c_float)]
+    L.mc_tuned_shape.argtypes = [P, ctypes.c_int, I32, ctypes.POINTER(LaunchShape)]
+    L.mc_set_kernel_timing.argtypes = [P, I32]
+    L.mc_last_kernel_ms.argtypes = [P, I32, ctypes.POINTER(ctypes.c_float)]
     for f in EXPORTS:
         if f not in ("mc_default_opts", "mc_problem_destroy", "mc_problem_dof", "mc_problem_rows",
-                     "mc_problem_family", "mc_last_error"):
+                     "mc_problem_family", "mc_last_error", "mc_autotune_candidates"):
             getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -119,7 +139,7 @@ MODES = {"stacked": 0, "cyclic": 1}
 
 
 def make_opts(dtype=MC_F32, tol=1e-6, max_iter=50, alpha=1.0, lam=0.0, max_step=0.0, cond=1e6, check=True,
-              variant="auto", waves_per_block=0, blocks_per_cu=0, mode="stacked") -> Opts:
+              variant="auto", waves_per_block=0, blocks_per_cu=0, mode="stacked", lanes_per_config=0) -> Opts:
     o = Opts()
     lib().mc_default_opts(ctypes.byref(o))
     o.dtype = dtype
@@ -134,6 +154,7 @@ def make_opts(dtype=MC_F32, tol=1e-6, max_iter=50, alpha=1.0, lam=0.0, max_step=
     o.waves_per_block = waves_per_block
     o.blocks_per_cu = blocks_per_cu
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    o.lanes_per_config = lanes_per_config
     return o
 
 
@@ -180,7 +201,8 @@ class Problem:
     # -- projection -------------------------------------------------------
     def project(self, q: torch.Tensor, tol=1e-6, max_iter=50, alpha=1.0, lam=0.0, max_step=0.0, cond=1e6,
                 check=True, variant="auto", geo_offsets=None, geo_ok=False, waves_per_block=0, blocks_per_cu=0,
-                out: ProjectResult | None = None, geo_offsets_host=None, mode="stacked") -> ProjectResult:
+                out: ProjectResult | None = None, geo_offsets_host=None, mode="stacked",
+                lanes_per_config=0) -> ProjectResult:
         """Project the columns of q ([d, n], float32 or float64). geo_offsets (CSR, int32) may be a host array
         or a device tensor; the plain variant also needs them on the host (geo_offsets_host, or a host
         geo_offsets). Under stream capture pass device offsets, `out`, and call once eagerly beforehand with a
@@ -213,7 +235,7 @@ class Problem:
             if geo_ok and out.geo_ok is None:
                 out.geo_ok = torch.empty(n_geo, dtype=torch.uint8, device=dev)
         o = make_opts(dt, tol, max_iter, alpha, lam, max_step, cond, check, variant, waves_per_block, blocks_per_cu,
-                      mode)
+                      mode, lanes_per_config)
         rc = lib().project_batch(self._h, n, _ptr(q), ld, _ptr(out.q), out.q.stride(0), _ptr(out.status),
                                  _ptr(out.iters), _ptr(out.resid), _ptr(out.verdict), _ptr(offs_dev),
                                  None if offs_host is None else offs_host.ctypes.data_as(ctypes.c_void_p),
@@ -253,29 +275,33 @@ class Problem:
         return (v, sd) if min_signed_dist else v
 
     def vjp(self, q_proj: torch.Tensor, status: torch.Tensor, g_out: torch.Tensor, cond=1e6):
+        """g_in [d, n] of q_proj's dtype; q_proj, g_out and g_in share one leading dimension (g_in is
+        allocated with q_proj's strides, so a column slice of a wider array is handled in place)."""
         n, ld = _soa(q_proj, self.d, "vjp")
         if g_out.shape != q_proj.shape or g_out.stride() != q_proj.stride() or g_out.dtype != q_proj.dtype:
             g_out = g_out.to(q_proj.dtype).contiguous()
             q_proj = q_proj.contiguous()
             ld = q_proj.stride(0)
-        g_in = torch.empty_like(q_proj)
+        g_in = torch.empty_strided(q_proj.shape, q_proj.stride(), dtype=q_proj.dtype, device=q_proj.device)
         o = make_opts(_dtype_code(q_proj), cond=cond)
         _check(lib().project_vjp(self._h, n, _ptr(q_proj), ld, _ptr(status), _ptr(g_out), _ptr(g_in),
                                  ctypes.byref(o), _stream()), "project_vjp")
         return g_in
 
     def interpolate(self, endpoints: torch.Tensor, geo_offsets: torch.Tensor, total: int):
-        """endpoints [d, 2 n_geo] (columns 2g, 2g+1 = the two ends); geo_offsets int32 device [n_geo + 1]."""
+        """endpoints [d, 2 n_geo] (columns 2g, 2g+1 = the two ends); geo_offsets int32 device [n_geo + 1];
+        total = geo_offsets[n_geo] (known to the caller, so nothing is read back from the device)."""
         n_geo = geo_offsets.numel() - 1
         out = torch.empty((self.d, total), dtype=endpoints.dtype, device=endpoints.device)
         _check(lib().interpolate_geodesics(self._h, n_geo, _ptr(geo_offsets), _ptr(endpoints), endpoints.stride(0),
-                                           _ptr(out), out.stride(0), _dtype_code(endpoints), _stream()),
+                                           int(total), _ptr(out), out.stride(0), _dtype_code(endpoints), _stream()),
                "interpolate_geodesics")
         return out
 
     def path_length_grad(self, q: torch.Tensor, geo_offsets: torch.Tensor, with_loss=True):
+        """Gradient [d, n] with q's strides (the library writes it with q's leading dimension)."""
         n, ld = _soa(q, self.d, "path_length_grad")
-        g = torch.empty_like(q)
+        g = torch.empty_strided(q.shape, q.stride(), dtype=q.dtype, device=q.device)
         loss = torch.empty(1, dtype=q.dtype, device=q.device) if with_loss else None
         _check(lib().path_length_grad(self._h, n, _ptr(q), ld, _ptr(geo_offsets), geo_offsets.numel() - 1, _ptr(g),
                                       _ptr(loss), _dtype_code(q), _stream()), "path_length_grad")
@@ -290,6 +316,51 @@ class Problem:
         _check(lib().mc_eval_residual_jacobian(self._h, n, _ptr(q), n, _dtype_code(q), _ptr(F), _ptr(J), _stream()),
                "mc_eval_residual_jacobian")
         return F, J
+
+    def condition(self, q: torch.Tensor, lam=0.0):
+        """The kernels' condition estimate (max L_ii / min L_ii)^2 of J J^T + lam I at every column of q
+        (+inf where the factorisation fails), in q's precision mode."""
+        n, ld = _soa(q, self.d, "condition")
+        k = torch.empty(n, dtype=q.dtype, device=q.device)
+        _check(lib().mc_eval_condition(self._h, n, _ptr(q), ld, _dtype_code(q), float(lam), _ptr(k), _stream()),
+               "mc_eval_condition")
+        return k
+
+    def queue_counts(self):
+        """[taken beyond the static share, FP64 projections, FP64 VJPs, exact collision checks] of the last calls."""
+        c = (ctypes.c_uint32 * 4)()
+        _check(lib().mc_queue_counts(self._h, c), "mc_queue_counts")
+        return [int(x) for x in c]
+
+    def autotune(self, q: torch.Tensor, reps=5, tol=1e-6, max_iter=50, cond=1e6, check=True, mode="stacked", **kw):
+        """The library's launch-shape autotuner on batch q; returns (best shape, [(shape, ms)])."""
+        n, ld = _soa(q, self.d, "autotune")
+        o = make_opts(_dtype_code(q), tol, max_iter, cond=cond, check=check, mode=mode, **kw)
+        nc = lib().mc_autotune_candidates(None)
+        shapes = (LaunchShape * nc)()
+        lib().mc_autotune_candidates(shapes)
+        ms = (ctypes.c_float * nc)()
+        best = LaunchShape()
+        _check(lib().mc_autotune_project(self._h, n, _ptr(q), ld, ctypes.byref(o), int(reps), _stream(),
+                                         ctypes.byref(best), ms), "mc_autotune_project")
+        return best.as_dict(), [(shapes[c].as_dict(), float(ms[c])) for c in range(nc)]
+
+    def tuned_shape(self, dtype=torch.float32, mode="stacked"):
+        """The shape the autotuner stored for (dtype, mode), or None."""
+        out = LaunchShape()
+        rc = lib().mc_tuned_shape(self._h, MC_F64 if dtype == torch.float64 else MC_F32, MODES[mode], ctypes.byref(out))
+        return out.as_dict() if rc == 0 else None
+
+    def kernel_timing(self, on=True):
+        """Bracket the main projection and VJP launches with HIP events (see last_kernel_ms)."""
+        _check(lib().mc_set_kernel_timing(self._h, 1 if on else 0), "mc_set_kernel_timing")
+
+    def last_kernel_ms(self, which="projection") -> float:
+        """Duration of the main kernel launch of the last timed project (or vjp) call; waits for it."""
+        ms = ctypes.c_float()
+        _check(lib().mc_last_kernel_ms(self._h, {"projection": 0, "vjp": 1}[which], ctypes.byref(ms)),
+               "mc_last_kernel_ms")
+        return float(ms.value)
 
     def fallback_count(self, reset=False) -> int:
         c = ctypes.c_uint64()

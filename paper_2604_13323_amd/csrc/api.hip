@@ -333,10 +333,10 @@ __device__ __forceinline__ int find_geo(const int32_t* offs, int n_geo, int64_t 
 }
 
 template <class IO>
-__global__ void k_interpolate(int n_geo, const int32_t* offs, const IO* e, int64_t ld_e, IO* q, int64_t ld, int d) {
-  const int64_t total = offs[n_geo];
+__global__ void k_interpolate(int n_geo, const int32_t* offs, const IO* e, int64_t ld_e, int64_t total, IO* q,
+                              int64_t ld, int d) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= total) return;
+  if (i >= total || i >= int64_t(offs[n_geo])) return;
   const int g = find_geo(offs, n_geo, i);
   const int L = offs[g + 1] - offs[g];
   if (L <= 0) return;
@@ -712,6 +712,12 @@ struct mc_problem {
   // queried once, so later calls (and calls under stream capture) make no runtime query
   mutable int occ[2][3] = {{0, 0, 0}, {0, 0, 0}};
   mutable int occ_wide = 0;  // resident 256-thread workgroups per CU of the two-wave launch
+  // launch shape stored by mc_autotune_project, by (FP64 mode, cyclic mode); waves_per_block 0 = none
+  mc_launch_shape tuned[2][2] = {{{0, 0, 0}, {0, 0, 0}}, {{0, 0, 0}, {0, 0, 0}}};
+  // mc_set_kernel_timing: events around the main projection launch [0, 1] and the VJP launch [2, 3]
+  bool timing = false;
+  hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
+  mutable bool timed[2] = {false, false};
   // extend_batch workspace (particle and level batches, chains, per-extension state), grown to
   // the largest call
   mutable unsigned char* x_arena = nullptr;
@@ -765,6 +771,7 @@ void mc_default_opts(mc_project_opts* o) {
   o->waves_per_block = 0;
   o->blocks_per_cu = 0;
   o->mode = 0;
+  o->lanes_per_config = 0;
 }
 
 int32_t mc_problem_dof(const mc_problem* p) { return p ? p->d : -1; }
@@ -773,6 +780,8 @@ int32_t mc_problem_family(const mc_problem* p) { return p ? p->family : -1; }
 
 void mc_problem_destroy(mc_problem* p) {
   if (!p) return;
+  for (hipEvent_t& ev : p->tev)
+    if (ev) (void)hipEventDestroy(ev);
   hipFree(p->dev);
   hipFree(p->obs);
   hipFree(p->counter);
@@ -978,14 +987,20 @@ static mc_status check_opts(const mc_problem* p, const mc_project_opts* o) {
   if (o->blocks_per_cu < 0 || o->blocks_per_cu > 64) return fail(MC_ERR_INVALID_ARG, "blocks_per_cu must be 0..64");
   if (o->mode != 0 && o->mode != 1) return fail(MC_ERR_INVALID_ARG, "mode must be 0 (stacked) or 1 (cyclic)");
   if (o->mode == 1 && o->variant == 1) return fail(MC_ERR_UNSUPPORTED, "the cyclic mode runs in the fused variant only");
+  if (o->lanes_per_config != 0 && o->lanes_per_config != 1)
+    return fail(MC_ERR_UNSUPPORTED, "lanes_per_config must be 0 (auto) or 1");
   (void)p;
   return MC_OK;
 }
 
-mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_t ld_in, void* q_out, int64_t ld_out,
-                        int8_t* status, int8_t* iters, void* resid, uint8_t* verdict, const int32_t* geo_offsets,
-                        const int32_t* geo_offsets_host, int32_t n_geo, uint8_t* geo_ok, const mc_project_opts* opts,
-                        void* stream) {
+}  // extern "C"
+
+// Body of project_batch (its workspace: the problem's queues, grown when a batch is larger than any
+// before).
+static mc_status project_impl(const mc_problem* p, int64_t n, const void* q_in, int64_t ld_in, void* q_out, int64_t ld_out,
+                              int8_t* status, int8_t* iters, void* resid, uint8_t* verdict, const int32_t* geo_offsets,
+                              const int32_t* geo_offsets_host, int32_t n_geo, uint8_t* geo_ok,
+                              const mc_project_opts* opts, void* stream) {
   g_err.clear();
   if (!p) return fail(MC_ERR_INVALID_ARG, "project_batch: null problem");
   if (n < 0) return fail(MC_ERR_INVALID_ARG, "project_batch: n < 0");
@@ -1006,6 +1021,7 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
   const FamilyOps* ops = ops_for(p->family, opts->dtype == MC_F64);
   if (!ops) return fail(MC_ERR_UNSUPPORTED, "project_batch: family without kernels");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned int* counter = p->counter;
 
   ProjArgs a;
   std::memset(&a, 0, sizeof a);
@@ -1024,24 +1040,37 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
   a.cond_thr = opts->fp64_cond_threshold;
   a.max_iter = opts->max_iter;
   a.check = opts->check_collision;
-  a.counter = p->counter;
+  a.counter = counter;
   a.n_sph = p->n_sph;
   a.n_obs = p->n_obs;
   hipError_t e;
   if (variant == 1) {
     a.verdict = verdict;
+    if (p->timing && (e = hipEventRecord(p->tev[0], s)) != hipSuccess) return hip_fail(e, "project_batch: timing event");
     for (int g = 0; g < n_geo; ++g) {
       a.base = geo_offsets_host[g];
       a.n = geo_offsets_host[g + 1] - geo_offsets_host[g];
       if (a.n == 0) continue;
       if ((e = ops->project_plain(a, s)) != hipSuccess) return hip_fail(e, "project_batch: plain launch");
     }
+    if (p->timing) {
+      if ((e = hipEventRecord(p->tev[1], s)) != hipSuccess) return hip_fail(e, "project_batch: timing event");
+      p->timed[0] = true;
+    }
   } else {
-    int wpb = opts->waves_per_block > 0 ? opts->waves_per_block : 1;
     const bool cyc = opts->mode == 1;
+    int wpb = opts->waves_per_block > 0 ? opts->waves_per_block : 1;
+    int bpc = opts->blocks_per_cu;
+    const mc_launch_shape& ts = p->tuned[ops->f64][cyc ? 1 : 0];
+    const bool use_tuned = opts->variant == 0 && opts->waves_per_block == 0 && opts->blocks_per_cu == 0 &&
+                           ts.waves_per_block > 0;
+    if (use_tuned) {
+      wpb = ts.waves_per_block;
+      bpc = ts.blocks_per_cu;
+    }
     while (wpb > 1 && (cyc ? 2 : 1) * ops->lds_bytes(64 * wpb) > p->max_lds_per_block) wpb >>= 1;
     const int block = 64 * wpb;
-    int bpc = opts->blocks_per_cu;
+    const int bpc_req = bpc;  // 0: occupancy limit (and the two-wave build for large batches)
     if (bpc <= 0) {
       int& c = p->occ[ops->f64][wpb == 1 ? 0 : wpb == 2 ? 1 : 2];
       if (c <= 0) c = ops->persistent_blocks_per_cu(block);  // registers bound it, not LDS
@@ -1050,7 +1079,7 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
     int64_t grid = int64_t(p->n_cu) * bpc;
     // a batch beyond the lanes of the one-wave launch, with the launch shape left to the library:
     // the two-wave launch where the family has one
-    const bool wide = !cyc && ops->project_persistent_wide != nullptr && opts->blocks_per_cu == 0 &&
+    const bool wide = !cyc && ops->project_persistent_wide != nullptr && bpc_req == 0 &&
                       n > grid * block && lds_ok(p, ops->lds_bytes(256));
     if (wide) {
       if (p->occ_wide <= 0) p->occ_wide = ops->persistent_wide_blocks_per_cu();
@@ -1064,21 +1093,27 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
     const bool tail = ops->project_tail != nullptr;
     const bool ctail = verdict && opts->check_collision && ops->check_tail != nullptr;
     if (tail || ctail) {
+      a.defer_count = counter + 1;
+      a.chk_count = counter + 3;
       if ((e = grow_defer(p, n, ops->dof_max)) != hipSuccess) return hip_fail(e, "project_batch: queue allocation");
-      a.defer_count = p->counter + 1;
       a.defer_ik = p->defer_ik;
       a.defer_q = p->defer_q;
       a.defer_cap = p->defer_cap;
-      a.chk_count = p->counter + 3;
       a.chk_idx = p->chk_idx;
       a.chk_q = p->chk_q;
     }
     a.verdict = verdict;
-    hipLaunchKernelGGL(k_reset_u32, dim3(1), dim3(64), 0, s, p->counter, 4);
+    // counters cleared by a kernel (graph-capturable), never by a memset
+    hipLaunchKernelGGL(k_reset_u32, dim3(1), dim3(64), 0, s, counter, 4);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "project_batch: reset");
+    if (p->timing && (e = hipEventRecord(p->tev[0], s)) != hipSuccess) return hip_fail(e, "project_batch: timing event");
     if (wide) e = ops->project_persistent_wide(a, int(grid), s);
     else e = (cyc ? ops->project_persistent_cyclic : ops->project_persistent)(a, int(grid), block, s);
     if (e != hipSuccess) return hip_fail(e, "project_batch: persistent launch");
+    if (p->timing) {
+      if ((e = hipEventRecord(p->tev[1], s)) != hipSuccess) return hip_fail(e, "project_batch: timing event");
+      p->timed[0] = true;
+    }
     if (tail && (e = (cyc ? ops->project_tail_cyclic : ops->project_tail)(a, p->n_cu, s)) != hipSuccess)
       return hip_fail(e, "project_batch: FP64 tail launch");
     // 4 workgroups of 4 waves per CU: 4,096 work items per round (blocks without work leave at once)
@@ -1089,6 +1124,16 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "project_batch: geo_ok");
   }
   return MC_OK;
+}
+
+extern "C" {
+
+mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_t ld_in, void* q_out, int64_t ld_out,
+                        int8_t* status, int8_t* iters, void* resid, uint8_t* verdict, const int32_t* geo_offsets,
+                        const int32_t* geo_offsets_host, int32_t n_geo, uint8_t* geo_ok, const mc_project_opts* opts,
+                        void* stream) {
+  return project_impl(p, n, q_in, ld_in, q_out, ld_out, status, iters, resid, verdict, geo_offsets, geo_offsets_host,
+                      n_geo, geo_ok, opts, stream);
 }
 
 mc_status check_batch(const mc_problem* p, int64_t n, const void* q, int64_t ld, mc_dtype dtype, uint8_t* verdict,
@@ -1146,33 +1191,36 @@ mc_status project_vjp(const mc_problem* p, int64_t n, const void* q_proj, int64_
     hipLaunchKernelGGL(k_reset_u32, dim3(1), dim3(64), 0, s, p->counter + 2, 1);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "project_vjp: reset");
   }
+  if (p->timing && (e = hipEventRecord(p->tev[2], s)) != hipSuccess) return hip_fail(e, "project_vjp: timing event");
   if ((e = ops->vjp(a, s)) != hipSuccess) return hip_fail(e, "project_vjp: launch");
+  if (p->timing) {
+    if ((e = hipEventRecord(p->tev[3], s)) != hipSuccess) return hip_fail(e, "project_vjp: timing event");
+    p->timed[1] = true;
+  }
   if (tail && (e = ops->vjp_tail(a, p->n_cu, s)) != hipSuccess) return hip_fail(e, "project_vjp: FP64 tail launch");
   return MC_OK;
 }
 
 mc_status interpolate_geodesics(const mc_problem* p, int32_t n_geo, const int32_t* geo_offsets, const void* endpoints,
-                                int64_t ld_e, void* q_out, int64_t ld_out, mc_dtype dtype, void* stream) {
+                                int64_t ld_e, int64_t total, void* q_out, int64_t ld_out, mc_dtype dtype, void* stream) {
   g_err.clear();
   if (!p) return fail(MC_ERR_INVALID_ARG, "interpolate_geodesics: null problem");
-  if (n_geo < 0) return fail(MC_ERR_INVALID_ARG, "interpolate_geodesics: n_geo < 0");
-  if (n_geo == 0) return MC_OK;
+  if (n_geo < 0 || total < 0) return fail(MC_ERR_INVALID_ARG, "interpolate_geodesics: negative size");
+  if (n_geo == 0 || total == 0) return MC_OK;
   if (!geo_offsets || !endpoints || !q_out) return fail(MC_ERR_INVALID_ARG, "interpolate_geodesics: null array");
   if (ld_e < 2 * int64_t(n_geo)) return fail(MC_ERR_INVALID_ARG, "interpolate_geodesics: ld_e < 2 n_geo");
   if (dtype != MC_F32 && dtype != MC_F64) return fail(MC_ERR_INVALID_ARG, "interpolate_geodesics: bad dtype");
-  int32_t total = 0;
-  hipError_t e = hipMemcpy(&total, geo_offsets + n_geo, sizeof(int32_t), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(e, "interpolate_geodesics: read total");
-  if (total < 0 || ld_out < total) return fail(MC_ERR_INVALID_ARG, "interpolate_geodesics: ld_out < total");
-  if (total == 0) return MC_OK;
+  if (total > (int64_t(1) << 31) - 1) return fail(MC_ERR_INVALID_ARG, "interpolate_geodesics: total too large");
+  if (ld_out < total) return fail(MC_ERR_INVALID_ARG, "interpolate_geodesics: ld_out < total");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const dim3 g((total + 255) / 256), b(256);
+  const dim3 g(unsigned((total + 255) / 256)), b(256);
   if (dtype == MC_F64)
     hipLaunchKernelGGL(k_interpolate<double>, g, b, 0, s, n_geo, geo_offsets, static_cast<const double*>(endpoints), ld_e,
-                       static_cast<double*>(q_out), ld_out, p->d);
+                       total, static_cast<double*>(q_out), ld_out, p->d);
   else
     hipLaunchKernelGGL(k_interpolate<float>, g, b, 0, s, n_geo, geo_offsets, static_cast<const float*>(endpoints), ld_e,
-                       static_cast<float*>(q_out), ld_out, p->d);
+                       total, static_cast<float*>(q_out), ld_out, p->d);
+  hipError_t e;
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "interpolate_geodesics: launch");
   return MC_OK;
 }
@@ -1360,6 +1408,182 @@ mc_status extend_batch(const mc_problem* p, int64_t E, const void* q_start, cons
   return extend_impl<float>(p, E, static_cast<const float*>(q_start), static_cast<const float*>(q_target), ld,
                             static_cast<const float*>(eps), xo, opts, static_cast<float*>(q_out), ld_out, result,
                             particle, n_points, lmax, s);
+}
+
+mc_status mc_eval_condition(const mc_problem* p, int64_t n, const void* q, int64_t ld, mc_dtype dtype, double lambda,
+                            void* kappa, void* stream) {
+  g_err.clear();
+  if (!p) return fail(MC_ERR_INVALID_ARG, "mc_eval_condition: null problem");
+  if (n < 0) return fail(MC_ERR_INVALID_ARG, "mc_eval_condition: n < 0");
+  if (dtype != MC_F32 && dtype != MC_F64) return fail(MC_ERR_INVALID_ARG, "mc_eval_condition: bad dtype");
+  if (!(lambda >= 0) || !std::isfinite(lambda)) return fail(MC_ERR_INVALID_ARG, "mc_eval_condition: lambda must be >= 0");
+  if (n == 0) return MC_OK;
+  if (!q || !kappa) return fail(MC_ERR_INVALID_ARG, "mc_eval_condition: null array");
+  if (ld < n) return fail(MC_ERR_INVALID_ARG, "mc_eval_condition: ld < n");
+  const FamilyOps* ops = ops_for(p->family, dtype == MC_F64);
+  hipError_t e = ops->eval_cond(p->dev, n, q, ld, lambda, kappa, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "mc_eval_condition: launch");
+  return MC_OK;
+}
+
+mc_status mc_set_kernel_timing(mc_problem* p, int32_t on) {
+  g_err.clear();
+  if (!p) return fail(MC_ERR_INVALID_ARG, "mc_set_kernel_timing: null problem");
+  if (on) {
+    for (hipEvent_t& ev : p->tev) {
+      if (ev) continue;
+      hipError_t e = hipEventCreate(&ev);
+      if (e != hipSuccess) return hip_fail(e, "mc_set_kernel_timing: event");
+    }
+  }
+  p->timing = on != 0;
+  p->timed[0] = p->timed[1] = false;
+  return MC_OK;
+}
+
+mc_status mc_last_kernel_ms(const mc_problem* p, int32_t which, float* ms) {
+  g_err.clear();
+  if (!p || !ms) return fail(MC_ERR_INVALID_ARG, "mc_last_kernel_ms: null argument");
+  if (which != 0 && which != 1) return fail(MC_ERR_INVALID_ARG, "mc_last_kernel_ms: which must be 0 or 1");
+  if (!p->timed[which]) return fail(MC_ERR_INVALID_ARG, "mc_last_kernel_ms: no timed call of this kind");
+  hipError_t e = hipEventSynchronize(p->tev[2 * which + 1]);
+  if (e != hipSuccess) return hip_fail(e, "mc_last_kernel_ms: sync");
+  if ((e = hipEventElapsedTime(ms, p->tev[2 * which], p->tev[2 * which + 1])) != hipSuccess)
+    return hip_fail(e, "mc_last_kernel_ms: elapsed");
+  return MC_OK;
+}
+
+mc_status mc_queue_counts(const mc_problem* p, uint32_t counts[4]) {
+  g_err.clear();
+  if (!p || !counts) return fail(MC_ERR_INVALID_ARG, "mc_queue_counts: null argument");
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "mc_queue_counts: sync");
+  if ((e = hipMemcpy(counts, p->counter, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(e, "mc_queue_counts: read");
+  return MC_OK;
+}
+
+}  // extern "C"
+
+// Candidate launch shapes of the autotuner (waves per workgroup, workgroups per CU, lanes per
+// configuration).
+static const mc_launch_shape kTuneCandidates[] = {{1, 0, 1}, {2, 0, 1}, {4, 0, 1}, {1, 1, 1},
+                                                  {1, 2, 1}, {2, 1, 1}, {4, 1, 1}};
+constexpr int kNumTuneCandidates = int(sizeof(kTuneCandidates) / sizeof(kTuneCandidates[0]));
+
+// Device outputs of one projection of the autotuner (one allocation).
+struct TuneOut {
+  unsigned char* base = nullptr;
+  void *q = nullptr, *resid = nullptr;
+  int8_t *status = nullptr, *iters = nullptr;
+  uint8_t* verdict = nullptr;
+  size_t bytes = 0;
+  hipError_t alloc(int64_t n, int d, size_t elem) {
+    const size_t nq = size_t(n) * d * elem, nr = size_t(n) * elem;
+    bytes = nq + nr + 3 * size_t(n);
+    hipError_t e = hipMalloc((void**)&base, bytes);
+    if (e != hipSuccess) return e;
+    q = base;
+    resid = base + nq;
+    status = reinterpret_cast<int8_t*>(base + nq + nr);
+    iters = status + n;
+    verdict = reinterpret_cast<uint8_t*>(iters + n);
+    return hipSuccess;
+  }
+  ~TuneOut() {
+    if (base) (void)hipFree(base);
+  }
+};
+
+extern "C" {
+
+int32_t mc_autotune_candidates(mc_launch_shape* shapes) {
+  if (shapes)
+    for (int c = 0; c < kNumTuneCandidates; ++c) shapes[c] = kTuneCandidates[c];
+  return kNumTuneCandidates;
+}
+
+mc_status mc_autotune_project(mc_problem* p, int64_t n, const void* q_in, int64_t ld_in, const mc_project_opts* opts,
+                              int32_t reps, void* stream, mc_launch_shape* best, float* ms) {
+  g_err.clear();
+  if (!p) return fail(MC_ERR_INVALID_ARG, "mc_autotune_project: null problem");
+  mc_status st = check_opts(p, opts);
+  if (st != MC_OK) return st;
+  if (n <= 0 || !q_in) return fail(MC_ERR_INVALID_ARG, "mc_autotune_project: empty batch");
+  if (ld_in < n) return fail(MC_ERR_INVALID_ARG, "mc_autotune_project: ld < n");
+  if (reps < 1 || reps > 1000) return fail(MC_ERR_INVALID_ARG, "mc_autotune_project: reps must be in 1..1000");
+  if (opts->variant == 1) return fail(MC_ERR_INVALID_ARG, "mc_autotune_project: tunes the fused variant");
+  const size_t elem = opts->dtype == MC_F64 ? 8 : 4;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  TuneOut ref, cand;
+  hipError_t e;
+  if ((e = ref.alloc(n, p->d, elem)) != hipSuccess || (e = cand.alloc(n, p->d, elem)) != hipSuccess)
+    return hip_fail(e, "mc_autotune_project: output buffers");
+  std::vector<unsigned char> h_ref(ref.bytes), h_cand(cand.bytes);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(e, "mc_autotune_project: events");
+  }
+  int best_c = -1;
+  float best_ms = 0.f;
+  mc_status rc = MC_OK;
+  for (int c = 0; c < kNumTuneCandidates && rc == MC_OK; ++c) {
+    mc_project_opts o = *opts;
+    o.variant = 2;
+    o.waves_per_block = kTuneCandidates[c].waves_per_block;
+    o.blocks_per_cu = kTuneCandidates[c].blocks_per_cu;
+    o.lanes_per_config = kTuneCandidates[c].lanes_per_config;
+    TuneOut& out = c == 0 ? ref : cand;
+    auto call = [&]() {
+      return project_batch(p, n, q_in, ld_in, out.q, n, out.status, out.iters, out.resid,
+                           o.check_collision ? out.verdict : nullptr, nullptr, nullptr, 0, nullptr, &o, stream);
+    };
+    if ((rc = call()) != MC_OK) break;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) { rc = hip_fail(e, "mc_autotune_project: run"); break; }
+    // every candidate must reproduce the first one bit for bit (the verdict bytes only when checked)
+    const size_t cmp = o.check_collision ? out.bytes : out.bytes - size_t(n);
+    if ((e = hipMemcpy(c == 0 ? h_ref.data() : h_cand.data(), out.base, cmp, hipMemcpyDeviceToHost)) != hipSuccess) {
+      rc = hip_fail(e, "mc_autotune_project: read outputs");
+      break;
+    }
+    if (c > 0 && std::memcmp(h_ref.data(), h_cand.data(), cmp) != 0) {
+      rc = fail(MC_ERR_HIP, "mc_autotune_project: launch shape " + std::to_string(o.waves_per_block) + "x" +
+                                std::to_string(o.blocks_per_cu) + " changed the results");
+      break;
+    }
+    if ((e = hipEventRecord(e0, s)) != hipSuccess) { rc = hip_fail(e, "mc_autotune_project: event"); break; }
+    for (int r = 0; r < reps && rc == MC_OK; ++r) rc = call();
+    if (rc != MC_OK) break;
+    float t = 0.f;
+    if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+        (e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) {
+      rc = hip_fail(e, "mc_autotune_project: timing");
+      break;
+    }
+    t /= float(reps);
+    if (ms) ms[c] = t;
+    if (best_c < 0 || t < best_ms) {
+      best_c = c;
+      best_ms = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != MC_OK) return rc;
+  p->tuned[opts->dtype == MC_F64 ? 1 : 0][opts->mode == 1 ? 1 : 0] = kTuneCandidates[best_c];
+  if (best) *best = kTuneCandidates[best_c];
+  return MC_OK;
+}
+
+mc_status mc_tuned_shape(const mc_problem* p, mc_dtype dtype, int32_t mode, mc_launch_shape* out) {
+  g_err.clear();
+  if (!p || !out) return fail(MC_ERR_INVALID_ARG, "mc_tuned_shape: null argument");
+  if ((dtype != MC_F32 && dtype != MC_F64) || (mode != 0 && mode != 1)) return fail(MC_ERR_INVALID_ARG, "mc_tuned_shape: bad key");
+  const mc_launch_shape& t = p->tuned[dtype == MC_F64 ? 1 : 0][mode];
+  if (t.waves_per_block <= 0) return fail(MC_ERR_INVALID_ARG, "mc_tuned_shape: no shape stored for this key");
+  *out = t;
+  return MC_OK;
 }
 
 mc_status mc_fallback_count(const mc_problem* p, int reset, uint64_t* count) {

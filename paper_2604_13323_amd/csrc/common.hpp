@@ -2,11 +2,11 @@
 //
 // Data layout. A problem lives in global memory as one DevProblem. Its kinematic and
 // constraint constants (Consts: FP64 copy for the residual pass, FP32 copy for the step
-// passes) and its collision constants (CollConsts; obstacles follow in a separate array)
-// are copied into LDS by every workgroup when a kernel starts. All later reads are LDS
-// broadcasts (every lane reads the same address), which are short-latency and prefetched
-// one joint ahead along the kinematic walk; nothing on the hot path waits on the scalar
-// cache or on global memory. A lane's FP64 iterate is a column of a [D][blockDim] LDS array.
+// passes) and its collision constants (CollConsts; obstacles follow in a separate array) are
+// wave-uniform: the projection kernels read them with scalar loads (through the constant
+// address space, into scalar registers), each joint's data requested one joint ahead of its
+// use along the kinematic walk; the exact-check kernels stage the robot spheres and obstacles
+// in LDS per workgroup. A lane's FP64 iterate is a column of a per-wave [D][64] LDS tile.
 #pragma once
 
 #include <hip/hip_runtime.h>

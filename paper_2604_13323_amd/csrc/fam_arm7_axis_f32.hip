@@ -1,8 +1,13 @@
 // Kernel instantiations: 7-DoF arm, end-effector z parallel to world z, FP32 mode (FP64 residual and iterate, FP32 step with FP64 fallback).
 #include "kin.hpp"
-#include "ops.hpp"
 #include "simple_models.hpp"
+#include "ops_impl.hpp"
 
 namespace mc {
-const FamilyOps ops_arm7_axis_f32 = OpsImpl<Kin<TopoArm7Axis>, float, float>::make();
+using Ops_arm7_axis_f32 = OpsImpl<Kin<TopoArm7Axis>, float, float>;
+}  // namespace mc
+MC_INST_LIGHT_F32(mc::Ops_arm7_axis_f32)
+
+namespace mc {
+const FamilyOps ops_arm7_axis_f32 = Ops_arm7_axis_f32::make();
 }  // namespace mc

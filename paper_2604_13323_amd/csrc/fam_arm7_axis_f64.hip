@@ -1,8 +1,13 @@
 // Kernel instantiations: 7-DoF arm, end-effector z parallel to world z, FP64 mode.
 #include "kin.hpp"
-#include "ops.hpp"
 #include "simple_models.hpp"
+#include "ops_impl.hpp"
 
 namespace mc {
-const FamilyOps ops_arm7_axis_f64 = OpsImpl<Kin<TopoArm7Axis>, double, double>::make();
+using Ops_arm7_axis_f64 = OpsImpl<Kin<TopoArm7Axis>, double, double>;
+}  // namespace mc
+MC_INST_LIGHT_F64(mc::Ops_arm7_axis_f64)
+
+namespace mc {
+const FamilyOps ops_arm7_axis_f64 = Ops_arm7_axis_f64::make();
 }  // namespace mc

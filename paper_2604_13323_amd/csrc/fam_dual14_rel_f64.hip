@@ -1,8 +1,13 @@
-// Kernel instantiations: dual 7-DoF arms, relative end-effector pose (Eq. 2), FP64 mode.
+// Kernel instantiations: two 7-DoF arms, relative end-effector pose (Eq. 2), FP64 mode.
 #include "kin.hpp"
-#include "ops.hpp"
 #include "simple_models.hpp"
+#include "ops_impl.hpp"
 
 namespace mc {
-const FamilyOps ops_dual14_rel_f64 = OpsImpl<Kin<TopoDual14Rel>, double, double>::make();
+using Ops_dual14_rel_f64 = OpsImpl<Kin<TopoDual14Rel>, double, double>;
+}  // namespace mc
+MC_INST_LIGHT_F64(mc::Ops_dual14_rel_f64)
+
+namespace mc {
+const FamilyOps ops_dual14_rel_f64 = Ops_dual14_rel_f64::make();
 }  // namespace mc

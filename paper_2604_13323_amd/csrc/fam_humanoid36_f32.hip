@@ -1,7 +1,8 @@
-// Kernel instantiations: 36-DoF humanoid tree: feet poses, hands relative pose, CoM xy, FP32 mode (FP64 residual and iterate, FP32 step with FP64 fallback).
+// Launch table of the 36-DoF humanoid tree (feet poses, hands relative pose, CoM xy), FP32 mode (FP64 residual and iterate, FP32 step with FP64 fallback).
+// The launchers it names are instantiated, with their kernels, in the fam_humanoid36_f32_*.hip units
+// (this unit sees only their declarations, so it compiles no kernel).
 #include "kin.hpp"
 #include "ops.hpp"
-#include "simple_models.hpp"
 
 namespace mc {
 const FamilyOps ops_humanoid36_f32 = OpsImpl<Kin<TopoHumanoid36>, float, float>::make();

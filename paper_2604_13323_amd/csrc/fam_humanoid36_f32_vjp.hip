@@ -1,0 +1,11 @@
+// Kernel instantiations: 36-DoF humanoid tree (feet poses, hands relative pose, CoM xy), FP32 mode (FP64 residual and iterate, FP32 step with FP64 fallback):
+// the VJP kernels and the diagnostics.
+#include "kin.hpp"
+#include "ops_impl.hpp"
+
+namespace mc {
+using Ops_humanoid36_f32 = OpsImpl<Kin<TopoHumanoid36>, float, float>;
+}  // namespace mc
+MC_INST_VJP(mc::Ops_humanoid36_f32)
+MC_INST_VJP_TAIL(mc::Ops_humanoid36_f32)
+MC_INST_DIAG(mc::Ops_humanoid36_f32)

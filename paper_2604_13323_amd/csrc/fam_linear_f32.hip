@@ -1,8 +1,13 @@
-// Kernel instantiations: linear constraints F = A q - b, FP32 mode (FP64 residual and iterate, FP32 step with FP64 fallback).
+// Kernel instantiations: linear constraint F = A q - b, FP32 mode (FP64 residual and iterate, FP32 step with FP64 fallback).
 #include "kin.hpp"
-#include "ops.hpp"
 #include "simple_models.hpp"
+#include "ops_impl.hpp"
 
 namespace mc {
-const FamilyOps ops_linear_f32 = OpsImpl<LinearModel, float, float>::make();
+using Ops_linear_f32 = OpsImpl<LinearModel, float, float>;
+}  // namespace mc
+MC_INST_LIGHT_F32(mc::Ops_linear_f32)
+
+namespace mc {
+const FamilyOps ops_linear_f32 = Ops_linear_f32::make();
 }  // namespace mc

@@ -1,8 +1,13 @@
 // Kernel instantiations: unit sphere F = q.q - 1, FP32 mode (FP64 residual and iterate, FP32 step with FP64 fallback).
 #include "kin.hpp"
-#include "ops.hpp"
 #include "simple_models.hpp"
+#include "ops_impl.hpp"
 
 namespace mc {
-const FamilyOps ops_sphere3_f32 = OpsImpl<SphereModel, float, float>::make();
+using Ops_sphere3_f32 = OpsImpl<SphereModel, float, float>;
+}  // namespace mc
+MC_INST_LIGHT_F32(mc::Ops_sphere3_f32)
+
+namespace mc {
+const FamilyOps ops_sphere3_f32 = Ops_sphere3_f32::make();
 }  // namespace mc

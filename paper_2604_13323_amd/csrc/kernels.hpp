@@ -600,44 +600,76 @@ struct VjpArgs {
   int32_t* defer_idx;
 };
 
-// FP64 Gram, factorisation and projection for one lane: out = g - J^T (J J^T)^-1 J g.
-template <class Model>
-__device__ __forceinline__ void vjp64(const QLds& q, const Consts& C, const double* gd, double* out) {
-  constexpr int D = Model::D, M = Model::M;
-  typename Model::template SD<double> sd;
-  double F[M], G[M * (M + 1) / 2], v[M], invd[M], kappa, jy[D];
-  Model::template residual<double>(q, C, F, sd);
-  Model::template gram<double, true>(q, C, sd, G, gd, v);
-  double maxd = 0.0;
-  for (int r = 0; r < M; ++r) maxd = fmax(maxd, G[pidx(r, r)]);
-  if (cholesky<Model, double>(G, invd, kappa, kFloorF64 * maxd)) {
-    chol_solve<Model, double>(G, invd, v);
-    Model::template jty<double>(q, C, sd, v, jy);
-    for (int j = 0; j < D; ++j) out[j] = gd[j] - jy[j];
-  } else {
-    for (int j = 0; j < D; ++j) out[j] = __builtin_nan("");
-  }
+// The VJP kernels keep the upstream gradient g of a lane in LDS, in the precision of the solve (a
+// [D][64] tile per wave after the waves' FP64 iterate tiles), instead of in registers across the Gram
+// and the factorisation, and stream g_in = g - J^T y out of the J^T y walk joint by joint.
+template <class S>
+struct GLds {
+  using LP = __attribute__((address_space(3))) S*;
+  LP base;
+  __device__ __forceinline__ S operator[](int j) const { return base[j * 64]; }
+  __device__ __forceinline__ void set(int j, S v) const { base[j * 64] = v; }
+};
+// The calling lane's column of g: smem holds blockDim.x / 64 FP64 iterate tiles, then as many g tiles.
+template <int D, class S>
+__device__ __forceinline__ GLds<S> g_lds(double* smem) {
+  const int w = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
+  S* base = reinterpret_cast<S*>(smem + (blockDim.x >> 6) * (D * 64)) + w * (D * 64) + l;
+  return GLds<S>{(typename GLds<S>::LP)base};
 }
+// Sink of the J^T y walk: out[j] = acc stores g_in[j] = g[j] - acc (coordinates below dof).
+template <class IO, class S>
+struct VjpOut {
+  IO* dst;  // g_in + i
+  int64_t ld;
+  GLds<S> g;
+  int dof;
+  struct Ref {
+    const VjpOut* o;
+    int j;
+    __device__ __forceinline__ void operator=(S acc) const {
+      if (j < o->dof) o->dst[int64_t(j) * o->ld] = IO(double(o->g[j]) - double(acc));
+    }
+  };
+  __device__ __forceinline__ Ref operator[](int j) const { return Ref{this, j}; }
+};
 
-template <class Model, class IO>
-__device__ __forceinline__ void vjp_load(const VjpArgs& a, int dof, int64_t i, const QLds& q, double* gd) {
+template <class Model, class IO, class S>
+__device__ __forceinline__ void vjp_load(const VjpArgs& a, int dof, int64_t i, const QLds& q, const GLds<S>& g) {
   const IO* pq = static_cast<const IO*>(a.q) + i;
   const IO* pg = static_cast<const IO*>(a.g) + i;
   for (int c = 0; c < Model::D; ++c) {
     q.set(c, c < dof ? double(*pq) : 0.0);
-    gd[c] = c < dof ? double(*pg) : 0.0;
+    g.set(c, c < dof ? S(*pg) : S(0));
     const int64_t ld = after(a.ld, c);
     pq += ld;
     pg += ld;
   }
 }
 
-template <class Model, class IO>
-__device__ __forceinline__ void vjp_store(const VjpArgs& a, int dof, int64_t i, const double* out) {
+template <class IO>
+__device__ __forceinline__ void vjp_fill(const VjpArgs& a, int dof, int64_t i, double v) {
   IO* p = static_cast<IO*>(a.g_in) + i;
-  for (int c = 0; c < Model::D; ++c) {
-    if (c < dof) *p = IO(out[c]);
-    p += after(a.ld, c);
+  for (int c = 0; c < dof; ++c) p[int64_t(c) * a.ld] = IO(v);
+}
+
+// FP64 Gram, factorisation and projection for one lane: g_in = g - J^T (J J^T)^-1 J g (NaN where
+// the FP64 factorisation fails).
+template <class Model, class IO>
+__device__ __forceinline__ void vjp64(const VjpArgs& a, int dof, int64_t i, const QLds& q, const GLds<double>& g,
+                                      const Consts& C) {
+  constexpr int M = Model::M;
+  typename Model::template SD<double> sd;
+  double F[M], G[M * (M + 1) / 2], v[M], invd[M], kappa;
+  Model::template residual<double>(q, C, F, sd);
+  Model::template gram<double, true>(q, C, sd, G, g, v);
+  double maxd = 0.0;
+  for (int r = 0; r < M; ++r) maxd = fmax(maxd, G[pidx(r, r)]);
+  if (cholesky<Model, double>(G, invd, kappa, kFloorF64 * maxd)) {
+    chol_solve<Model, double>(G, invd, v);
+    Model::template jty<double>(q, C, sd, v, VjpOut<IO, double>{static_cast<IO*>(a.g_in) + i, a.ld, g, dof});
+  } else {
+    vjp_fill<IO>(a, dof, i, __builtin_nan(""));
   }
 }
 
@@ -645,60 +677,54 @@ __device__ __forceinline__ void vjp_store(const VjpArgs& a, int dof, int64_t i, 
 // pass stores nothing beyond q and status). g_in = 0 for configurations that did not converge.
 // In FP32 mode a lane whose factorisation fails or whose condition estimate exceeds the
 // threshold is queued for k_vjp_tail, which redoes it in FP64.
+// Dynamic LDS: D * blockDim doubles (iterates) + D * blockDim S (gradients).
 template <class Model, class IO, class S>
-__global__ void __launch_bounds__(256) k_vjp(VjpArgs a) {
+__global__ void __launch_bounds__(64) k_vjp(VjpArgs a) {
   constexpr int D = Model::D, M = Model::M;
   extern __shared__ double smem[];
   const Consts& C = consts_of(a.P);
-  const QLds q = q_lds<Model::D>(smem);
+  const QLds q = q_lds<D>(smem);
+  const GLds<S> g = g_lds<D, S>(smem);
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const int dof = dof_of<Model>(C);
-  double out[D];
   if (a.status[i] != ST_CONVERGED) {
-    for (int c = 0; c < D; ++c) out[c] = 0.0;
-    vjp_store<Model, IO>(a, dof, i, out);
+    vjp_fill<IO>(a, dof, i, 0.0);
     return;
   }
-  double gd[D];
-  vjp_load<Model, IO>(a, dof, i, q, gd);
+  vjp_load<Model, IO, S>(a, dof, i, q, g);
   if constexpr (std::is_same<S, float>::value) {
     typename Model::template SD<float> sd;
-    float F[M], gs[D], G[M * (M + 1) / 2], v[M], invd[M], kappa;
+    float F[M], G[M * (M + 1) / 2], v[M], invd[M], kappa;
     Model::template residual<float>(q, C, F, sd);
-    for (int j = 0; j < D; ++j) gs[j] = float(gd[j]);
-    Model::template gram<float, true>(q, C, sd, G, gs, v);
+    Model::template gram<float, true>(q, C, sd, G, g, v);
     if (cholesky<Model, float>(G, invd, kappa, kFloorF32) && double(kappa) <= a.cond_thr) {
       chol_solve<Model, float>(G, invd, v);
-      float jy[D];
-      Model::template jty<float>(q, C, sd, v, jy);
-      for (int j = 0; j < D; ++j) out[j] = gd[j] - double(jy[j]);
-      vjp_store<Model, IO>(a, dof, i, out);
+      Model::template jty<float>(q, C, sd, v, VjpOut<IO, float>{static_cast<IO*>(a.g_in) + i, a.ld, g, dof});
     } else {
       atomicAdd(a.P->fallback_counter, 1ull);
       a.defer_idx[atomicAdd(a.defer_count, 1u)] = int32_t(i);
     }
   } else {
-    vjp64<Model>(q, C, gd, out);
-    vjp_store<Model, IO>(a, dof, i, out);
+    vjp64<Model, IO>(a, dof, i, q, g, C);
   }
 }
 
 // FP64 redo of the VJPs queued by k_vjp (grid-stride over the queue).
+// Dynamic LDS: 2 * D * blockDim doubles (iterates, gradients).
 template <class Model, class IO>
 __global__ void __launch_bounds__(64) k_vjp_tail(VjpArgs a) {
   constexpr int D = Model::D;
   extern __shared__ double smem[];
   const Consts& C = consts_of(a.P);
   const int dof = dof_of<Model>(C);
-  const QLds q = q_lds<Model::D>(smem);
+  const QLds q = q_lds<D>(smem);
+  const GLds<double> g = g_lds<D, double>(smem);
   const int64_t cnt = *a.defer_count;
   for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < cnt; s += int64_t(gridDim.x) * blockDim.x) {
     const int64_t i = a.defer_idx[s];
-    double gd[D], out[D];
-    vjp_load<Model, IO>(a, dof, i, q, gd);
-    vjp64<Model>(q, C, gd, out);
-    vjp_store<Model, IO>(a, dof, i, out);
+    vjp_load<Model, IO, double>(a, dof, i, q, g);
+    vjp64<Model, IO>(a, dof, i, q, g, C);
   }
 }
 
@@ -725,6 +751,35 @@ __global__ void __launch_bounds__(256) k_eval_fj(const DevProblem* Pp, int64_t n
     for (int c = 0; c < D; ++c)
       if (c < dof) st_io<IO>(Jo, (int64_t(r) * dof + c) * ld + i, double(J[r * D + c]));
   }
+}
+
+// Diagnostic: the condition estimate (max L_ii / min L_ii)^2 of J J^T + lambda I as the step
+// computes it in precision S (+inf where the factorisation fails). The iterate is staged in LDS
+// as in the projection kernels. Dynamic LDS: D * blockDim doubles.
+template <class Model, class IO, class S>
+__global__ void __launch_bounds__(64) k_eval_cond(const DevProblem* Pp, int64_t n, const void* qv, int64_t ld,
+                                                  double lambda, void* kappa_out) {
+  constexpr int D = Model::D, M = Model::M;
+  extern __shared__ double smem[];
+  const Consts& C = consts_of(Pp);
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int dof = dof_of<Model>(C);
+  const QLds q = q_lds<D>(smem);
+  const IO* p = static_cast<const IO*>(qv) + i;
+  for (int c = 0; c < D; ++c) q.set(c, c < dof ? double(p[int64_t(c) * ld]) : 0.0);
+  typename Model::template SD<S> sd;
+  S F[M], G[M * (M + 1) / 2], invd[M], kappa;
+  Model::template residual<S>(q, C, F, sd);
+  Model::template gram<S, false>(q, C, sd, G, nullptr, nullptr);
+  S maxd = S(0);
+  for (int r = 0; r < M; ++r) {
+    G[pidx(r, r)] += S(lambda);
+    maxd = G[pidx(r, r)] > maxd ? G[pidx(r, r)] : maxd;
+  }
+  const S floor = std::is_same<S, float>::value ? S(kFloorF32) : S(kFloorF64);
+  const bool ok = cholesky<Model, S>(G, invd, kappa, floor * maxd);
+  st_io<IO>(kappa_out, i, ok ? double(kappa) : __builtin_huge_val());
 }
 
 }  // namespace mc

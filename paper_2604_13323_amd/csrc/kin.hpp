@@ -267,7 +267,7 @@ struct Kin {
     return T(x);
   }
 
-  // What the walk needs at joint j, read from LDS one joint ahead of its use.
+  // What the walk needs at joint j, read with scalar loads one joint ahead of its use.
   template <class T>
   struct JP {
     T q;       // joint coordinate
@@ -558,9 +558,10 @@ struct Kin {
     });
   }
 
-  // J^T y pass.
-  template <class S, uint32_t RM = ALL, class Q>
-  static __device__ __forceinline__ void jty(const Q& q, const Consts& P, const SD<S>& sd, const S* y, S* out) {
+  // J^T y pass: out[j] = (J^T y)_j, assigned in joint order (out: an array, or a sink whose
+  // operator[] returns an assignable proxy, so results can be streamed out of the walk).
+  template <class S, uint32_t RM = ALL, class Q, class OUT>
+  static __device__ __forceinline__ void jty(const Q& q, const Consts& P, const SD<S>& sd, const S* y, OUT&& out) {
     const TP<S>& T = tp<S>(P);
     S Qr[3] = {S(0), S(0), S(0)};
     fk<S>(q, T, [&](auto J, const Rig<S>& X, const JP<S>& jp) {

@@ -64,8 +64,8 @@ struct SphereModel {
     G[0] = S(4) * (a * a + b * b + c * c);
     if constexpr (WITH_V) v[0] = S(2) * (a * g[0] + b * g[1] + c * g[2]);
   }
-  template <class S, uint32_t RM = ~uint32_t(0), class Q>
-  static __device__ __forceinline__ void jty(const Q& q, const Consts&, const SD<S>&, const S* y, S* out) {
+  template <class S, uint32_t RM = ~uint32_t(0), class Q, class OUT>
+  static __device__ __forceinline__ void jty(const Q& q, const Consts&, const SD<S>&, const S* y, OUT&& out) {
     for (int k = 0; k < 3; ++k) out[k] = S(2) * S(q.at(k)) * y[0];
   }
   template <class S, class Q>
@@ -140,8 +140,8 @@ struct LinearModel {
       }
     }
   }
-  template <class S, uint32_t RM = ~uint32_t(0), class Q>
-  static __device__ __forceinline__ void jty(const Q&, const Consts& P, const SD<S>&, const S* y, S* out) {
+  template <class S, uint32_t RM = ~uint32_t(0), class Q, class OUT>
+  static __device__ __forceinline__ void jty(const Q&, const Consts& P, const SD<S>&, const S* y, OUT&& out) {
     const TP<S>& T = tp<S>(P);
     for (int c = 0; c < D; ++c) {
       S acc = S(0);
