@@ -27,8 +27,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_VALU_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz (non-packed FP32 and FP64)
-PEAK_FP32_PACKED_TFLOPS = 157.3
+PEAK_FP32_TFLOPS = 157.3         # MI355X published FP32 vector peak (counts packed FP32 FMAs)
+PEAK_NONPACKED_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz (non-packed FP32 and FP64)
 PEAK_HBM_GBS = 8000.0
 
 
@@ -36,7 +36,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-PROJECTION_SOURCES = ("common.hpp", "kin.hpp", "kernels.hpp", "simple_models.hpp", "fam_humanoid36_f32.hip")
+PROJECTION_SOURCES = ("common.hpp", "kin.hpp", "kernels.hpp", "ops.hpp", "ops_impl.hpp", "fam_humanoid36_f32_persistent.hip")
 
 
 def source_hash() -> str:
@@ -83,8 +83,20 @@ def build_batch(G, cfg, torch):
     return q, offs, re
 
 
-def cpu_baseline(cfg, max_configs: int):
-    """The FP64 oracle on the same workload recipe (its own endpoint projection and interpolation)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, max_configs: int, runs: int = 3):
+    """The FP64 oracle on the same workload recipe (its own endpoint projection and interpolation):
+    wall clock of projection + brute-force check over the sample, median of `runs` runs."""
     import oracle
     sc = cfg["scene"]
     P = oracle.Problem(sc.to_blob())
@@ -96,11 +108,14 @@ def cpu_baseline(cfg, max_configs: int):
     e = cfg["endpoints"][:g_take].reshape(-1, sc.d)
     qe = P.project(e, tol=1e-9, max_iter=100)[0]
     q = oracle.interpolate_interior(qe.reshape(-1, 2, sc.d), offs)
-    t0 = time.perf_counter()
-    qo, st, it, rs = P.project(q, tol=cfg["tol"], max_iter=cfg["max_iter"])
-    conv = st == 0
-    v, _ = P.check(qo[conv])
-    dt = time.perf_counter() - t0
+    times = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        qo, st, it, rs = P.project(q, tol=cfg["tol"], max_iter=cfg["max_iter"])
+        conv = st == 0
+        v, _ = P.check(qo[conv])
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
     # one thread on the first 2,048 configurations of the same sample
     q1 = q[:2048]
     t1 = time.perf_counter()
@@ -110,8 +125,8 @@ def cpu_baseline(cfg, max_configs: int):
     return dict(value=float(conv.sum() / dt), unit="converged projections/s", cores=oracle.max_threads(),
                 kind="oracle",
                 sample=f"{len(q)} configurations ({g_take} geodesics x {per}) of the humanoid batch, "
-                       f"projection + brute-force collision check, FP64, {dt:.2f} s",
-                seconds=dt, n=int(len(q)),
+                       f"projection + brute-force collision check, FP64, median of {runs} runs: {dt:.2f} s",
+                seconds=dt, run_seconds=times, n=int(len(q)), cpu_model=cpu_model(), nproc=os.cpu_count(),
                 single_thread=dict(value=float((st1 == 0).sum() / dt1), n=int(len(q1)), seconds=dt1))
 
 
@@ -251,7 +266,7 @@ def main():
     tuning = None
     if not args.no_autotune and args.waves_per_block == 0 and args.blocks_per_cu == 0:
         from paper_2604_13323_amd import autotune
-        tuning = autotune.tune(G, q_in, tol=tol, max_iter=mi, cache_path=None)
+        tuning = autotune.tune(G, q_in, tol=tol, max_iter=mi)
         kw.update(tuning["best"])
         shapes = ", ".join("%dx%d: %.3f" % (r["waves_per_block"], r["blocks_per_cu"], r["ms"]) for r in tuning["table"])
         log(f"autotuned launch shape: {tuning['best']} ({shapes} ms)")
@@ -267,19 +282,26 @@ def main():
     value = n_conv / (ms * 1e-3)
     log(f"fused: {ms:.3f} ms/step, {value:.4g} converged projections/s, converged {n_conv}/{n}")
 
-    # --- the dominant kernel alone (projection without the check): its launch duration
-    out_nc = M.ProjectResult(q=torch.empty_like(out.q), status=torch.empty_like(out.status),
-                             iters=torch.empty_like(out.iters), resid=torch.empty_like(out.resid),
-                             verdict=None, geo_ok=None)
-    ms_proj = timed(lambda: G.project(q_in, variant="fused", out=out_nc, check=False, **kw), args.steps,
-                    args.warmup, torch, "projection")
+    # --- the dominant kernel: the persistent projection kernel of the fused step (with its broad-phase
+    # walk), its launch duration from HIP events the library records around that launch alone on the
+    # call's stream (queue reset, FP64 and exact-check tails excluded), one timed call after another
+    G.kernel_timing(True)
+    for _ in range(args.warmup):
+        G.project(q_in, variant="fused", out=out, **kw)
+    kms = []
+    for _ in range(args.steps):
+        G.project(q_in, variant="fused", out=out, **kw)
+        kms.append(G.last_kernel_ms("projection"))
+    G.kernel_timing(False)
+    ms_kernel = float(np.mean(kms))
     ms_check = timed(lambda: G.check(out.q), args.steps, args.warmup, torch)
-    # the roofline kernel is the projection launch without the collision walk (check=False), so its
-    # work excludes the broad phase
-    flop = FL.batch_flops(sc, iters, with_broad=False)
-    achieved_tflops = flop / (ms_proj * 1e-3) / 1e12
-    log(f"projection kernel alone: {ms_proj:.3f} ms, {achieved_tflops:.2f} TFLOP/s algorithmic; "
-        f"check alone {ms_check:.3f} ms")
+    # algorithmic work of one launch: the scope table's per-iteration figure x the batch's Newton
+    # iterations + a final residual per configuration + the broad phase the kernel runs at convergence
+    flop = FL.survey_batch_flops(sc, iters, with_broad=True)
+    flop_model = FL.batch_flops(sc, iters, with_broad=True)
+    achieved_tflops = flop / (ms_kernel * 1e-3) / 1e12
+    log(f"persistent kernel: {ms_kernel:.4f} ms per launch (min {min(kms):.4f}), {achieved_tflops:.2f} TFLOP/s "
+        f"algorithmic = {achieved_tflops / PEAK_FP32_TFLOPS:.3f} of {PEAK_FP32_TFLOPS}; check_batch alone {ms_check:.3f} ms")
 
     # --- the paper's composition rule: cyclic steps over the constraint blocks (same batch)
     cyclic = None
@@ -335,9 +357,22 @@ def main():
             G.vjp(o4.q, o4.status, g)
 
         ms4 = timed(fwd_vjp, args.steps, args.warmup, torch, "fwd_vjp")
+        # the VJP kernel alone (HIP events around its launch); ~14 kFLOP per converged configuration
+        # (one Newton iteration's work plus J g, the scope table's per-unit VJP figure)
+        g4, _ = G.path_length_grad(o4.q, offs4)
+        G.kernel_timing(True)
+        vms = []
+        for _ in range(args.steps):
+            G.vjp(o4.q, o4.status, g4)
+            vms.append(G.last_kernel_ms("vjp"))
+        G.kernel_timing(False)
+        n4c = int((o4.status == 0).sum().item())
+        vjp_tflops = 14000.0 * n4c / (np.mean(vms) * 1e-3) / 1e12
         fv = dict(value=n4 / (ms4 * 1e-3), unit="configurations/s", ms_per_step=ms4, configs=n4,
-                  geodesics=len(cfg4["geo_offsets"]) - 1)
-        log(f"fwd+vjp: {ms4:.3f} ms/step, {fv['value']:.4g} configurations/s")
+                  geodesics=len(cfg4["geo_offsets"]) - 1, vjp_kernel_ms=float(np.mean(vms)),
+                  vjp_kernel_tflops=vjp_tflops, vjp_kernel_frac=vjp_tflops / PEAK_FP32_TFLOPS)
+        log(f"fwd+vjp: {ms4:.3f} ms/step, {fv['value']:.4g} configurations/s; VJP kernel {np.mean(vms):.4f} ms, "
+            f"{vjp_tflops:.2f} TFLOP/s")
 
     if args.copy_calibration:
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -373,10 +408,13 @@ def main():
                                "projected endpoints), 36 DoF, 20 rows, 248 robot spheres vs 500 obstacle spheres, "
                                "tol 1e-6, max 40 steps, fused persistent kernel + collision check",
                    "configs": n, "geodesics": len(cfg["geo_offsets"]) - 1},
-        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / PEAK_VALU_TFLOPS, "traffic": traffic,
-                     "kernel": "k_project_persistent<humanoid36, FP32 mode>", "kernel_ms": ms_proj,
-                     "flop_per_launch": flop, "frac_vs_packed_fp32_peak": achieved_tflops / PEAK_FP32_PACKED_TFLOPS},
+        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "kernel": "k_project_persistent<humanoid36, FP32 mode>", "kernel_ms": ms_kernel,
+                     "kernel_ms_min": min(kms), "flop_per_launch": flop,
+                     "flop_per_launch_structural_model": flop_model,
+                     "frac_vs_nonpacked_peak": achieved_tflops / PEAK_NONPACKED_TFLOPS,
+                     "nonpacked_peak": PEAK_NONPACKED_TFLOPS},
         "cpu_baseline": cpu,
         "plain": plain,
         "fused_vs_plain": (value / plain["value"]) if plain else None,
@@ -388,7 +426,7 @@ def main():
                   "iters_p99": float(np.percentile(iters, 99)), "iters_max": int(iters.max()),
                   "collision_free_frac_of_converged": float((verdict[status == 0] == 0).mean()) if n_conv else None,
                   "fp64_fallbacks_per_step": fallbacks / max(1, args.steps + args.warmup),
-                  "check_batch_ms": ms_check, "projection_ms": ms_proj,
+                  "check_batch_ms": ms_check, "persistent_kernel_ms": ms_kernel,
                   "launch_shape": {k: kw[k] for k in ("waves_per_block", "blocks_per_cu")},
                   "median_ms_per_step": dict(STEP_MEDIANS),
                   "cus": torch.cuda.get_device_properties(0).multi_processor_count,

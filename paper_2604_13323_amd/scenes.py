@@ -347,7 +347,11 @@ def humanoid_geometry(r):
     return g
 
 
-def humanoid36_scene(config_id: int = 3, n_slabs: int = 4, bend: float = 0.3) -> Scene:
+def humanoid36_scene(config_id: int = 3, n_slabs: int = 4, bend: float = 0.3, slab_x=(0.35, 0.6),
+                     slab_h=(0.2, 1.6)) -> Scene:
+    """The 36-DoF humanoid with `n_slabs` shelf slabs of 25 x 5 obstacle spheres (r 0.03, pitch 0.05 m):
+    front edge x0 ~ U[slab_x], height ~ U[slab_h]. The defaults keep the slabs in front of the robot;
+    slab_x = (0.42, 0.5), slab_h = (1.0, 1.2) puts them in reach of the hands (a scene with collisions)."""
     r = rng_for(config_id, 0)
     g = humanoid_geometry(r)
     I = np.eye(3)
@@ -430,8 +434,8 @@ def humanoid36_scene(config_id: int = 3, n_slabs: int = 4, bend: float = 0.3) ->
     ro = rng_for(config_id, 1)
     obs = []
     for _ in range(n_slabs):
-        h = ro.uniform(0.2, 1.6)
-        x0 = ro.uniform(0.35, 0.6)
+        h = ro.uniform(*slab_h)
+        x0 = ro.uniform(*slab_x)
         for iy in range(25):
             for ix in range(5):
                 obs.append([x0 + 0.05 * ix, -0.6 + 0.05 * iy, h, 0.03])
@@ -502,6 +506,14 @@ def make_config(name: str, small: bool = False):
     if name == "c3":
         sc = humanoid36_scene(3)
         n_geo = 32 if small else 2048
+        return dict(name=name, scene=sc, tol=1e-6, max_iter=40,
+                    endpoints=raw_endpoints(sc, 3, n_geo, humanoid_noise_sigma()),
+                    geo_offsets=np.arange(n_geo + 1, dtype=np.int32) * 32)
+    if name == "c3near":
+        # the humanoid batch recipe with the shelf slabs moved into reach of the hands (a test scene
+        # in which most projected configurations collide); 256 geodesics = 8,192 configurations
+        sc = humanoid36_scene(3, slab_x=(0.42, 0.5), slab_h=(1.0, 1.2))
+        n_geo = 32 if small else 256
         return dict(name=name, scene=sc, tol=1e-6, max_iter=40,
                     endpoints=raw_endpoints(sc, 3, n_geo, humanoid_noise_sigma()),
                     geo_offsets=np.arange(n_geo + 1, dtype=np.int32) * 32)

@@ -35,7 +35,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("project_batch", "check_batch", "project_vjp", "mc_problem_create", "mc_problem_destroy",
               "mc_last_error", "mc_default_opts", "interpolate_geodesics", "path_length_grad",
-              "mc_eval_residual_jacobian", "mc_fallback_count", "extend_batch"):
+              "mc_eval_residual_jacobian", "mc_fallback_count", "extend_batch", "mc_eval_condition",
+              "mc_queue_counts", "mc_autotune_candidates", "mc_autotune_project", "mc_tuned_shape"):
         assert n in names, n
 
 
@@ -53,6 +54,22 @@ def test_default_options(L):
     L.mc_default_opts(ctypes.byref(o))
     assert o.dtype == 0 and o.tol == 1e-6 and o.max_iter == 50 and o.alpha == 1.0 and o.lambda_ == 0.0
     assert o.max_step == 0.0 and o.fp64_cond_threshold == 1e6 and o.check_collision == 1 and o.variant == 0
+    assert o.mode == 0 and o.lanes_per_config == 0 and o.waves_per_block == 0 and o.blocks_per_cu == 0
+
+
+def test_autotune_candidates_and_host_errors(L):
+    from paper_2604_13323_amd import binding
+    n = L.mc_autotune_candidates(None)
+    shapes = (binding.LaunchShape * n)()
+    assert L.mc_autotune_candidates(shapes) == n and n >= 7
+    assert all(s.waves_per_block in (1, 2, 4) and s.lanes_per_config == 1 for s in shapes)
+    out = binding.LaunchShape()
+    assert L.mc_tuned_shape(None, 0, 0, ctypes.byref(out)) == MC_ERR_INVALID_ARG
+    assert L.mc_queue_counts(None, (ctypes.c_uint32 * 4)()) == MC_ERR_INVALID_ARG
+    assert L.mc_eval_condition(None, 1, None, 1, 0, 0.0, None, None) == MC_ERR_INVALID_ARG
+    o = binding.Opts()
+    L.mc_default_opts(ctypes.byref(o))
+    assert L.mc_autotune_project(None, 1, None, 1, ctypes.byref(o), 1, None, None, None) == MC_ERR_INVALID_ARG
 
 
 def test_create_rejects_malformed_blobs_on_the_host(L):

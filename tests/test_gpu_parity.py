@@ -1,13 +1,14 @@
 """GPU parity: the HIP library (through its C ABI) against the FP64 oracle on the same seeded
 inputs. Tolerances: projected coordinates within 1e-4 (FP32 mode) and 1e-9 (FP64 mode) of the
-oracle; statuses and iteration counts equal outside the band (see parity.py); collision verdicts
-equal outside a 1e-5 m margin band; VJPs within 1e-3 relative (FP32) / 1e-9 (FP64)."""
+oracle; statuses and iteration counts equal outside the band, band configurations compared as
+parity.py describes; collision verdicts equal outside a 1e-5 m margin band; VJPs within 1e-3
+relative (FP32) / 1e-9 (FP64)."""
 import math
 
 import numpy as np
 import pytest
 
-from parity import CONV, MAXIT, NONF, SING, band_mask, config_inputs, from_dev, to_dev
+from parity import CONV, MAXIT, NONF, SING, band_mask, compare, config_inputs, from_dev, oracle_run, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -31,43 +32,6 @@ def run_gpu(mc, sc, q, tol, max_iter, dtype=torch.float32, **kw):
     r = G.project(to_dev(q, dtype), tol=tol, max_iter=max_iter, **kw)
     torch.cuda.synchronize()
     return G, r
-
-
-def compare(P, q, r, tol, max_iter, qtol, require_iters=True, min_agree=0.98, max_band=0.05, max_step=0.0,
-            mode="stacked", alpha=1.0, lam=0.0):
-    qo, st, it, rs = P.project(q, tol=tol, max_iter=max_iter, max_step=max_step, mode=mode, alpha=alpha, lam=lam)
-    band = band_mask(P, q, tol, max_iter, max_step, mode, alpha=alpha, lam=lam)
-    gst = from_dev(r.status).astype(int)
-    git = from_dev(r.iters).astype(int)
-    gq = from_dev(r.q).T
-    out = ~band
-    # statuses agree outside the band
-    bad = out & (gst != st)
-    assert bad.sum() == 0, f"status mismatch on {bad.sum()} configs, e.g. idx {np.where(bad)[0][:5]}: gpu {gst[bad][:5]} oracle {st[bad][:5]}"
-    both = (gst == CONV) & (st == CONV) & out
-    err = np.abs(gq[both] - qo[both]).max(axis=1) if both.any() else np.zeros(0)
-    assert (err <= qtol).all(), f"q mismatch: max {err.max():.3e} on {np.sum(err > qtol)} configs"
-    agree = (git == it)[out & both]
-    if require_iters:
-        assert agree.all(), f"iteration mismatch on {np.sum(~agree)} configs"
-    else:
-        assert agree.mean() >= min_agree, f"iteration agreement {agree.mean():.4f}"
-    assert band.mean() < max_band, f"band too large: {band.mean():.3f}"
-    # converged residuals really are below tol
-    grs = from_dev(r.resid)
-    assert (grs[gst == CONV] < tol).all()
-    # band configurations: a converged GPU result must lie on the manifold (oracle residual at the
-    # GPU's output; FP32 outputs are checked only where FP32 can represent q to 1e-6 rad)
-    gb = band & (gst == CONV)
-    if r.q.dtype == torch.float32:
-        gb &= np.abs(gq).max(axis=1) < 1.0
-        ftol = 20 * tol
-    else:
-        ftol = 2 * tol
-    if gb.any():
-        Fg = np.linalg.norm(P.residual(gq[gb]), axis=1)
-        assert (Fg < ftol).all(), f"band config off the manifold: {Fg.max():.3e}"
-    return dict(n=len(q), band=int(band.sum()), max_err=float(err.max() if err.size else 0), conv=float((gst == CONV).mean()))
 
 
 # ---------------------------------------------------------------- closed forms through the GPU
@@ -160,26 +124,72 @@ def test_residual_and_jacobian_match_oracle(mc, name):
 
 
 # ---------------------------------------------------------------- projection parity
-# C1's specified inputs (uniform random joint vectors, far from the manifold) send most min-norm
-# Newton paths through near-singular Jacobians; those configurations are band (property-checked).
-# C0 chords pass near the origin, where the first radial (Heron) step is longer than 1: not
-# chaotic, but band by the step rule; the closed-form test covers those radii exactly.
-MAX_BAND = {"c0": 0.10, "c1": 0.85, "c2": 0.05, "c3": 0.05}
+# Band fractions under the band rule of parity.py, measured on these inputs: C1 0.27 in FP32 mode,
+# 0.23 in FP64 mode (0.20 / 0.17 unstable: min-norm paths from random joint vectors with steps of
+# hundreds of radians; 0.09 within a factor 2 of tol; 0.01 ill-conditioned), C2 0.16, C3 0.19 (all
+# through the tolerance criterion).
+MAX_BAND = {"c1": 0.30, "c2": 0.22, "c3": 0.25}
 
 
-@pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3"])
+def heron(r0, tol, max_iter):
+    """Radii and step count of the sphere projection from radius r0 (the min-norm step on
+    ||q||^2 - 1 is radial: r <- (r + 1/r) / 2), FP64."""
+    r, k, tests = r0, 0, []
+    while True:
+        tests.append(abs(r * r - 1.0))
+        if tests[-1] < tol or k >= max_iter:
+            return r, k, tests
+        r = 0.5 * (r + 1.0 / r)
+        k += 1
+
+
+@pytest.mark.parametrize("dt,qtol", [(torch.float32, 1e-4), (torch.float64, 1e-9)])
+def test_sphere_batch_matches_closed_form_everywhere(mc, dt, qtol):
+    """C0 without any band: every configuration converges to r_K q / ||q||, where r_K is the Heron
+    iterate at which |r^2 - 1| first drops below tol (-> q / ||q|| as tol -> 0), after exactly K
+    steps. In FP32 mode the step is rounded to FP32, which moves a radius by ~1e-7 of the step (the
+    last steps are ~1e-3, so a test value moves by ~1e-4 of tol): the count may differ only where a
+    Heron test value lies within 1e-3 (relative) of tol."""
+    sc, P, q, offs, tol, mi = config_inputs("c0", small=True)
+    G, r = run_gpu(mc, sc, q, tol, mi, dt, geo_offsets=offs)
+    st = from_dev(r.status).astype(int)
+    it = from_dev(r.iters).astype(int)
+    gq = from_dev(r.q).T
+    assert (st == CONV).all()
+    nrm = np.linalg.norm(q, axis=1)
+    want_q = np.zeros_like(q)
+    want_k = np.zeros(len(q), int)
+    close = np.zeros(len(q), bool)
+    for i, r0 in enumerate(nrm):
+        rk, k, tests = heron(r0, tol, mi)
+        want_q[i] = rk * q[i] / r0
+        want_k[i] = k
+        close[i] = any(abs(t / tol - 1.0) < 1e-3 for t in tests)
+    if dt == torch.float64:
+        assert (it == want_k).all(), f"{np.sum(it != want_k)} step counts differ from Heron's"
+    else:
+        assert (it[~close] == want_k[~close]).all(), f"{np.sum(it[~close] != want_k[~close])} step counts differ"
+        assert close.mean() < 0.01
+    # where the count differs (FP32, a test value at tol), both radii satisfy the tolerance
+    same = it == want_k
+    np.testing.assert_allclose(gq[same], want_q[same], atol=qtol)
+    np.testing.assert_allclose(gq / np.linalg.norm(gq, axis=1, keepdims=True), q / nrm[:, None],
+                               atol=5e-7 if dt == torch.float32 else 1e-14)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
 def test_projection_parity_fp32(mc, name):
     sc, P, q, offs, tol, mi = config_inputs(name, small=True)
     G, r = run_gpu(mc, sc, q, tol, mi, torch.float32, geo_offsets=offs)
-    stats = compare(P, q, r, tol, mi, 1e-4, require_iters=False, max_band=MAX_BAND[name])
+    stats = compare(P, q, r, tol, mi, 1e-4, max_band=MAX_BAND[name])
     print(name, stats)
 
 
-@pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
 def test_projection_parity_fp64(mc, name):
     sc, P, q, offs, tol, mi = config_inputs(name, small=True, max_geo=16)
     G, r = run_gpu(mc, sc, q, tol, mi, torch.float64, geo_offsets=offs)
-    stats = compare(P, q, r, tol, mi, 1e-9, require_iters=True, max_band=MAX_BAND[name])
+    stats = compare(P, q, r, tol, mi, 1e-9, max_band=MAX_BAND[name])
     print(name, stats)
 
 
@@ -192,7 +202,8 @@ def test_cyclic_mode_parity_humanoid(mc, dt, qtol):
     # alternating steps converge linearly on this humanoid (the blocks share the floating base):
     # at the benchmark's 1e-6 most paths need more than 40 cycles, at 1e-3 they converge in 1-9
     G, r = run_gpu(mc, sc, q, 1e-3, mi, dtype=dt, mode="cyclic")
-    info = compare(P, q, r, 1e-3, mi, qtol, require_iters=dt == torch.float64, mode="cyclic")
+    # block-wise steps converge linearly, so most paths pass within a factor 2 of tol (band 0.63)
+    info = compare(P, q, r, 1e-3, mi, qtol, max_band=0.7, mode="cyclic")
     assert info["conv"] > 0.99
     # five full cycles at tol 1e-6 (every path still running): the iterates agree step for step
     G, r = run_gpu(mc, sc, q, 1e-6, 5, dtype=dt, mode="cyclic")
@@ -219,7 +230,7 @@ def test_cyclic_mode_forced_fp64_tail_and_divergence(mc):
     assert torch.equal(rf.status, r64.status) and torch.equal(rf.iters, r64.iters)
     assert torch.equal(rf.q, r64.q.float())
     qin = from_dev(q32.double()).T
-    compare(P, qin, rd, tol, mi, 1e-9, max_step=1e-3, mode="cyclic", max_band=0.2)
+    compare(P, qin, rd, tol, mi, 1e-9, max_step=1e-3, mode="cyclic", max_band=0.3)
     qo, st, it, rs = P.project(qin, tol=tol, max_iter=mi, mode="cyclic", max_step=1e-3)
     band = band_mask(P, qin, tol, mi, 1e-3, "cyclic")
     div = (from_dev(rd.status).astype(int) == 3) & (st == 3) & ~band
@@ -235,7 +246,7 @@ def test_c1_with_divergence_exit(mc, dt, qtol):
     as DIVERGED on both sides, which keeps the remaining paths well conditioned."""
     sc, P, q, offs, tol, mi = config_inputs("c1", small=True)
     G, r = run_gpu(mc, sc, q, tol, mi, dt, max_step=0.5)
-    stats = compare(P, q, r, tol, mi, qtol, require_iters=dt == torch.float64, max_band=0.25, max_step=0.5)
+    stats = compare(P, q, r, tol, mi, qtol, max_band=0.05, max_step=0.5)
     print("c1 max_step 0.5", stats)
 
 
@@ -247,7 +258,8 @@ def test_damped_steps_parity(mc, name, dt, qtol):
     G = mc.Problem(sc.to_blob())
     r = G.project(to_dev(q, dt), tol=tol, max_iter=mi, lam=1e-3, alpha=0.9)
     torch.cuda.synchronize()
-    info = compare(P, q, r, tol, mi, qtol, require_iters=(dt == torch.float64), alpha=0.9, lam=1e-3)
+    # damped steps converge linearly: most paths pass within a factor 2 of tol (band 0.54-0.64)
+    info = compare(P, q, r, tol, mi, qtol, max_band=0.7, alpha=0.9, lam=1e-3)
     assert info["conv"] > 0.9, info
 
 
@@ -320,7 +332,7 @@ def test_fp64_tail_queue_matches_fp64_mode(mc, name):
     assert torch.equal(gi32, gi64.float())
 
 
-@pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3"])
+@pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3", "c3near"])
 def test_fused_verdicts_match_oracle(mc, name):
     """Verdicts written by project_batch (fused: broad-phase flag from the last residual pass,
     exact check only for flagged configurations) equal the oracle's brute-force check of the
@@ -337,12 +349,14 @@ def test_fused_verdicts_match_oracle(mc, name):
     vo, sdo = P.check(qg)
     out = np.abs(sdo) > 1e-5
     assert (v[conv][out] == vo[out]).all(), f"{np.sum(v[conv][out] != vo[out])} verdicts differ"
-    if name != "c0":
-        assert (vo == 1).any() or name == "c3", "workload has no colliding configuration to exercise the queue"
+    # the benchmark's humanoid scene keeps its shelves out of reach (collision-free by design); its
+    # c3near variant moves them into reach of the hands
+    if name not in ("c0", "c3"):
+        assert (vo == 1).any(), "workload has no colliding configuration to exercise the queue"
 
 
 # ---------------------------------------------------------------- collision parity
-@pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3"])
+@pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3", "c3near"])
 def test_check_batch_matches_oracle(mc, name):
     sc, P, q, offs, tol, mi = config_inputs(name, small=True, max_geo=16)
     qo = P.project(q, tol=1e-9, max_iter=60)[0]
