@@ -168,6 +168,23 @@ mc_status project_batch(const mc_problem* p, int64_t n,
                         const int32_t* geo_offsets, const int32_t* geo_offsets_host, int32_t n_geo,
                         uint8_t* geo_ok, const mc_project_opts* opts, void* stream);
 
+/* project_batch_noalloc — project_batch for callers that cannot allocate device memory: code
+   under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc. Same arguments,
+   kernels and results as project_batch; it calls no hipMalloc, hipFree or allocating library
+   routine. Its queue counters and FP64 / exact-check queues live in a 64 MiB array of the library
+   (one per device, looked up on the first call on a device with that device current, and held
+   until the process ends) instead of the problem's grown buffers: n is limited to
+   floor((64 MiB - 1 KiB) / (16 d + 12)) configurations, d the family's compiled dimension (114,126
+   for the 36-DoF family; 8 for the linear family), and a larger n fails with MC_ERR_INVALID_ARG
+   before anything is enqueued. Every call on one device shares that array and clears its counters
+   itself: calls that overlap on one device (concurrent streams, or threads) race and must not be
+   issued. mc_queue_counts does not report the counters of this call. */
+mc_status project_batch_noalloc(const mc_problem* p, int64_t n,
+                                const void* q_in, int64_t ld_in, void* q_out, int64_t ld_out,
+                                int8_t* status, int8_t* iters, void* resid, uint8_t* verdict,
+                                const int32_t* geo_offsets, const int32_t* geo_offsets_host, int32_t n_geo,
+                                uint8_t* geo_ok, const mc_project_opts* opts, void* stream);
+
 /* check_batch — collision check of arbitrary configurations (Sec. IV-A: robot spheres vs obstacle
    spheres, collision when ||c_i - o_j||^2 < (r_i + r_j)^2 for some pair).
    verdict uint8[n]: MC_FREE or MC_COLLIDES. min_signed_dist (nullable, dtype[n]): minimum over

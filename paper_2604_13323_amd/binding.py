@@ -56,7 +56,7 @@ EXPORTS = ["mc_default_opts", "mc_problem_create", "mc_problem_destroy", "mc_pro
            "mc_problem_family", "mc_last_error", "project_batch", "check_batch", "project_vjp",
            "interpolate_geodesics", "path_length_grad", "mc_eval_residual_jacobian", "mc_fallback_count", "extend_batch",
            "mc_eval_condition", "mc_queue_counts", "mc_autotune_candidates", "mc_autotune_project", "mc_tuned_shape",
-           "mc_set_kernel_timing", "mc_last_kernel_ms"]
+           "mc_set_kernel_timing", "mc_last_kernel_ms", "project_batch_noalloc"]
 
 
 def lib():
@@ -79,6 +79,7 @@ def lib():
     L.mc_last_error.argtypes = []
     L.mc_last_error.restype = ctypes.c_char_p
     L.project_batch.argtypes = [P, I64, P, I64, P, I64, P, P, P, P, P, P, I32, P, ctypes.POINTER(Opts), P]
+    L.project_batch_noalloc.argtypes = L.project_batch.argtypes
     L.check_batch.argtypes = [P, I64, P, I64, ctypes.c_int, P, P, P]
     L.project_vjp.argtypes = [P, I64, P, I64, P, P, P, ctypes.POINTER(Opts), P]
     L.interpolate_geodesics.argtypes = [P, I32, P, P, I64, I64, P, I64, ctypes.c_int, P]
@@ -202,11 +203,12 @@ class Problem:
     def project(self, q: torch.Tensor, tol=1e-6, max_iter=50, alpha=1.0, lam=0.0, max_step=0.0, cond=1e6,
                 check=True, variant="auto", geo_offsets=None, geo_ok=False, waves_per_block=0, blocks_per_cu=0,
                 out: ProjectResult | None = None, geo_offsets_host=None, mode="stacked",
-                lanes_per_config=0) -> ProjectResult:
+                lanes_per_config=0, noalloc=False) -> ProjectResult:
         """Project the columns of q ([d, n], float32 or float64). geo_offsets (CSR, int32) may be a host array
         or a device tensor; the plain variant also needs them on the host (geo_offsets_host, or a host
         geo_offsets). Under stream capture pass device offsets, `out`, and call once eagerly beforehand with a
-        batch at least as large (that sizes the library's work queues)."""
+        batch at least as large (that sizes the library's work queues). noalloc=True calls project_batch_noalloc (the
+        library's fixed scratch array instead of the problem's grown queues: nothing is allocated)."""
         n, ld = _soa(q, self.d, "project")
         dt = _dtype_code(q)
         dev = q.device
@@ -236,11 +238,12 @@ class Problem:
                 out.geo_ok = torch.empty(n_geo, dtype=torch.uint8, device=dev)
         o = make_opts(dt, tol, max_iter, alpha, lam, max_step, cond, check, variant, waves_per_block, blocks_per_cu,
                       mode, lanes_per_config)
-        rc = lib().project_batch(self._h, n, _ptr(q), ld, _ptr(out.q), out.q.stride(0), _ptr(out.status),
+        fn = lib().project_batch_noalloc if noalloc else lib().project_batch
+        rc = fn(self._h, n, _ptr(q), ld, _ptr(out.q), out.q.stride(0), _ptr(out.status),
                                  _ptr(out.iters), _ptr(out.resid), _ptr(out.verdict), _ptr(offs_dev),
                                  None if offs_host is None else offs_host.ctypes.data_as(ctypes.c_void_p),
                                  n_geo, _ptr(out.geo_ok) if geo_ok else None, ctypes.byref(o), _stream())
-        _check(rc, "project_batch")
+        _check(rc, "project_batch_noalloc" if noalloc else "project_batch")
         return out
 
     def extend(self, q_start: torch.Tensor, q_target: torch.Tensor, eps: torch.Tensor, r: float, delta: float,

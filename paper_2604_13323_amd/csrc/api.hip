@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -995,12 +996,50 @@ static mc_status check_opts(const mc_problem* p, const mc_project_opts* o) {
 
 }  // extern "C"
 
-// Body of project_batch (its workspace: the problem's queues, grown when a batch is larger than any
-// before).
+// ---------------------------------------------------------------- allocation-free workspace
+// project_batch_noalloc takes the queue counters and the FP64 and exact-check queues of its call
+// from this file-scope array (one copy per device, kept until the process ends) instead of the
+// problem's grown buffers. Its layout per call: 4 counters, then the FP64 queue (iterates, then
+// index and step pairs) and the exact-check queue (configurations, then indices), sized for the
+// call's n, each part 256-byte aligned.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kScratchDevices] = {};
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Bytes of the scratch layout for n configurations of dmax coordinates.
+static size_t scratch_bytes(int64_t n, int dmax) {
+  return align256(4 * sizeof(uint32_t)) + 2 * align256(size_t(n) * dmax * sizeof(double)) +
+         align256(size_t(n) * 2 * sizeof(int32_t)) + align256(size_t(n) * sizeof(int32_t));
+}
+
+// The device address of `scratch` on the current device (looked up once per device, with that
+// device current: the array's host-side name is not a device address).
+static mc_status scratch_on_current_device(unsigned char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "project_batch_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= kScratchDevices) return fail(MC_ERR_UNSUPPORTED, "project_batch_noalloc: device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if ((e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))) != hipSuccess)
+      return hip_fail(e, "project_batch_noalloc: hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  return MC_OK;
+}
+
+// Shared body of project_batch (noalloc = false: the problem's workspace, grown when a batch is
+// larger than any before) and project_batch_noalloc (the device's scratch array).
 static mc_status project_impl(const mc_problem* p, int64_t n, const void* q_in, int64_t ld_in, void* q_out, int64_t ld_out,
                               int8_t* status, int8_t* iters, void* resid, uint8_t* verdict, const int32_t* geo_offsets,
                               const int32_t* geo_offsets_host, int32_t n_geo, uint8_t* geo_ok,
-                              const mc_project_opts* opts, void* stream) {
+                              const mc_project_opts* opts, void* stream, bool noalloc) {
   g_err.clear();
   if (!p) return fail(MC_ERR_INVALID_ARG, "project_batch: null problem");
   if (n < 0) return fail(MC_ERR_INVALID_ARG, "project_batch: n < 0");
@@ -1021,7 +1060,17 @@ static mc_status project_impl(const mc_problem* p, int64_t n, const void* q_in, 
   const FamilyOps* ops = ops_for(p->family, opts->dtype == MC_F64);
   if (!ops) return fail(MC_ERR_UNSUPPORTED, "project_batch: family without kernels");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  unsigned int* counter = p->counter;
+  unsigned char* scr = nullptr;
+  if (noalloc) {
+    // the documented limit; the layout's alignment padding (< 1 KiB) fits below it
+    const int64_t cap = int64_t((kScratchBytes - 1024) / (16 * size_t(ops->dof_max) + 12));
+    if (n > cap || scratch_bytes(n, ops->dof_max) > kScratchBytes)
+      return fail(MC_ERR_INVALID_ARG, "project_batch_noalloc: n = " + std::to_string(n) + " exceeds the scratch capacity of " +
+                                          std::to_string(cap) + " configurations for this family");
+    mc_status sst = scratch_on_current_device(&scr);
+    if (sst != MC_OK) return sst;
+  }
+  unsigned int* counter = noalloc ? reinterpret_cast<unsigned int*>(scr) : p->counter;
 
   ProjArgs a;
   std::memset(&a, 0, sizeof a);
@@ -1095,12 +1144,25 @@ static mc_status project_impl(const mc_problem* p, int64_t n, const void* q_in, 
     if (tail || ctail) {
       a.defer_count = counter + 1;
       a.chk_count = counter + 3;
-      if ((e = grow_defer(p, n, ops->dof_max)) != hipSuccess) return hip_fail(e, "project_batch: queue allocation");
-      a.defer_ik = p->defer_ik;
-      a.defer_q = p->defer_q;
-      a.defer_cap = p->defer_cap;
-      a.chk_idx = p->chk_idx;
-      a.chk_q = p->chk_q;
+      if (noalloc) {
+        size_t off = align256(4 * sizeof(uint32_t));
+        const size_t nq = align256(size_t(n) * ops->dof_max * sizeof(double));
+        a.defer_q = reinterpret_cast<double*>(scr + off);
+        off += nq;
+        a.defer_ik = reinterpret_cast<int32_t*>(scr + off);
+        off += align256(size_t(n) * 2 * sizeof(int32_t));
+        a.chk_q = reinterpret_cast<double*>(scr + off);
+        off += nq;
+        a.chk_idx = reinterpret_cast<int32_t*>(scr + off);
+        a.defer_cap = n;
+      } else {
+        if ((e = grow_defer(p, n, ops->dof_max)) != hipSuccess) return hip_fail(e, "project_batch: queue allocation");
+        a.defer_ik = p->defer_ik;
+        a.defer_q = p->defer_q;
+        a.defer_cap = p->defer_cap;
+        a.chk_idx = p->chk_idx;
+        a.chk_q = p->chk_q;
+      }
     }
     a.verdict = verdict;
     // counters cleared by a kernel (graph-capturable), never by a memset
@@ -1133,7 +1195,15 @@ mc_status project_batch(const mc_problem* p, int64_t n, const void* q_in, int64_
                         const int32_t* geo_offsets_host, int32_t n_geo, uint8_t* geo_ok, const mc_project_opts* opts,
                         void* stream) {
   return project_impl(p, n, q_in, ld_in, q_out, ld_out, status, iters, resid, verdict, geo_offsets, geo_offsets_host,
-                      n_geo, geo_ok, opts, stream);
+                      n_geo, geo_ok, opts, stream, false);
+}
+
+mc_status project_batch_noalloc(const mc_problem* p, int64_t n, const void* q_in, int64_t ld_in, void* q_out,
+                                int64_t ld_out, int8_t* status, int8_t* iters, void* resid, uint8_t* verdict,
+                                const int32_t* geo_offsets, const int32_t* geo_offsets_host, int32_t n_geo,
+                                uint8_t* geo_ok, const mc_project_opts* opts, void* stream) {
+  return project_impl(p, n, q_in, ld_in, q_out, ld_out, status, iters, resid, verdict, geo_offsets, geo_offsets_host,
+                      n_geo, geo_ok, opts, stream, true);
 }
 
 mc_status check_batch(const mc_problem* p, int64_t n, const void* q, int64_t ld, mc_dtype dtype, uint8_t* verdict,
