@@ -56,6 +56,8 @@ def lib():
         L.oracle_vjp.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, P, P, P, ctypes.c_int]
         L.oracle_path_length.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_int32, P, P]
         L.oracle_kappa_est.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, ctypes.c_double, P, P, ctypes.c_int]
+        L.oracle_vjp_exact.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, P, ctypes.c_double, ctypes.c_int32,
+                                       ctypes.c_double, ctypes.c_double, P, ctypes.c_int]
         L.oracle_max_threads.argtypes = []
         _lib = L
     return _lib
@@ -144,6 +146,17 @@ class Problem:
         assert lib().oracle_vjp(*self._args(), n, _p(q), None if st is None else _p(st), _p(g), _p(gi),
                                 _p(kap), threads) == 0
         return gi, kap
+
+    def vjp_exact(self, q0, g, tol=1e-13, max_iter=100, alpha=1.0, lam=0.0, threads: int = 0):
+        """(g_in, status): g_in = (dP/dq0)^T g, the derivative of the projection map at the (possibly
+        off-manifold) inputs q0, by forward-mode dual numbers through every Newton step run to tol."""
+        q0 = np.ascontiguousarray(q0, np.float64).reshape(-1, self.d)
+        g = np.ascontiguousarray(g, np.float64).reshape(-1, self.d)
+        gi = np.zeros_like(q0)
+        st = np.zeros(len(q0), np.int8)
+        assert lib().oracle_vjp_exact(*self._args(), len(q0), _p(q0), _p(g), _p(gi), float(tol), int(max_iter),
+                                      float(alpha), float(lam), _p(st), threads) == 0
+        return gi, st
 
     def kappa_est(self, q, lam=0.0, threads: int = 0):
         """(kappa_est, kappa2) per configuration: (max L_ii / min L_ii)^2 of the FP64 Cholesky factor

@@ -142,23 +142,31 @@ bool parse(const void* blob, size_t nbytes, Scene& s) {
 }
 
 // ------------------------------------------------------------ dual numbers
-// Forward-mode AD value with one tangent direction.
-struct Dual {
-  double v, d;
-  Dual(double a = 0.0, double b = 0.0) : v(a), d(b) {}
+// Forward-mode AD value with one tangent direction, over any scalar T: Dn<double> gives first
+// derivatives (the Jacobian), Dn<Dn<double>> second derivatives (the derivative of J along a
+// direction, which differentiating the Newton iteration itself needs).
+template <class T>
+struct Dn {
+  T v, d;
+  Dn(double a = 0.0) : v(a), d(0.0) {}
+  Dn(T a, T b) : v(a), d(b) {}
 };
-inline Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
-inline Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
-inline Dual operator-(Dual a) { return {-a.v, -a.d}; }
-inline Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
-inline Dual operator/(Dual a, Dual b) { return {a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)}; }
-inline Dual sin(Dual a) { return {std::sin(a.v), std::cos(a.v) * a.d}; }
-inline Dual cos(Dual a) { return {std::cos(a.v), -std::sin(a.v) * a.d}; }
-inline Dual sqrt(Dual a) { double s = std::sqrt(a.v); return {s, a.d / (2.0 * s)}; }
-inline Dual atan2(Dual y, Dual x) { double r2 = x.v * x.v + y.v * y.v; return {std::atan2(y.v, x.v), (x.v * y.d - y.v * x.d) / r2}; }
-inline double val(double x) { return x; }
-inline double val(Dual x) { return x.v; }
+using Dual = Dn<double>;
+template <class T> inline Dn<T> operator+(Dn<T> a, Dn<T> b) { return {a.v + b.v, a.d + b.d}; }
+template <class T> inline Dn<T> operator-(Dn<T> a, Dn<T> b) { return {a.v - b.v, a.d - b.d}; }
+template <class T> inline Dn<T> operator-(Dn<T> a) { return {-a.v, -a.d}; }
+template <class T> inline Dn<T> operator*(Dn<T> a, Dn<T> b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+template <class T> inline Dn<T> operator/(Dn<T> a, Dn<T> b) { return {a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)}; }
 using std::sin; using std::cos; using std::sqrt; using std::atan2;
+template <class T> inline Dn<T> sin(Dn<T> a) { return {sin(a.v), cos(a.v) * a.d}; }
+template <class T> inline Dn<T> cos(Dn<T> a) { return {cos(a.v), -(sin(a.v) * a.d)}; }
+template <class T> inline Dn<T> sqrt(Dn<T> a) { T s = sqrt(a.v); return {s, a.d / (T(2.0) * s)}; }
+template <class T> inline Dn<T> atan2(Dn<T> y, Dn<T> x) {
+  T r2 = x.v * x.v + y.v * y.v;
+  return {atan2(y.v, x.v), (x.v * y.d - y.v * x.d) / r2};
+}
+inline double val(double x) { return x; }
+template <class T> inline double val(Dn<T> x) { return val(x.v); }
 
 // ------------------------------------------------------- rigid transforms
 template <class T> struct Tf { T R[3][3]; T p[3]; };
@@ -322,15 +330,18 @@ template <class T> void residual(const Scene& s, const Targets& tg, const T* q, 
   }
 }
 
-// Jacobian by forward-mode duals, one column per pass. J is m x d row-major.
-void jacobian(const Scene& s, const Targets& tg, const double* q, double* J) {
-  std::vector<Dual> qd(s.d), Fd(s.m);
+// Jacobian by forward-mode duals, one column per pass. J is m x d row-major. Over T = Dual the
+// entries carry their own derivative along q's tangent.
+template <class T>
+void jacobian_t(const Scene& s, const Targets& tg, const T* q, T* J) {
+  std::vector<Dn<T>> qd(s.d), Fd(s.m);
   for (int j = 0; j < s.d; ++j) {
-    for (int i = 0; i < s.d; ++i) qd[i] = Dual(q[i], i == j ? 1.0 : 0.0);
-    residual<Dual>(s, tg, qd.data(), Fd.data());
+    for (int i = 0; i < s.d; ++i) qd[i] = Dn<T>(q[i], T(i == j ? 1.0 : 0.0));
+    residual<Dn<T>>(s, tg, qd.data(), Fd.data());
     for (int i = 0; i < s.m; ++i) J[size_t(i) * s.d + j] = Fd[i].d;
   }
 }
+void jacobian(const Scene& s, const Targets& tg, const double* q, double* J) { jacobian_t<double>(s, tg, q, J); }
 
 // ------------------------------------------------------ dense linear algebra
 // Householder QR of a rows x cols matrix A (column-major, rows >= cols), in place:
@@ -452,6 +463,111 @@ bool descent_step(int m, int d, const double* J, const double* F, double lambda,
 }
 
 double norm2(const double* x, int n) { double a = 0; for (int i = 0; i < n; ++i) a += x[i] * x[i]; return std::sqrt(a); }
+
+// ------------------------------------------------- the iteration as a differentiable map
+// The same Householder QR and min-norm / damped step as above, over any scalar T, so the
+// Newton iteration can run on dual numbers and carry the derivative of the projection map along.
+template <class T>
+void householder_qr_t(int rows, int cols, T* A, T* tau) {
+  for (int k = 0; k < cols; ++k) {
+    T* a = A + size_t(k) * rows;
+    T nrm2 = T(0.0);
+    for (int i = k; i < rows; ++i) nrm2 = nrm2 + a[i] * a[i];
+    if (val(nrm2) == 0.0) { tau[k] = T(0.0); continue; }
+    T nrm = sqrt(nrm2);
+    T alpha = val(a[k]) > 0 ? -nrm : nrm;
+    T v0 = a[k] - alpha;
+    for (int i = k + 1; i < rows; ++i) a[i] = a[i] / v0;
+    tau[k] = (alpha - a[k]) / alpha;
+    a[k] = alpha;
+    for (int c = k + 1; c < cols; ++c) {
+      T* b = A + size_t(c) * rows;
+      T dot = b[k];
+      for (int i = k + 1; i < rows; ++i) dot = dot + a[i] * b[i];
+      dot = dot * tau[k];
+      b[k] = b[k] - dot;
+      for (int i = k + 1; i < rows; ++i) b[i] = b[i] - dot * a[i];
+    }
+  }
+}
+template <class T>
+void apply_reflector_t(int rows, int k, const T* A, const T* tau, T* x) {
+  const T* a = A + size_t(k) * rows;
+  T dot = x[k];
+  for (int i = k + 1; i < rows; ++i) dot = dot + a[i] * x[i];
+  dot = dot * tau[k];
+  x[k] = x[k] - dot;
+  for (int i = k + 1; i < rows; ++i) x[i] = x[i] - dot * a[i];
+}
+// delta with J delta = F (min-norm for lambda = 0, else the damped least-squares step); false when J
+// is singular (the test on the values, as descent_step).
+template <class T>
+bool descent_step_t(int m, int d, const T* J, const T* F, double lambda, T* delta) {
+  std::vector<double> Jv(size_t(m) * d), At(size_t(d) * m), sv(m);
+  for (int i = 0; i < m * d; ++i) Jv[i] = val(J[i]);
+  for (int i = 0; i < m; ++i) for (int j = 0; j < d; ++j) At[size_t(i) * d + j] = Jv[size_t(i) * d + j];
+  jacobi_singular_values(d, m, At.data(), sv.data());
+  double smax = 0, smin = INFINITY;
+  for (double x : sv) { smax = std::max(smax, x); smin = std::min(smin, x); }
+  if (!(smax > 0.0) || smin / smax < 1e-12) return false;
+  if (lambda <= 0.0) {
+    std::vector<T> B(size_t(d) * m), tau(m), z(d, T(0.0));
+    for (int i = 0; i < m; ++i) for (int j = 0; j < d; ++j) B[size_t(i) * d + j] = J[size_t(i) * d + j];
+    householder_qr_t(d, m, B.data(), tau.data());
+    for (int i = 0; i < m; ++i) {
+      T acc = F[i];
+      for (int k = 0; k < i; ++k) acc = acc - B[size_t(i) * d + k] * z[k];
+      z[i] = acc / B[size_t(i) * d + i];
+    }
+    for (int k = m - 1; k >= 0; --k) apply_reflector_t(d, k, B.data(), tau.data(), z.data());
+    for (int j = 0; j < d; ++j) delta[j] = z[j];
+  } else {
+    const int rows = m + d;
+    std::vector<T> B(size_t(rows) * d, T(0.0)), rhs(rows, T(0.0)), tau(d);
+    for (int j = 0; j < d; ++j) {
+      for (int i = 0; i < m; ++i) B[size_t(j) * rows + i] = J[size_t(i) * d + j];
+      B[size_t(j) * rows + m + j] = T(std::sqrt(lambda));
+    }
+    for (int i = 0; i < m; ++i) rhs[i] = F[i];
+    householder_qr_t(rows, d, B.data(), tau.data());
+    for (int k = 0; k < d; ++k) apply_reflector_t(rows, k, B.data(), tau.data(), rhs.data());
+    for (int i = d - 1; i >= 0; --i) {
+      T acc = rhs[i];
+      for (int k = i + 1; k < d; ++k) acc = acc - B[size_t(k) * rows + i] * delta[k];
+      delta[i] = acc / B[size_t(i) * rows + i];
+    }
+  }
+  return true;
+}
+// ParallelProject (Alg. 2, stacked) of one configuration, in place, over scalar T; the convergence and
+// exit tests look at the values. After convergence `extra` more steps are taken (each is the identity
+// on the values up to ||F||, and on the derivative the tangent projector: the converged map's
+// derivative at an input that needs no step is that projector, not the identity). Returns the status;
+// iters = steps taken before convergence.
+template <class T>
+int newton_map_t(const Scene& s, const Targets& tg, const Opts& o, T* q, int* iters, int extra = 0) {
+  const int d = s.d, m = s.m;
+  std::vector<T> F(m), J(size_t(m) * d), delta(d);
+  int conv_at = -1;
+  for (int k = 0;; ++k) {
+    residual<T>(s, tg, q, F.data());
+    double n2 = 0.0;
+    bool fin = true;
+    for (int i = 0; i < m; ++i) { n2 += val(F[i]) * val(F[i]); fin = fin && std::isfinite(val(F[i])); }
+    if (conv_at < 0) *iters = k;
+    if (!fin) return ST_NONFINITE;
+    if (conv_at < 0 && std::sqrt(n2) < o.tol) conv_at = k;
+    if (conv_at >= 0 && k - conv_at >= extra) return ST_CONVERGED;
+    if (conv_at < 0 && k >= o.max_iter) return ST_MAX_ITER;
+    jacobian_t<T>(s, tg, q, J.data());
+    if (!descent_step_t<T>(m, d, J.data(), F.data(), o.lambda, delta.data())) return ST_SINGULAR;
+    double s2 = 0.0;
+    for (int j = 0; j < d; ++j) { delta[j] = delta[j] * T(o.alpha); s2 += val(delta[j]) * val(delta[j]); }
+    if (!std::isfinite(s2)) return ST_NONFINITE;
+    if (o.max_step > 0.0 && std::sqrt(s2) > o.max_step) return ST_DIVERGED;
+    for (int j = 0; j < d; ++j) q[j] = q[j] - delta[j];
+  }
+}
 
 // Path record of one projection (nullable), used by the parity tests to recognise outcomes that are
 // not well posed for an exact comparison: [0] smallest sigma_min(J) over the steps taken, [1] longest
@@ -766,6 +882,40 @@ int oracle_kappa_est(const void* blob, size_t nbytes, int64_t n, const double* q
       for (double x : sv) { smax = std::max(smax, x); smin = std::min(smin, x); }
       kappa2[c] = (smax / smin) * (smax / smin);
     }
+  }
+  return 0;
+}
+
+// Exact VJP of the projection map q0 -> P(q0) at arbitrary (off-manifold) inputs: the Jacobian of
+// the map is obtained column by column by running the Newton iteration on dual numbers seeded
+// with the input direction e_i (forward-mode through every step, second derivatives of F
+// included), to the given tolerance and one step past it; g_in = (dP/dq0)^T g. Run to a tight
+// tolerance (1e-13 or below) this is the derivative of the fully converged projection (up to
+// the final ||F||). status [n] receives the value iteration's status; configurations that do not
+// converge get g_in = 0.
+int oracle_vjp_exact(const void* blob, size_t nbytes, int64_t n, const double* q0, const double* g, double* g_in,
+                     double tol, int32_t max_iter, double alpha, double lambda, int8_t* status, int nthreads) {
+  Scene s;
+  if (!parse(blob, nbytes, s)) return 1;
+  if (n < 0 || !(tol > 0) || max_iter < 0) return 2;
+  Targets tg = make_targets(s);
+  const int d = s.d;
+  Opts o{tol, max_iter, alpha, lambda, 0.0, 0};
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads_or_default(nthreads))
+  for (int64_t c = 0; c < n; ++c) {
+    std::vector<Dual> q(d);
+    double* out = g_in + c * d;
+    int st = ST_CONVERGED, it = 0;
+    for (int i = 0; i < d && st == ST_CONVERGED; ++i) {
+      for (int j = 0; j < d; ++j) q[j] = Dual(q0[c * d + j], j == i ? 1.0 : 0.0);
+      st = newton_map_t<Dual>(s, tg, o, q.data(), &it, 1);
+      double acc = 0.0;
+      for (int j = 0; j < d; ++j) acc += q[j].d * g[c * d + j];  // (dP_j / dq0_i) g_j
+      out[i] = acc;
+    }
+    if (status) status[c] = int8_t(st);
+    if (st != ST_CONVERGED)
+      for (int i = 0; i < d; ++i) out[i] = 0.0;
   }
   return 0;
 }

@@ -723,3 +723,85 @@ def test_kappa_est_is_a_lower_bound_of_kappa2(oracle_mod, name):
     fin = np.isfinite(ke)
     assert fin.mean() > 0.99
     assert (ke[fin] <= k2[fin] * (1 + 1e-9)).all()
+
+
+# ---------------------------------------------------------------- exact derivative of the projection map
+def test_vjp_exact_sphere_closed_form_off_manifold(oracle_mod):
+    """The converged sphere projection is q0 / ||q0||, whose derivative (I - q^ q^T) / ||q0|| holds at
+    every input, near the origin and far outside the sphere alike."""
+    P = prob(S.sphere_scene(0))
+    rng = np.random.default_rng(21)
+    u = rng.standard_normal((6, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    q0 = u * np.array([0.05, 0.3, 0.9, 1.1, 2.5, 7.0])[:, None]
+    g = rng.standard_normal((6, 3))
+    gi, st = P.vjp_exact(q0, g)
+    assert (st == CONV).all()
+    r = np.linalg.norm(q0, axis=1, keepdims=True)
+    want = (g - u * np.sum(u * g, axis=1, keepdims=True)) / r
+    np.testing.assert_allclose(gi, want, atol=1e-10 * np.abs(want).max())
+
+
+def test_vjp_exact_linear_steps_closed_form(oracle_mod):
+    """F = A q - b: one min-norm step lands on the manifold from anywhere, so the map's derivative is
+    I - A^+ A at every input. With damping lambda and step scale alpha every step is the same linear
+    map q -> q - M (q - q*), M = alpha (A^T A + lambda I)^-1 A^T A, so after the oracle's K steps and
+    the one past convergence the derivative is (I - M)^(K+1)."""
+    rng = np.random.default_rng(22)
+    A = rng.standard_normal((3, 6))
+    b = rng.standard_normal(3)
+    P = prob(S.linear_scene(A, b))
+    q0 = 3.0 * rng.standard_normal((4, 6))
+    g = rng.standard_normal((4, 6))
+    gi, st = P.vjp_exact(q0, g)
+    Pr = np.eye(6) - np.linalg.pinv(A) @ A
+    np.testing.assert_allclose(gi, g @ Pr.T, atol=1e-11)
+    lam, alpha = 0.3, 0.8
+    gi, st = P.vjp_exact(q0, g, tol=1e-10, max_iter=400, alpha=alpha, lam=lam)
+    _, st2, it, _ = P.project(q0, tol=1e-10, max_iter=400, alpha=alpha, lam=lam)
+    assert (st == CONV).all() and (st2 == CONV).all()
+    M = alpha * np.linalg.solve(A.T @ A + lam * np.eye(6), A.T @ A)
+    for k in range(4):
+        D = np.linalg.matrix_power(np.eye(6) - M, int(it[k]) + 1)  # dq_(K+1) / dq_0
+        np.testing.assert_allclose(gi[k], D.T @ g[k], atol=1e-11)
+
+
+@pytest.mark.parametrize("name", ["c1", "c4"])
+def test_vjp_exact_matches_fd_of_the_projection_off_manifold(oracle_mod, name):
+    """At the raw (off-manifold) inputs of the arm and humanoid batches: central differences (h = 1e-6)
+    of the oracle's projection run to ||F|| < 1e-13 (the converged map) against the forward-mode
+    derivative, relative error in ||g_in||."""
+    from parity import config_inputs
+    sc, P, q, offs, tol, mi = config_inputs(name, small=True, max_geo=1)
+    q = q[:6]
+    _, st0, _, _, pi = P.project(q, tol=1e-13, max_iter=100, path_info=True)
+    keep = (st0 == CONV) & (pi[:, 0] > 1e-2) & (pi[:, 1] < 1.0)  # well-conditioned paths, FD is meaningful
+    q = q[keep]
+    assert len(q) >= 3
+    rng = np.random.default_rng(23)
+    g = rng.standard_normal(q.shape)
+    gi, st = P.vjp_exact(q, g)
+    h, d = 1e-6, sc.d
+    qp = np.repeat(q, d, axis=0) + h * np.tile(np.eye(d), (len(q), 1))
+    qm = np.repeat(q, d, axis=0) - h * np.tile(np.eye(d), (len(q), 1))
+    pp = P.project(qp, tol=1e-13, max_iter=100)[0]
+    pm = P.project(qm, tol=1e-13, max_iter=100)[0]
+    dP = ((pp - pm) / (2 * h)).reshape(len(q), d, d)  # [n, i (input), :] = dP / dq_i
+    g_fd = np.einsum("nij,nj->ni", dP, g)
+    rel = np.linalg.norm(gi - g_fd, axis=1) / np.linalg.norm(g_fd, axis=1)
+    assert rel.max() < 1e-5, rel
+    # off the manifold the exact derivative is not the tangent projector at the output
+    go, _ = P.vjp(P.project(q, tol=1e-13, max_iter=100)[0], g)
+    assert (np.linalg.norm(go - g_fd, axis=1) / np.linalg.norm(g_fd, axis=1)).max() > 1e-4
+
+
+def test_vjp_exact_on_the_manifold_is_the_tangent_projector(oracle_mod):
+    """From an input already on the manifold the converged map's derivative is I - J^+ J there."""
+    from parity import config_inputs
+    sc, P, q, offs, tol, mi = config_inputs("c3", small=True, max_geo=1)
+    q = P.project(q[:4], tol=1e-14, max_iter=100)[0]
+    g = np.random.default_rng(24).standard_normal(q.shape)
+    gi, st = P.vjp_exact(q, g, tol=1e-13)
+    go, _ = P.vjp(q, g)
+    assert (st == CONV).all()
+    np.testing.assert_allclose(gi, go, atol=1e-8 * np.abs(go).max())
