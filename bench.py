@@ -374,6 +374,23 @@ def main():
         log(f"fwd+vjp: {ms4:.3f} ms/step, {fv['value']:.4g} configurations/s; VJP kernel {np.mean(vms):.4f} ms, "
             f"{vjp_tflops:.2f} TFLOP/s")
 
+        # the exact VJP of the map at the (off-manifold) interpolants: reverse mode through the steps
+        def fwd_vjp_exact():
+            G.project(q4, variant="fused", out=o4, **kw4)
+            g, _ = G.path_length_grad(o4.q, offs4)
+            G.vjp_exact(q4, o4.status, o4.iters, g)
+
+        ms4x = timed(fwd_vjp_exact, max(3, args.steps // 2), 1, torch, "fwd_vjp_exact")
+        G.kernel_timing(True)
+        xms = []
+        for _ in range(3):
+            G.vjp_exact(q4, o4.status, o4.iters, g4)
+            xms.append(G.last_kernel_ms("vjp"))
+        G.kernel_timing(False)
+        fv["exact"] = dict(value=n4 / (ms4x * 1e-3), ms_per_step=ms4x, vjp_exact_kernel_ms=float(np.mean(xms)))
+        log(f"fwd+exact vjp: {ms4x:.3f} ms/step, {fv['exact']['value']:.4g} configurations/s; "
+            f"exact VJP kernel {np.mean(xms):.3f} ms")
+
     if args.copy_calibration:
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

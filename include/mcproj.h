@@ -204,6 +204,24 @@ mc_status project_vjp(const mc_problem* p, int64_t n, const void* q_proj, int64_
                       const int8_t* status, const void* g_out, void* g_in,
                       const mc_project_opts* opts, void* stream);
 
+/* project_vjp_exact — the exact vector-Jacobian product of the projection map at the (possibly
+   off-manifold) inputs: g_in = (dP/dq_in)^T g_out, where P is the iteration of project_batch (Alg. 2
+   ParallelProject, stacked mode) continued to convergence. Reverse mode through the Newton steps the
+   forward call took: the output cotangent is projected on the tangent space at the converged point
+   (I - J^+ J, what a further step there does), then pulled back step by step through
+   q_{k+1} = q_k - alpha J^T (J J^T + lambda I)^-1 F, second derivatives of F included (Hessian-vector
+   products by central differences of the analytic gradient, step 1e-5 max(1, |q|_inf)). On the manifold
+   it equals project_vjp; off it, project_vjp is its first-order approximation.
+   q_in [d][ld] are the inputs of the forward project_batch call, status and iters (int8[n]) its outputs,
+   g_out and g_in [d][ld]; element type opts->dtype, with alpha, lambda and dtype as in that call (mode
+   must be stacked). The arithmetic is FP64 in both dtypes; the iterates are recomputed from q_in
+   (nothing is stored between the calls, O(iters^2) steps per configuration). Configurations whose
+   status is not MC_CONVERGED get g_in = 0; where a Gram matrix on the path is not positive definite,
+   g_in = NaN. */
+mc_status project_vjp_exact(const mc_problem* p, int64_t n, const void* q_in, int64_t ld,
+                            const int8_t* status, const int8_t* iters, const void* g_out, void* g_in,
+                            const mc_project_opts* opts, void* stream);
+
 /* interpolate_geodesics — the interpolation step of Alg. 2: geodesic g gets
    L_g = geo_offsets[g+1] - geo_offsets[g] interior points q_a + t_k (q_b - q_a),
    t_k = k / (L_g + 1), k = 1..L_g, written to q_out[:, geo_offsets[g] + k - 1].
@@ -296,7 +314,7 @@ mc_status mc_queue_counts(const mc_problem* p, uint32_t counts[4]);
 
 /* mc_set_kernel_timing — diagnostic: when on, project_batch brackets its main projection launch
    (the persistent kernel of the fused variant, all per-geodesic launches of the plain one) and
-   project_vjp its main VJP launch with HIP events on the call's stream; mc_last_kernel_ms waits for
+   project_vjp / project_vjp_exact their main VJP launch with HIP events on the call's stream; mc_last_kernel_ms waits for
    the last such call and returns the time between its two events (which = 0: projection, 1: VJP).
    The time excludes the queue reset and the FP64 and exact-check tail launches. Off by default;
    turning it on creates the events (not under stream capture). */

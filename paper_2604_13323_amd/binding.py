@@ -56,7 +56,7 @@ EXPORTS = ["mc_default_opts", "mc_problem_create", "mc_problem_destroy", "mc_pro
            "mc_problem_family", "mc_last_error", "project_batch", "check_batch", "project_vjp",
            "interpolate_geodesics", "path_length_grad", "mc_eval_residual_jacobian", "mc_fallback_count", "extend_batch",
            "mc_eval_condition", "mc_queue_counts", "mc_autotune_candidates", "mc_autotune_project", "mc_tuned_shape",
-           "mc_set_kernel_timing", "mc_last_kernel_ms", "project_batch_noalloc"]
+           "mc_set_kernel_timing", "mc_last_kernel_ms", "project_batch_noalloc", "project_vjp_exact"]
 
 
 def lib():
@@ -82,6 +82,7 @@ def lib():
     L.project_batch_noalloc.argtypes = L.project_batch.argtypes
     L.check_batch.argtypes = [P, I64, P, I64, ctypes.c_int, P, P, P]
     L.project_vjp.argtypes = [P, I64, P, I64, P, P, P, ctypes.POINTER(Opts), P]
+    L.project_vjp_exact.argtypes = [P, I64, P, I64, P, P, P, P, ctypes.POINTER(Opts), P]
     L.interpolate_geodesics.argtypes = [P, I32, P, P, I64, I64, P, I64, ctypes.c_int, P]
     L.path_length_grad.argtypes = [P, I64, P, I64, P, I32, P, P, ctypes.c_int, P]
     L.mc_eval_residual_jacobian.argtypes = [P, I64, P, I64, ctypes.c_int, P, P, P]
@@ -131,9 +132,9 @@ def _soa(q: torch.Tensor, d: int, name: str):
         raise McError(f"{name}: expected shape [{d}, N], got {tuple(q.shape)}")
     if not q.is_cuda:
         raise McError(f"{name}: expected a device tensor")
-    if q.stride(1) != 1:
+    if q.stride(1) != 1 and q.shape[1] > 1:
         raise McError(f"{name}: rows must be contiguous")
-    return q.shape[1], q.stride(0)
+    return q.shape[1], max(q.stride(0), q.shape[1])  # a single column's strides are arbitrary
 
 
 MODES = {"stacked": 0, "cyclic": 1}
@@ -291,6 +292,21 @@ class Problem:
                                  ctypes.byref(o), _stream()), "project_vjp")
         return g_in
 
+    def vjp_exact(self, q_in: torch.Tensor, status: torch.Tensor, iters: torch.Tensor, g_out: torch.Tensor,
+                  alpha=1.0, lam=0.0):
+        """Exact VJP of the projection map at the forward call's inputs q_in (with its status and iters):
+        g_in [d, n] with q_in's strides."""
+        n, ld = _soa(q_in, self.d, "vjp_exact")
+        if g_out.shape != q_in.shape or g_out.stride() != q_in.stride() or g_out.dtype != q_in.dtype:
+            g_out = g_out.to(q_in.dtype).contiguous()
+            q_in = q_in.contiguous()
+            ld = q_in.stride(0)
+        g_in = torch.empty_strided(q_in.shape, q_in.stride(), dtype=q_in.dtype, device=q_in.device)
+        o = make_opts(_dtype_code(q_in), alpha=alpha, lam=lam)
+        _check(lib().project_vjp_exact(self._h, n, _ptr(q_in), ld, _ptr(status), _ptr(iters), _ptr(g_out), _ptr(g_in),
+                                       ctypes.byref(o), _stream()), "project_vjp_exact")
+        return g_in
+
     def interpolate(self, endpoints: torch.Tensor, geo_offsets: torch.Tensor, total: int):
         """endpoints [d, 2 n_geo] (columns 2g, 2g+1 = the two ends); geo_offsets int32 device [n_geo + 1];
         total = geo_offsets[n_geo] (known to the caller, so nothing is read back from the device)."""
@@ -373,22 +389,34 @@ class Problem:
 
 class ProjectFn(torch.autograd.Function):
     """q_proj = P(q_in); backward gives (I - J^+ J) g at q_proj (implicit differentiation at
-    convergence). Only q_proj and status are saved: the backward kernel recomputes the
-    kinematics and the Jacobian."""
+    convergence; only q_proj and status are saved, the backward kernel recomputes the kinematics
+    and the Jacobian), or with exact=True the exact derivative of the map at q_in (q_in, status and
+    iters saved; the backward kernel replays the steps)."""
 
     @staticmethod
     def forward(ctx, q_in: torch.Tensor, problem: Problem, kwargs: dict):
+        kwargs = dict(kwargs)
+        exact = kwargs.pop("exact", False)
         r = problem.project(q_in.detach(), **kwargs)
         ctx.problem = problem
         ctx.cond = kwargs.get("cond", 1e6)
-        ctx.save_for_backward(r.q, r.status)
+        ctx.exact = exact
+        ctx.step = (kwargs.get("alpha", 1.0), kwargs.get("lam", 0.0))
+        if exact:
+            ctx.save_for_backward(q_in.detach(), r.status, r.iters)
+        else:
+            ctx.save_for_backward(r.q, r.status)
         ctx.mark_non_differentiable(r.status)
         return r.q, r.status
 
     @staticmethod
     def backward(ctx, g_q, g_status):
-        q, status = ctx.saved_tensors
-        g_in = ctx.problem.vjp(q, status, g_q.contiguous(), cond=ctx.cond)
+        if ctx.exact:
+            q_in, status, iters = ctx.saved_tensors
+            g_in = ctx.problem.vjp_exact(q_in, status, iters, g_q.contiguous(), alpha=ctx.step[0], lam=ctx.step[1])
+        else:
+            q, status = ctx.saved_tensors
+            g_in = ctx.problem.vjp(q, status, g_q.contiguous(), cond=ctx.cond)
         return g_in, None, None
 
 

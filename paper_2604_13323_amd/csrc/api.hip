@@ -1271,6 +1271,42 @@ mc_status project_vjp(const mc_problem* p, int64_t n, const void* q_proj, int64_
   return MC_OK;
 }
 
+mc_status project_vjp_exact(const mc_problem* p, int64_t n, const void* q_in, int64_t ld, const int8_t* status,
+                            const int8_t* iters, const void* g_out, void* g_in, const mc_project_opts* opts,
+                            void* stream) {
+  g_err.clear();
+  if (!p) return fail(MC_ERR_INVALID_ARG, "project_vjp_exact: null problem");
+  if (n < 0) return fail(MC_ERR_INVALID_ARG, "project_vjp_exact: n < 0");
+  mc_status st = check_opts(p, opts);
+  if (st != MC_OK) return st;
+  if (opts->mode != 0) return fail(MC_ERR_UNSUPPORTED, "project_vjp_exact: stacked mode only");
+  if (n == 0) return MC_OK;
+  if (!q_in || !status || !iters || !g_out || !g_in) return fail(MC_ERR_INVALID_ARG, "project_vjp_exact: null array");
+  if (ld < n) return fail(MC_ERR_INVALID_ARG, "project_vjp_exact: ld < n");
+  const FamilyOps* ops = ops_for(p->family, opts->dtype == MC_F64);
+  VjpxArgs a;
+  a.P = p->dev;
+  a.n = n;
+  a.q_in = q_in;
+  a.ld = ld;
+  a.status = status;
+  a.iters = iters;
+  a.g = g_out;
+  a.g_in = g_in;
+  a.alpha = opts->alpha;
+  a.lambda = opts->lambda;
+  a.h_rel = 1e-5;  // central-difference step of the Hessian-vector products, relative to max(1, |q|_inf)
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (p->timing && (e = hipEventRecord(p->tev[2], s)) != hipSuccess) return hip_fail(e, "project_vjp_exact: timing event");
+  if ((e = ops->vjp_exact(a, s)) != hipSuccess) return hip_fail(e, "project_vjp_exact: launch");
+  if (p->timing) {
+    if ((e = hipEventRecord(p->tev[3], s)) != hipSuccess) return hip_fail(e, "project_vjp_exact: timing event");
+    p->timed[1] = true;
+  }
+  return MC_OK;
+}
+
 mc_status interpolate_geodesics(const mc_problem* p, int32_t n_geo, const int32_t* geo_offsets, const void* endpoints,
                                 int64_t ld_e, int64_t total, void* q_out, int64_t ld_out, mc_dtype dtype, void* stream) {
   g_err.clear();

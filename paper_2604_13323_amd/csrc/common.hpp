@@ -250,6 +250,7 @@ struct QLds {
     return opaque(b[j * 64]);
   }
   __device__ __forceinline__ void set(int j, double v) const { base[j * 64] = v; }
+  __device__ __forceinline__ double operator[](int j) const { return at(j); }
 };
 // One configuration shared by the 64 lanes of a wave (D consecutive doubles; every lane reads the
 // same address, an LDS broadcast).

@@ -662,7 +662,8 @@ __device__ __forceinline__ void vjp64(const VjpArgs& a, int dof, int64_t i, cons
   typename Model::template SD<double> sd;
   double F[M], G[M * (M + 1) / 2], v[M], invd[M], kappa;
   Model::template residual<double>(q, C, F, sd);
-  Model::template gram<double, true>(q, C, sd, G, g, v);
+  Model::template gram<double, false>(q, C, sd, G, g, v);
+  Model::template jv<double>(q, C, sd, g, v);
   double maxd = 0.0;
   for (int r = 0; r < M; ++r) maxd = fmax(maxd, G[pidx(r, r)]);
   if (cholesky<Model, double>(G, invd, kappa, kFloorF64 * maxd)) {
@@ -697,7 +698,8 @@ __global__ void __launch_bounds__(64) k_vjp(VjpArgs a) {
     typename Model::template SD<float> sd;
     float F[M], G[M * (M + 1) / 2], v[M], invd[M], kappa;
     Model::template residual<float>(q, C, F, sd);
-    Model::template gram<float, true>(q, C, sd, G, g, v);
+    Model::template gram<float, false>(q, C, sd, G, g, v);
+    Model::template jv<float>(q, C, sd, g, v);
     if (cholesky<Model, float>(G, invd, kappa, kFloorF32) && double(kappa) <= a.cond_thr) {
       chol_solve<Model, float>(G, invd, v);
       Model::template jty<float>(q, C, sd, v, VjpOut<IO, float>{static_cast<IO*>(a.g_in) + i, a.ld, g, dof});
@@ -726,6 +728,183 @@ __global__ void __launch_bounds__(64) k_vjp_tail(VjpArgs a) {
     vjp_load<Model, IO, double>(a, dof, i, q, g);
     vjp64<Model, IO>(a, dof, i, q, g, C);
   }
+}
+
+// ---------------------------------------------------------------- exact VJP off the manifold
+// The derivative of the projection map itself (not only of the projection at its output), by
+// reverse mode through the Newton steps the forward pass took: with q_{k+1} = q_k - alpha J^T y,
+// y = G^-1 F, G = J J^T + lambda I, a cotangent w of q_{k+1} pulls back to
+//   w_k = w - alpha (J^T z + H(y.F) a - H(z.F) delta),   z = G^-1 J w, a = w - J^T z, delta = J^T y,
+// where H(c.F) v is the Hessian-vector product of the scalar c.F, the directional derivative of its
+// gradient J^T c along v (here by central differences of the analytic gradient in FP64). The output
+// cotangent is first projected on the tangent space at q_K, which is what one more Newton step at
+// the converged point does to it (the converged map's derivative there).
+struct VjpxArgs {
+  const DevProblem* P;
+  int64_t n;
+  const void* q_in;   // the forward pass's (unprojected) inputs
+  int64_t ld;
+  const int8_t* status;
+  const int8_t* iters;  // the forward pass's step counts
+  const void* g;
+  void* g_in;
+  double alpha, lambda, h_rel;
+};
+
+// A per-lane FP32 column of a [D][64] LDS tile.
+struct FLds {
+  using LP = __attribute__((address_space(3))) float*;
+  LP base;
+  __device__ __forceinline__ float operator[](int j) const { return base[j * 64]; }
+  __device__ __forceinline__ void set(int j, float v) const { base[j * 64] = v; }
+};
+// Sink of a J^T c walk that hands (j, value) to a callable.
+template <class S, class Fn>
+struct FnSink {
+  Fn fn;
+  struct Ref {
+    const FnSink* o;
+    int j;
+    __device__ __forceinline__ void operator=(S acc) const { o->fn(j, acc); }
+  };
+  __device__ __forceinline__ Ref operator[](int j) const { return Ref{this, j}; }
+};
+template <class S, class Fn>
+__device__ __forceinline__ FnSink<S, Fn> fn_sink(Fn fn) { return FnSink<S, Fn>{fn}; }
+// The iterate moved along a unit direction: coordinate j is q_j + t u_j / |u|.
+struct QShift {
+  QLds q;
+  FLds u;
+  double t;  // step already divided by |u|
+  __device__ __forceinline__ double at(int j) const { return q.at(j) + t * double(u[j]); }
+  template <class U>
+  __device__ __forceinline__ double at(int j, U dep) const { return q.at(j, dep) + t * double(u[j]); }
+};
+
+// FP64 Gram of J J^T + lambda I at q, factorised; false when it is not positive definite.
+template <class Model>
+__device__ __forceinline__ bool gram64(const QLds& q, const Consts& C, double lambda,
+                                       typename Model::template SD<double>& sd, double* F, double* G, double* invd) {
+  constexpr int M = Model::M;
+  Model::template residual<double>(q, C, F, sd);
+  Model::template gram<double, false>(q, C, sd, G, (const double*)nullptr, (double*)nullptr);
+  double maxd = 0.0, kappa;
+  for (int r = 0; r < M; ++r) {
+    G[pidx(r, r)] += lambda;
+    maxd = fmax(maxd, G[pidx(r, r)]);
+  }
+  return cholesky<Model, double>(G, invd, kappa, kFloorF64 * maxd);
+}
+
+// k FP64 Newton steps from the input (replaying the forward pass's path); false on a failure.
+template <class Model, class IO>
+__device__ __forceinline__ bool replay(const VjpxArgs& a, int dof, int64_t i, int k, const QLds& q, const Consts& C) {
+  constexpr int M = Model::M;
+  const IO* p = static_cast<const IO*>(a.q_in) + i;
+  for (int c = 0; c < Model::D; ++c) q.set(c, c < dof ? double(p[int64_t(c) * a.ld]) : 0.0);
+  for (int s = 0; s < k; ++s) {
+    typename Model::template SD<double> sd;
+    double F[M], G[M * (M + 1) / 2], invd[M];
+    if (!gram64<Model>(q, C, a.lambda, sd, F, G, invd)) return false;
+    chol_solve<Model, double>(G, invd, F);
+    const double al = a.alpha;
+    // the walk has read coordinate j when it reports column j, so the update can go in place
+    Model::template jty<double>(q, C, sd, F, fn_sink<double>([&](int j, double acc) { q.set(j, q.at(j) - al * acc); }));
+  }
+  return true;
+}
+
+// Accumulate coef * (gradient of c.F at q + t u/|u|) into w (the FP64 cotangent tile: the two
+// evaluations of a central difference add nearly cancelling terms of size |u| |grad| / 2h).
+template <class Model>
+__device__ __forceinline__ void grad_axpy(const QLds& q, const FLds& u, double t, const Consts& C, const double* c,
+                                          double coef, const QLds& w) {
+  constexpr int M = Model::M;
+  const QShift qs{q, u, t};
+  typename Model::template SD<double> sd;
+  double F[M];
+  Model::template residual<double>(qs, C, F, sd);
+  Model::template jty<double>(qs, C, sd, c, fn_sink<double>([&](int j, double acc) { w.set(j, w.at(j) + coef * acc); }));
+}
+
+template <class Model, class IO>
+__global__ void __launch_bounds__(64) k_vjp_exact(VjpxArgs a) {
+  constexpr int D = Model::D, M = Model::M;
+  extern __shared__ double smem[];
+  const Consts& C = consts_of(a.P);
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int dof = dof_of<Model>(C);
+  IO* out = static_cast<IO*>(a.g_in) + i;
+  if (a.status[i] != ST_CONVERGED) {
+    for (int c = 0; c < dof; ++c) out[int64_t(c) * a.ld] = IO(0);
+    return;
+  }
+  // tiles: the FP64 iterate and cotangent w (waves' tiles in turn), then the FP32 direction v (a, then delta)
+  const int nw = int(blockDim.x) >> 6, w0 = int(threadIdx.x) >> 6, l = int(threadIdx.x) & 63;
+  const QLds q{(QLds::LP)(smem + w0 * (D * 64) + l)};
+  const QLds w{(QLds::LP)(smem + (nw + w0) * (D * 64) + l)};
+  float* fb = reinterpret_cast<float*>(smem + 2 * nw * (D * 64));
+  const FLds v{(FLds::LP)(fb + w0 * (D * 64) + l)};
+  const int K = a.iters[i];
+  bool ok = replay<Model, IO>(a, dof, i, K, q, C);
+  {
+    const IO* pg = static_cast<const IO*>(a.g) + i;
+    for (int c = 0; c < D; ++c) w.set(c, c < dof ? double(pg[int64_t(c) * a.ld]) : 0.0);
+  }
+  // w <- (I - J^+ J) w at q_K
+  if (ok) {
+    typename Model::template SD<double> sd;
+    double F[M], G[M * (M + 1) / 2], invd[M], z[M];
+    ok = gram64<Model>(q, C, 0.0, sd, F, G, invd);
+    if (ok) {
+      Model::template jv<double>(q, C, sd, w, z);
+      chol_solve<Model, double>(G, invd, z);
+      Model::template jty<double>(q, C, sd, z, fn_sink<double>([&](int j, double acc) { w.set(j, w.at(j) - acc); }));
+    }
+  }
+  for (int k = K - 1; k >= 0 && ok; --k) {
+    ok = replay<Model, IO>(a, dof, i, k, q, C);
+    if (!ok) break;
+    typename Model::template SD<double> sd;
+    double F[M], G[M * (M + 1) / 2], invd[M], z[M];
+    ok = gram64<Model>(q, C, a.lambda, sd, F, G, invd);
+    if (!ok) break;
+    chol_solve<Model, double>(G, invd, F);  // F <- y
+    Model::template jv<double>(q, C, sd, w, z);
+    chol_solve<Model, double>(G, invd, z);  // z = G^-1 J w
+    const double al = a.alpha;
+    // v <- a = w - J^T z, then w <- (1 - alpha) w + alpha a (= w - alpha J^T z)
+    Model::template jty<double>(q, C, sd, z, fn_sink<double>([&](int j, double acc) {
+      const double wj = w.at(j), aj = wj - acc;
+      v.set(j, float(aj));
+      w.set(j, (1.0 - al) * wj + al * aj);
+    }));
+    double qn = 1.0, vn = 0.0;
+    for (int c = 0; c < D; ++c) {
+      qn = fmax(qn, fabs(q.at(c)));
+      vn += double(v[c]) * double(v[c]);
+    }
+    const double h = a.h_rel * qn;
+    vn = sqrt(vn);
+    // w -= alpha H(y.F) a: central difference of the gradient J^T y along a / |a|, times |a| / 2h
+    if (vn > 0.0) {
+      const double coef = al * vn / (2.0 * h);
+      grad_axpy<Model>(q, v, h / vn, C, F, -coef, w);
+      grad_axpy<Model>(q, v, -h / vn, C, F, coef, w);
+    }
+    // v <- delta = J^T y, then w += alpha H(z.F) delta
+    Model::template jty<double>(q, C, sd, F, fn_sink<double>([&](int j, double acc) { v.set(j, float(acc)); }));
+    double dn = 0.0;
+    for (int c = 0; c < D; ++c) dn += double(v[c]) * double(v[c]);
+    dn = sqrt(dn);
+    if (dn > 0.0) {
+      const double coef = al * dn / (2.0 * h);
+      grad_axpy<Model>(q, v, h / dn, C, z, coef, w);
+      grad_axpy<Model>(q, v, -h / dn, C, z, -coef, w);
+    }
+  }
+  for (int c = 0; c < dof; ++c) out[int64_t(c) * a.ld] = ok ? IO(w.at(c)) : IO(__builtin_nan(""));
 }
 
 // Diagnostic: residual (FP64) and dense Jacobian (step precision S) as the projection

@@ -558,6 +558,25 @@ struct Kin {
     });
   }
 
+  // v = J g pass (its own walk: accumulating v inside the Gram walk keeps g and v live next to the
+  // Gram and spills).
+  template <class S, class Q, class GV>
+  static __device__ __forceinline__ void jv(const Q& q, const Consts& P, const SD<S>& sd, GV g, S* v) {
+    const TP<S>& T = tp<S>(P);
+    for (int i = 0; i < M; ++i) v[i] = S(0);
+    S Qr[3] = {S(0), S(0), S(0)};
+    fk<S>(q, T, [&](auto J, const Rig<S>& X, const JP<S>& jp) {
+      constexpr int j = decltype(J)::value;
+      S col[M];
+      column<S, j>(X, jp, T, sd, Qr, col);
+      const S gj = g[j];
+      sfor<0, M>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (KI::rdep(i, j)) v[i] += col[i] * gj;
+      });
+    });
+  }
+
   // J^T y pass: out[j] = (J^T y)_j, assigned in joint order (out: an array, or a sink whose
   // operator[] returns an assignable proxy, so results can be streamed out of the walk).
   template <class S, uint32_t RM = ALL, class Q, class OUT>

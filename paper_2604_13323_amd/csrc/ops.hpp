@@ -24,6 +24,7 @@ struct FamilyOps {
   hipError_t (*check)(const CheckArgs& a, int minsd, hipStream_t s);
   hipError_t (*vjp)(const VjpArgs& a, hipStream_t s);
   hipError_t (*vjp_tail)(const VjpArgs& a, int grid, hipStream_t s);  // FP32 mode only
+  hipError_t (*vjp_exact)(const VjpxArgs& a, hipStream_t s);
   hipError_t (*eval_fj)(const DevProblem* P, int64_t n, const void* q, int64_t ld, void* F, void* J, hipStream_t s);
   hipError_t (*eval_cond)(const DevProblem* P, int64_t n, const void* q, int64_t ld, double lambda, void* kappa,
                           hipStream_t s);
@@ -53,6 +54,7 @@ struct OpsImpl {
   static hipError_t vjp_tail(const VjpArgs& a, int grid, hipStream_t s);
   static hipError_t check(const CheckArgs& a, int minsd, hipStream_t s);
   static hipError_t vjp(const VjpArgs& a, hipStream_t s);
+  static hipError_t vjp_exact(const VjpxArgs& a, hipStream_t s);
   static hipError_t eval_fj(const DevProblem* P, int64_t n, const void* q, int64_t ld, void* F, void* J, hipStream_t s);
   static hipError_t eval_cond(const DevProblem* P, int64_t n, const void* q, int64_t ld, double lambda, void* kappa,
                               hipStream_t s);
@@ -96,6 +98,7 @@ struct OpsImpl {
     if constexpr (Model::broad_in_residual) o.check_tail = &check_tail;
     o.check = &check;
     o.vjp = &vjp;
+    o.vjp_exact = &vjp_exact;
     o.eval_fj = &eval_fj;
     o.eval_cond = &eval_cond;
     o.persistent_blocks_per_cu = &persistent_blocks_per_cu;

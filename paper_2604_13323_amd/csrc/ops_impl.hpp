@@ -73,6 +73,12 @@ hipError_t OpsImpl<Model, IO, S>::vjp(const VjpArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 template <class Model, class IO, class S>
+hipError_t OpsImpl<Model, IO, S>::vjp_exact(const VjpxArgs& a, hipStream_t s) {
+  // LDS per wave: the FP64 iterate and cotangent tiles and the FP32 direction tile
+  hipLaunchKernelGGL((k_vjp_exact<Model, IO>), dim3(blocks_for(a.n, 64)), dim3(64), size_t(Model::D) * 64 * 20, s, a);
+  return hipGetLastError();
+}
+template <class Model, class IO, class S>
 hipError_t OpsImpl<Model, IO, S>::eval_fj(const DevProblem* P, int64_t n, const void* q, int64_t ld, void* F, void* J,
                                           hipStream_t s) {
   hipLaunchKernelGGL((k_eval_fj<Model, IO, S>), dim3(blocks_for(n, 64)), dim3(64), 0, s, P, n, q, ld, F, J);
@@ -120,10 +126,12 @@ int OpsImpl<Model, IO, S>::persistent_wide_blocks_per_cu() {
   template hipError_t O::check(const mc::CheckArgs&, int, hipStream_t);
 #define MC_INST_VJP(O) template hipError_t O::vjp(const mc::VjpArgs&, hipStream_t);
 #define MC_INST_VJP_TAIL(O) template hipError_t O::vjp_tail(const mc::VjpArgs&, int, hipStream_t);
+#define MC_INST_VJP_EXACT(O) template hipError_t O::vjp_exact(const mc::VjpxArgs&, hipStream_t);
 #define MC_INST_DIAG(O)                                                                              \
   template hipError_t O::eval_fj(const mc::DevProblem*, int64_t, const void*, int64_t, void*, void*, hipStream_t); \
   template hipError_t O::eval_cond(const mc::DevProblem*, int64_t, const void*, int64_t, double, void*, hipStream_t);
 // every launcher a single-block family uses (its cyclic mode is the stacked one), in one unit
 #define MC_INST_LIGHT_F32(O) MC_INST_PERSISTENT(O) MC_INST_PLAIN(O) MC_INST_TAIL(O) MC_INST_CHECK(O) \
-  MC_INST_VJP(O) MC_INST_VJP_TAIL(O) MC_INST_DIAG(O)
-#define MC_INST_LIGHT_F64(O) MC_INST_PERSISTENT(O) MC_INST_PLAIN(O) MC_INST_CHECK(O) MC_INST_VJP(O) MC_INST_DIAG(O)
+  MC_INST_VJP(O) MC_INST_VJP_TAIL(O) MC_INST_VJP_EXACT(O) MC_INST_DIAG(O)
+#define MC_INST_LIGHT_F64(O) MC_INST_PERSISTENT(O) MC_INST_PLAIN(O) MC_INST_CHECK(O) MC_INST_VJP(O) \
+  MC_INST_VJP_EXACT(O) MC_INST_DIAG(O)

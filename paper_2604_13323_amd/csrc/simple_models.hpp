@@ -64,6 +64,10 @@ struct SphereModel {
     G[0] = S(4) * (a * a + b * b + c * c);
     if constexpr (WITH_V) v[0] = S(2) * (a * g[0] + b * g[1] + c * g[2]);
   }
+  template <class S, class Q, class GV>
+  static __device__ __forceinline__ void jv(const Q& q, const Consts&, const SD<S>&, GV g, S* v) {
+    v[0] = S(2) * (S(q.at(0)) * g[0] + S(q.at(1)) * g[1] + S(q.at(2)) * g[2]);
+  }
   template <class S, uint32_t RM = ~uint32_t(0), class Q, class OUT>
   static __device__ __forceinline__ void jty(const Q& q, const Consts&, const SD<S>&, const S* y, OUT&& out) {
     for (int k = 0; k < 3; ++k) out[k] = S(2) * S(q.at(k)) * y[0];
@@ -138,6 +142,15 @@ struct LinearModel {
         for (int c = 0; c < D; ++c) acc += T.A[i][c] * g[c];
         v[i] = i < P.lin_m ? acc : S(0);
       }
+    }
+  }
+  template <class S, class Q, class GV>
+  static __device__ __forceinline__ void jv(const Q&, const Consts& P, const SD<S>&, GV g, S* v) {
+    const TP<S>& T = tp<S>(P);
+    for (int i = 0; i < M; ++i) {
+      S acc = S(0);
+      for (int c = 0; c < D; ++c) acc += T.A[i][c] * g[c];
+      v[i] = i < P.lin_m ? acc : S(0);
     }
   }
   template <class S, uint32_t RM = ~uint32_t(0), class Q, class OUT>
