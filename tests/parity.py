@@ -13,11 +13,12 @@ band when, along the oracle's FP64 path,
     near its cut locus at pi);
 and, only for runs with the divergence exit on, when the longest step is within 1% of max_step
 (the same ambiguity as the first criterion, for the MaxDistance threshold); and when the oracle's
-own outcome is unstable at the compared precision: projecting the input moved by a random
-perturbation of relative size 1e-7 (FP32 mode) or 1e-12 (FP64 mode), two draws, changes a status
-or moves the output by more than a quarter of the coordinate bound. (On the 7-DoF arm the min-norm
-iteration from random joint vectors takes steps of hundreds of radians on some paths, and there a
-1e-13 relative input change moves the oracle's own result by up to 100 rad.)
+own outcome is unstable at the compared precision: moving the input by a random vector of length
+rel * max(1, |q|_inf, longest step of the path), rel = 1e-7 in FP32 mode (the FP32 rounding of the
+largest step the GPU takes) or 1e-12 in FP64 mode, two draws, changes a status or moves the output
+by more than a quarter of the coordinate bound. (On the 7-DoF arm the min-norm iteration from
+random joint vectors takes steps of hundreds of radians on some paths, and there a 1e-13 relative
+input change moves the oracle's own result by up to 100 rad.)
 
 Coordinates are compared as angles where the constraint is 2 pi-periodic in them (revolute joints:
 F(q + 2 pi e_j) = F(q) exactly, so q and q + 2 pi e_j are one configuration), i.e. by the difference
@@ -48,7 +49,10 @@ CONV, MAXIT, SING, DIV, NONF = range(5)
 BAND_TOL_FACTOR = 2.0
 BAND_SIGMA_MIN = 1e-3
 BAND_ROTATION = 3.0
-UNSTABLE_REL = {4: 1e-7, 8: 1e-12}   # input perturbation by I/O element size (FP32, FP64 mode)
+# Relative size of the stability probe by I/O element size. FP32 mode: 3e-7, about five units of
+# FP32 rounding (2^-24 = 6e-8), which is the relative error FP32 forward kinematics over a chain of
+# 7-9 joints leaves in the Jacobian and hence in each step; FP64 mode: 1e-12.
+UNSTABLE_REL = {4: 3e-7, 8: 1e-12}
 
 
 def config_inputs(name: str, small: bool = True, max_geo: int | None = None):
@@ -81,15 +85,18 @@ def band_parts(path, iters, max_iter, max_step=0.0):
     return parts
 
 
-def unstable_mask(P, q, qo, st, tol, max_iter, rel, limit, draws=2, **kw):
-    """Configurations whose oracle outcome moves under an input perturbation of relative size rel:
-    a status change, or an output coordinate moving by more than `limit`."""
+def unstable_mask(P, q, qo, st, longest, tol, max_iter, rel, limit, draws=2, **kw):
+    """Configurations whose oracle outcome moves when the input moves by a random vector of length
+    rel * max(1, |q|_inf, longest step): a status change, or an output coordinate moving by more than
+    `limit` (angles compared modulo 2 pi)."""
     rng = np.random.default_rng(12345)
-    scale = np.maximum(1.0, np.abs(q).max(axis=1, keepdims=True)) / np.sqrt(q.shape[1])
+    size = rel * np.maximum(np.maximum(1.0, np.abs(q).max(axis=1)), longest)
     bad = np.zeros(len(q), bool)
     for _ in range(draws):
-        q2, st2, _, _ = P.project(q + rel * scale * rng.standard_normal(q.shape), tol=tol, max_iter=max_iter, **kw)
-        bad |= (st2 != st) | (np.abs(q2 - qo).max(axis=1) > limit)
+        u = rng.standard_normal(q.shape)
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        q2, st2, _, _ = P.project(q + size[:, None] * u, tol=tol, max_iter=max_iter, **kw)
+        bad |= (st2 != st) | (coord_error(P, q2, qo) > limit)
     return bad
 
 
@@ -100,8 +107,8 @@ def oracle_run(P, q, tol, max_iter, max_step=0.0, mode="stacked", alpha=1.0, lam
                                    alpha=alpha, lam=lam)
     parts = band_parts(pi, it, max_iter, max_step)
     if unstable is not None:
-        parts["unstable"] = unstable_mask(P, q, qo, st, tol, max_iter, unstable[0], unstable[1], max_step=max_step,
-                                          mode=mode, alpha=alpha, lam=lam)
+        parts["unstable"] = unstable_mask(P, q, qo, st, pi[:, 1], tol, max_iter, unstable[0], unstable[1],
+                                          max_step=max_step, mode=mode, alpha=alpha, lam=lam)
     band = np.zeros(len(q), bool)
     for m in parts.values():
         band |= m
@@ -177,7 +184,11 @@ def compare(P, q, r, tol, max_iter, qtol, max_band=0.25, max_step=0.0, mode="sta
         assert it_bad.sum() == 0, f"iteration mismatch on {it_bad.sum()} configs outside the band, e.g. {np.where(it_bad)[0][:5]}"
     err = coord_error(P, gq, qo)
     stats["same_modulo_full_turns"] = int(((np.abs(gq - qo).max(axis=1) > qtol) & (err <= qtol) & both).sum())
-    assert (err[bo] <= qtol).all(), f"q mismatch outside the band: max {err[bo].max():.3e} on {np.sum(err[bo] > qtol)} configs"
+    badq = bo & (err > qtol)
+    if badq.any():
+        dump(q=q, gq=gq, qo=qo, gst=gst, st=st, git=git, it=it, path=o["path"], band=band)
+    assert not badq.any(), (f"q mismatch outside the band: max {err[bo].max():.3e} on {badq.sum()} configs, "
+                            f"e.g. idx {np.where(badq)[0][:8]}")
     # band, tolerance criterion only, same iteration count: as strict as outside
     others = np.zeros(len(q), bool)
     for k, m in o["parts"].items():
@@ -205,6 +216,16 @@ def compare(P, q, r, tol, max_iter, qtol, max_band=0.25, max_step=0.0, mode="sta
         assert (Fg < bound).all(), f"converged GPU output off the manifold: ||F|| {Fg[worst]:.3e} > {bound[worst]:.3e}"
         stats["max_resid_at_output"] = float(Fg.max())
     return stats
+
+
+def dump(**arrays):
+    """Keep the arrays of a failed comparison for offline analysis when PARITY_DUMP_DIR is set."""
+    import os
+    import time
+    d = os.environ.get("PARITY_DUMP_DIR")
+    if d:
+        os.makedirs(d, exist_ok=True)
+        np.savez_compressed(os.path.join(d, f"parity_fail_{time.time_ns()}.npz"), **arrays)
 
 
 def to_dev(q: np.ndarray, dtype):

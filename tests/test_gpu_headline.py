@@ -7,7 +7,7 @@ larger than the batch."""
 import numpy as np
 import pytest
 
-from parity import CONV, compare, config_inputs, from_dev, oracle_run, to_dev
+from parity import CONV, UNSTABLE_REL, compare, config_inputs, from_dev, oracle_run, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -28,7 +28,7 @@ def headline(mc):
     projected by the oracle, and the oracle's projection of every configuration."""
     sc, P, q, offs, tol, mi = config_inputs("c3", small=False)
     assert len(q) == 65536
-    return dict(sc=sc, P=P, q=q, offs=offs, tol=tol, mi=mi, orc=oracle_run(P, q, tol, mi, unstable=(1e-7, 2.5e-5)),
+    return dict(sc=sc, P=P, q=q, offs=offs, tol=tol, mi=mi, orc=oracle_run(P, q, tol, mi, unstable=(UNSTABLE_REL[4], 2.5e-5)),
                 G=mc.Problem(sc.to_blob()), q32=to_dev(q, torch.float32))
 
 
@@ -158,10 +158,12 @@ def test_geo_ok_is_the_and_over_each_geodesic(mc):
 def test_condition_estimate_matches_oracle(mc, name):
     """kappa_est = (max L_ii / min L_ii)^2 of the kernels' factorisation of J J^T against the
     oracle's FP64 Cholesky at the same configurations: FP64 mode to 1e-9 relative; FP32 mode within
-    what FP32 kinematics and Gram rounding allow (relative 1e-5 kappa: FP32 forward kinematics put
-    ~1e-6 relative error into the Gram entries, and the Schur complements of the factorisation
-    amplify it by up to kappa), and the FP64-fallback decision at 1e6 agrees outside a factor 4
-    around the threshold."""
+    what FP32 kinematics and Gram rounding allow. The Gram entries carry a few units of FP32 rounding
+    relative to ||J||^2, and a pivot of the factorisation, at least sigma_min(J)^2, moves by that
+    much, so the relative error of kappa_est is bounded by a multiple of kappa_2 = (sigma_max /
+    sigma_min)^2 of J, which can be far larger than kappa_est itself on a badly scaled Gram: 1e-6
+    kappa_2 + 1e-4. The FP64-fallback decision at 1e6 agrees outside a factor 4 around the
+    threshold."""
     sc, P, q, offs, tol, mi = config_inputs(name, small=True, max_geo=16)
     G = mc.Problem(sc.to_blob())
     for dt in (torch.float64, torch.float32):
@@ -177,7 +179,8 @@ def test_condition_estimate_matches_oracle(mc, name):
         else:
             ok = fin & (ke < 1e5)
             rel = np.abs(k[ok] / ke[ok] - 1.0)
-            assert (rel <= 1e-5 * ke[ok] + 1e-4).all(), rel.max()
+            worst = np.argmax(rel - 1e-6 * k2[ok])
+            assert (rel <= 1e-6 * k2[ok] + 1e-4).all(), (rel[worst], ke[ok][worst], k2[ok][worst])
             sure = fin & ((ke < 0.25e6) | (ke > 4e6))
             assert ((k[sure] > 1e6) == (ke[sure] > 1e6)).all()
         print(name, dt, "kappa_est range", np.nanmin(ke), np.nanmax(ke[fin]), "above 1e6:", int((ke > 1e6).sum()))
