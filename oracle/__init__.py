@@ -154,8 +154,11 @@ class Problem:
         g = np.ascontiguousarray(g, np.float64).reshape(-1, self.d)
         gi = np.zeros_like(q0)
         st = np.zeros(len(q0), np.int8)
-        assert lib().oracle_vjp_exact(*self._args(), len(q0), _p(q0), _p(g), _p(gi), float(tol), int(max_iter),
-                                      float(alpha), float(lam), _p(st), threads) == 0
+        rc = lib().oracle_vjp_exact(*self._args(), len(q0), _p(q0), _p(g), _p(gi), float(tol), int(max_iter),
+                                    float(alpha), float(lam), _p(st), threads)
+        if rc == 3:
+            raise NotImplementedError("oracle: no dual-number derivative for scenes with bounded or polygon rows")
+        assert rc == 0
         return gi, st
 
     def kappa_est(self, q, lam=0.0, threads: int = 0):

@@ -15,10 +15,17 @@
 //     d <- F(q); stop when ||d|| < eps; step = alpha J^T (J J^T + lambda I)^-1 d;
 //     optional divergence exit when ||step|| > MaxDistance; q <- q - step.
 //   Pose error of Eq. 1 (TSR, T_w^0 = T_ref, grasp offset folded into the frame),
-//   relative pose error of Eq. 2, the humanoid CoM constraint of the Digit
-//   constraint figure (equality to the support-polygon centroid), and the SO(3)
-//   log map with the first-order Taylor form of 1/sinc near zero (Sec. IV-A,
-//   the paragraph on the tracing compiler).
+//   optionally with finite bounds B^w (Sec. III: a component inside its interval
+//   contributes zero, outside it contributes its excess over the nearer bound),
+//   relative pose error of Eq. 2, the humanoid constraints of the Digit
+//   constraint figure (CoM equal to the support-polygon centroid, or the CoM
+//   minus its nearest point of the support polygon, zero inside; closed-linkage
+//   rod lengths), and the SO(3) log map with the first-order Taylor form of
+//   1/sinc near zero (Sec. IV-A, the paragraph on the tracing compiler).
+//   Scenes with rows that vanish on a region (bounded TSR components, the
+//   polygon distance) have Jacobians of varying rank; there the step is the
+//   pseudo-inverse solution J^+ F from a full SVD (one-sided Jacobi with the
+//   right rotations accumulated), the plain definition of the minimum-norm step.
 //   Collision check of the projected configurations (Sec. IV-A, the validation
 //   that follows projection in the extend step): robot spheres vs obstacle
 //   spheres, strict overlap ||c_i - o_j||^2 < (r_i + r_j)^2, brute force over
@@ -44,13 +51,14 @@
 namespace {
 
 // ------------------------------------------------------------------ scene
-enum { F_SPHERE = 0, F_LINEAR = 1, F_PLANAR2 = 2, F_ARM7_AXIS = 3, F_DUAL14_REL = 4, F_HUMANOID36 = 5 };
-enum { B_POSE = 0, B_REL = 1, B_AXIS = 2, B_COM = 3, B_SPHERE = 4, B_LINEAR = 5 };
+enum { B_POSE = 0, B_REL = 1, B_AXIS = 2, B_COM = 3, B_SPHERE = 4, B_LINEAR = 5, B_DIST = 6, B_HULL = 7 };
+constexpr int kExt = 16;         // block data doubles of blob version 2
+constexpr int kPoseBounded = 1;  // POSE block aux flag
 enum { ST_CONVERGED = 0, ST_MAX_ITER = 1, ST_SINGULAR = 2, ST_DIVERGED = 3, ST_NONFINITE = 4 };
 
 struct JointSpec { int parent, type, axis; double R[9], p[3]; };
 struct FrameSpec { int link; double R[9], p[3]; };
-struct BlockSpec { int type, fa, fb, mask, ref_from_qref; double R[9], p[3], target[3]; };
+struct BlockSpec { int type, fa, fb, mask, ref_from_qref, aux; double R[9], p[3], target[3], ext[kExt]; };
 struct SphereSpec { int link; double c[3], r; };
 
 struct Scene {
@@ -81,8 +89,8 @@ struct Reader {
 int block_rows(const BlockSpec& b, const Scene& s) {
   switch (b.type) {
     case B_POSE: case B_REL: { int r = 0; for (int i = 0; i < 6; ++i) r += (b.mask >> i) & 1; return r; }
-    case B_AXIS: case B_COM: return 2;
-    case B_SPHERE: return 1;
+    case B_AXIS: case B_COM: case B_HULL: return 2;
+    case B_SPHERE: case B_DIST: return 1;
     case B_LINEAR: return s.m;
   }
   return -1;
@@ -92,7 +100,8 @@ bool parse(const void* blob, size_t nbytes, Scene& s) {
   Reader r{static_cast<const unsigned char*>(blob), nbytes};
   int32_t h[16];
   for (int i = 0; i < 16; ++i) h[i] = r.get<int32_t>();
-  if (!r.ok || h[0] != 0x5343434D || h[1] != 1) return false;
+  if (!r.ok || h[0] != 0x5343434D || (h[1] != 1 && h[1] != 2)) return false;
+  const bool v2 = h[1] == 2;
   s.family = h[2]; s.d = h[3]; s.m = h[4];
   int nj = h[5], nf = h[6], nb = h[7], ns = h[8], no = h[9], has_qref = h[10], has_lin = h[11];
   if (s.d <= 0 || s.m <= 0 || s.m > s.d || nj < 0 || nf < 0 || nb <= 0 || ns < 0 || no < 0) return false;
@@ -108,8 +117,10 @@ bool parse(const void* blob, size_t nbytes, Scene& s) {
   s.blocks.resize(nb);
   for (auto& b : s.blocks) {
     b.type = r.get<int32_t>(); b.fa = r.get<int32_t>(); b.fb = r.get<int32_t>(); b.mask = r.get<int32_t>();
-    b.ref_from_qref = r.get<int32_t>(); r.get<int32_t>();
+    b.ref_from_qref = r.get<int32_t>(); b.aux = r.get<int32_t>();
     r.getd(b.R, 9); r.getd(b.p, 3); r.getd(b.target, 3);
+    for (int k = 0; k < kExt; ++k) b.ext[k] = 0.0;
+    if (v2) r.getd(b.ext, kExt);
   }
   s.spheres.resize(ns);
   for (auto& sp : s.spheres) { sp.link = r.get<int32_t>(); r.get<int32_t>(); r.getd(sp.c, 3); sp.r = r.get<double>(); }
@@ -129,7 +140,18 @@ bool parse(const void* blob, size_t nbytes, Scene& s) {
     int k = block_rows(b, s);
     if (k < 0) return false;
     if ((b.type == B_POSE || b.type == B_AXIS) && (b.fa < 0 || b.fa >= nf)) return false;
-    if (b.type == B_REL && (b.fa < 0 || b.fa >= nf || b.fb < 0 || b.fb >= nf)) return false;
+    if ((b.type == B_REL || b.type == B_DIST) && (b.fa < 0 || b.fa >= nf || b.fb < 0 || b.fb >= nf)) return false;
+    if (b.type == B_POSE && (b.aux & kPoseBounded))
+      for (int c = 0; c < 6; ++c) if (!(b.ext[c] <= b.ext[6 + c])) return false;
+    if (b.type == B_HULL) {  // a convex polygon, counter-clockwise
+      if (b.aux < 3 || b.aux > kExt / 2 || nj == 0) return false;
+      for (int i = 0; i < b.aux; ++i) {
+        const double* a = b.ext + 2 * i;
+        const double* c = b.ext + 2 * ((i + 1) % b.aux);
+        const double* e = b.ext + 2 * ((i + 2) % b.aux);
+        if (!((c[0] - a[0]) * (e[1] - c[1]) - (c[1] - a[1]) * (e[0] - c[0]) > 0.0)) return false;
+      }
+    }
     if (b.ref_from_qref && !has_qref) return false;
     if (b.type == B_LINEAR && !has_lin) return false;
     if (b.type == B_SPHERE && s.d != 3) return false;
@@ -239,26 +261,86 @@ template <class T> void so3_log(const T R[3][3], T w[3], double* theta = nullptr
   if (theta) *theta = std::atan2(std::sqrt(val(s2)), val(c));
 }
 
+// Excess of a bounded component over its interval [lo, hi]: zero inside (a constant: no
+// derivative), v - hi above it, v - lo below it (TSR bounds B^w, Sec. III).
+template <class T> T bound_excess(T v, double lo, double hi) {
+  if (val(v) > hi) return v - T(hi);
+  if (val(v) < lo) return v - T(lo);
+  return T(0.0);
+}
+
 // error rows [t; log(R)] of a pose error transform, selected by a 6-bit mask; max_theta (nullable)
 // is raised to the error's rotation angle
-template <class T> int pose_rows(const Tf<T>& e, int mask, T* out, double* max_theta = nullptr) {
+template <class T> int pose_rows(const Tf<T>& e, int mask, T* out, double* max_theta = nullptr,
+                                  const double* bounds = nullptr) {
   T w[3];
   double th = 0.0;
   so3_log(e.R, w, &th);
   if (max_theta && th > *max_theta) *max_theta = th;
   T all[6] = {e.p[0], e.p[1], e.p[2], w[0], w[1], w[2]};
   int r = 0;
-  for (int i = 0; i < 6; ++i) if ((mask >> i) & 1) out[r++] = all[i];
+  for (int i = 0; i < 6; ++i)
+    if ((mask >> i) & 1) out[r++] = bounds ? bound_excess(all[i], bounds[i], bounds[6 + i]) : all[i];
   return r;
 }
 
+// Centre-of-mass xy of the robot: sum of m_l c_l over the links with mass, divided by their mass.
+template <class T> void com_xy(const Scene& s, const std::vector<Tf<T>>& link, T* out) {
+  T cx = T(0.0), cy = T(0.0);
+  double M = 0.0;
+  for (size_t l = 0; l < s.joints.size(); ++l) {
+    double ml = s.mass[l];
+    if (ml == 0.0) continue;
+    const auto& L = link[l];
+    const auto& c = s.com[l];
+    T wx = L.R[0][0] * T(c[0]) + L.R[0][1] * T(c[1]) + L.R[0][2] * T(c[2]) + L.p[0];
+    T wy = L.R[1][0] * T(c[0]) + L.R[1][1] * T(c[1]) + L.R[1][2] * T(c[2]) + L.p[1];
+    cx = cx + T(ml) * wx;
+    cy = cy + T(ml) * wy;
+    M += ml;
+  }
+  out[0] = cx / T(M);
+  out[1] = cy / T(M);
+}
+
+// Distance rows of a point x against a convex polygon V (nv counter-clockwise xy vertices): zero
+// when x is inside or on the boundary, else x minus its nearest point of the boundary, found edge
+// by edge (projection onto each edge's segment, the parameter clamped to its ends).
+template <class T> void polygon_rows(const double* V, int nv, const T* x, T* out) {
+  bool inside = true;
+  for (int i = 0; i < nv; ++i) {
+    const double* a = V + 2 * i;
+    const double* b = V + 2 * ((i + 1) % nv);
+    const double cr = (b[0] - a[0]) * (val(x[1]) - a[1]) - (b[1] - a[1]) * (val(x[0]) - a[0]);
+    if (cr < 0.0) inside = false;
+  }
+  if (inside) { out[0] = T(0.0); out[1] = T(0.0); return; }
+  double best = INFINITY;
+  T nx = T(0.0), ny = T(0.0);
+  for (int i = 0; i < nv; ++i) {
+    const double* a = V + 2 * i;
+    const double* b = V + 2 * ((i + 1) % nv);
+    const double ex = b[0] - a[0], ey = b[1] - a[1];
+    T t = ((x[0] - T(a[0])) * T(ex) + (x[1] - T(a[1])) * T(ey)) / T(ex * ex + ey * ey);
+    if (val(t) < 0.0) t = T(0.0);
+    if (val(t) > 1.0) t = T(1.0);
+    const T cx = T(a[0]) + t * T(ex), cy = T(a[1]) + t * T(ey);
+    const double dx = val(x[0]) - val(cx), dy = val(x[1]) - val(cy);
+    if (dx * dx + dy * dy < best) { best = dx * dx + dy * dy; nx = cx; ny = cy; }
+  }
+  out[0] = x[0] - nx;
+  out[1] = x[1] - ny;
+}
+
 // Targets of pose blocks (constant, FP64). For blocks flagged ref_from_qref the
-// target is the pose (POSE) or relative pose (REL) at the reference configuration.
-struct Targets { std::vector<Tf<double>> T; };
+// target is the pose (POSE) or relative pose (REL) at the reference configuration, and the
+// rod length (DIST) the distance of its two frame origins there.
+struct Targets { std::vector<Tf<double>> T; std::vector<double> L; };
 
 Targets make_targets(const Scene& s) {
   Targets t;
   t.T.resize(s.blocks.size());
+  t.L.assign(s.blocks.size(), 0.0);
   std::vector<Tf<double>> link;
   if (!s.qref.empty() && !s.joints.empty()) forward_kinematics<double>(s, s.qref.data(), link);
   for (size_t k = 0; k < s.blocks.size(); ++k) {
@@ -266,6 +348,15 @@ Targets make_targets(const Scene& s) {
     if (b.ref_from_qref && b.type == B_POSE) t.T[k] = frame_pose(s, link, b.fa);
     else if (b.ref_from_qref && b.type == B_REL) t.T[k] = tf_mul(tf_inv(frame_pose(s, link, b.fa)), frame_pose(s, link, b.fb));
     else t.T[k] = tf_const<double>(b.R, b.p);
+    if (b.type == B_DIST) {
+      t.L[k] = b.target[0];
+      if (b.ref_from_qref) {
+        const Tf<double> pa = frame_pose(s, link, b.fa), pb = frame_pose(s, link, b.fb);
+        double d2 = 0.0;
+        for (int i = 0; i < 3; ++i) d2 += (pb.p[i] - pa.p[i]) * (pb.p[i] - pa.p[i]);
+        t.L[k] = std::sqrt(d2);
+      }
+    }
   }
   return t;
 }
@@ -281,8 +372,23 @@ template <class T> void residual(const Scene& s, const Targets& tg, const T* q, 
     Tf<T> Tref;
     for (int i = 0; i < 3; ++i) { for (int c = 0; c < 3; ++c) Tref.R[i][c] = T(tg.T[k].R[i][c]); Tref.p[i] = T(tg.T[k].p[i]); }
     switch (b.type) {
-      case B_POSE: {  // Eq. 1: T_err = T_ref^-1 T_frame
-        r += pose_rows(tf_mul(tf_inv(Tref), frame_pose(s, link, b.fa)), b.mask, F + r, max_theta);
+      case B_POSE: {  // Eq. 1: T_err = T_ref^-1 T_frame, minus the bounds B^w where the block has them
+        const double* bnd = (b.aux & kPoseBounded) ? b.ext : nullptr;
+        r += pose_rows(tf_mul(tf_inv(Tref), frame_pose(s, link, b.fa)), b.mask, F + r, max_theta, bnd);
+        break;
+      }
+      case B_DIST: {  // closed linkage: distance of the two frame origins minus the rod length
+        const Tf<T> pa = frame_pose(s, link, b.fa), pb = frame_pose(s, link, b.fb);
+        T d2 = T(0.0);
+        for (int i = 0; i < 3; ++i) d2 = d2 + (pb.p[i] - pa.p[i]) * (pb.p[i] - pa.p[i]);
+        F[r++] = sqrt(d2) - T(tg.L[k]);
+        break;
+      }
+      case B_HULL: {  // CoM xy minus its nearest point of the support polygon (zero inside)
+        T x[2];
+        com_xy(s, link, x);
+        polygon_rows(b.ext, b.aux, x, F + r);
+        r += 2;
         break;
       }
       case B_REL: {   // Eq. 2: T_err = T_ref^-1 (T_a^-1 T_b)
@@ -297,21 +403,10 @@ template <class T> void residual(const Scene& s, const Targets& tg, const T* q, 
         break;
       }
       case B_COM: {   // centre of mass xy minus target
-        T cx = T(0.0), cy = T(0.0);
-        double M = 0.0;
-        for (size_t l = 0; l < s.joints.size(); ++l) {
-          double ml = s.mass[l];
-          if (ml == 0.0) continue;
-          const auto& L = link[l];
-          const auto& c = s.com[l];
-          T wx = L.R[0][0] * T(c[0]) + L.R[0][1] * T(c[1]) + L.R[0][2] * T(c[2]) + L.p[0];
-          T wy = L.R[1][0] * T(c[0]) + L.R[1][1] * T(c[1]) + L.R[1][2] * T(c[2]) + L.p[1];
-          cx = cx + T(ml) * wx;
-          cy = cy + T(ml) * wy;
-          M += ml;
-        }
-        F[r++] = cx / T(M) - T(b.target[0]);
-        F[r++] = cy / T(M) - T(b.target[1]);
+        T x[2];
+        com_xy(s, link, x);
+        F[r++] = x[0] - T(b.target[0]);
+        F[r++] = x[1] - T(b.target[1]);
         break;
       }
       case B_SPHERE: {
@@ -464,6 +559,107 @@ bool descent_step(int m, int d, const double* J, const double* F, double lambda,
 
 double norm2(const double* x, int n) { double a = 0; for (int i = 0; i < n; ++i) a += x[i] * x[i]; return std::sqrt(a); }
 
+// Scenes whose rows vanish on a region (bounded TSR components, the polygon distance): the rank of
+// J varies there, so the step is taken by pinv_step.
+bool has_piecewise_rows(const Scene& s) {
+  for (const auto& b : s.blocks)
+    if (b.type == B_HULL || (b.type == B_POSE && (b.aux & kPoseBounded))) return true;
+  return false;
+}
+
+constexpr double kRankCut = 1e-10;  // singular values at or below this fraction of the largest count as zero
+
+// Full SVD of J (m x d row-major, m <= d) by one-sided Jacobi on J^T: the rotations that make the
+// columns of A = J^T orthogonal are accumulated in V (m x m, column-major), so J^T V = A with
+// orthogonal columns, sigma_k = ||A_k|| and J = V diag(sigma) U^T with U_k = A_k / sigma_k.
+void jacobi_svd(int m, int d, const double* J, std::vector<double>& A, std::vector<double>& V, std::vector<double>& sv) {
+  A.assign(size_t(d) * m, 0.0);
+  V.assign(size_t(m) * m, 0.0);
+  sv.assign(m, 0.0);
+  for (int i = 0; i < m; ++i) {
+    for (int j = 0; j < d; ++j) A[size_t(i) * d + j] = J[size_t(i) * d + j];
+    V[size_t(i) * m + i] = 1.0;
+  }
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < m - 1; ++p) {
+      for (int r = p + 1; r < m; ++r) {
+        double* ap = A.data() + size_t(p) * d;
+        double* ar = A.data() + size_t(r) * d;
+        double alpha = 0, beta = 0, gamma = 0;
+        for (int i = 0; i < d; ++i) { alpha += ap[i] * ap[i]; beta += ar[i] * ar[i]; gamma += ap[i] * ar[i]; }
+        if (gamma == 0.0 || alpha == 0.0 || beta == 0.0) continue;
+        const double rel = std::fabs(gamma) / std::sqrt(alpha * beta);
+        if (!(rel > 1e-15)) continue;
+        off = std::max(off, rel);
+        const double zeta = (beta - alpha) / (2.0 * gamma);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
+        for (int i = 0; i < d; ++i) {
+          const double x = ap[i], y = ar[i];
+          ap[i] = c * x - sn * y;
+          ar[i] = sn * x + c * y;
+        }
+        double* vp = V.data() + size_t(p) * m;
+        double* vr = V.data() + size_t(r) * m;
+        for (int i = 0; i < m; ++i) {
+          const double x = vp[i], y = vr[i];
+          vp[i] = c * x - sn * y;
+          vr[i] = sn * x + c * y;
+        }
+      }
+    }
+    if (off < 1e-15) break;
+  }
+  for (int k = 0; k < m; ++k) sv[k] = norm2(A.data() + size_t(k) * d, d);
+}
+
+// Pseudo-inverse step: delta = J^+ F (lambda = 0) or the damped J^T (J J^T + lambda I)^-1 F, from the
+// SVD: delta = sum_k A_k (V_k^T F) / (sigma_k^2 + lambda) over the singular values above kRankCut
+// sigma_max. Returns false when J = 0 while F is not. smin_out (nullable) receives the smallest
+// singular value above the cut.
+bool pinv_step(int m, int d, const double* J, const double* F, double lambda, double* delta, double* smin_out = nullptr) {
+  std::vector<double> A, V, sv;
+  jacobi_svd(m, d, J, A, V, sv);
+  double smax = 0.0;
+  for (double x : sv) smax = std::max(smax, x);
+  for (int j = 0; j < d; ++j) delta[j] = 0.0;
+  if (!(smax > 0.0)) {  // J = 0: no step; singular unless every row is zero too (a block all inside)
+    if (smin_out) *smin_out = INFINITY;
+    for (int i = 0; i < m; ++i) if (F[i] != 0.0) return false;
+    return true;
+  }
+  double smin = INFINITY;
+  for (int k = 0; k < m; ++k) {
+    if (!(sv[k] > kRankCut * smax)) continue;
+    smin = std::min(smin, sv[k]);
+    double vf = 0.0;
+    for (int i = 0; i < m; ++i) vf += V[size_t(k) * m + i] * F[i];
+    const double c = vf / (sv[k] * sv[k] + lambda);
+    for (int j = 0; j < d; ++j) delta[j] += A[size_t(k) * d + j] * c;
+  }
+  if (smin_out) *smin_out = smin;
+  return true;
+}
+
+// g - P g with P the orthogonal projector onto the row space of J (the span of the U_k above the cut).
+void pinv_tangent(int m, int d, const double* J, const double* g, double* out) {
+  std::vector<double> A, V, sv;
+  jacobi_svd(m, d, J, A, V, sv);
+  double smax = 0.0;
+  for (double x : sv) smax = std::max(smax, x);
+  for (int j = 0; j < d; ++j) out[j] = g[j];
+  for (int k = 0; k < m; ++k) {
+    if (!(sv[k] > kRankCut * smax)) continue;
+    const double* a = A.data() + size_t(k) * d;
+    double ag = 0.0;
+    for (int j = 0; j < d; ++j) ag += a[j] * g[j];
+    const double c = ag / (sv[k] * sv[k]);
+    for (int j = 0; j < d; ++j) out[j] -= a[j] * c;
+  }
+}
+
+
 // ------------------------------------------------- the iteration as a differentiable map
 // The same Householder QR and min-norm / damped step as above, over any scalar T, so the
 // Newton iteration can run on dual numbers and carry the derivative of the projection map along.
@@ -594,6 +790,7 @@ void path_note_test(double* path, double nF, double tol, double theta) {
 void project_one_cyclic(const Scene& s, const Targets& tg, const Opts& o, const double* q0, double* q,
                         int8_t* status, int32_t* iters, double* resid, double* path) {
   const int d = s.d, m = s.m;
+  const bool pw = has_piecewise_rows(s);
   std::vector<double> F(m), J(size_t(m) * d), delta(d), qs(d);
   for (int j = 0; j < d; ++j) q[j] = q0[j];
   path_init(path);
@@ -617,7 +814,9 @@ void project_one_cyclic(const Scene& s, const Targets& tg, const Opts& o, const 
       jacobian(s, tg, q, J.data());
       if (!all_finite(J.data() + size_t(r0) * d, mb * d)) { *status = ST_NONFINITE; return; }
       double smin = 0.0;
-      const bool ok = descent_step(mb, d, J.data() + size_t(r0) * d, F.data() + r0, o.lambda, delta.data(), &smin);
+      const double* Jb = J.data() + size_t(r0) * d;
+      const bool ok = pw ? pinv_step(mb, d, Jb, F.data() + r0, o.lambda, delta.data(), &smin)
+                         : descent_step(mb, d, Jb, F.data() + r0, o.lambda, delta.data(), &smin);
       if (path) path[0] = std::min(path[0], smin);
       if (!ok) { *status = ST_SINGULAR; return; }
       for (int j = 0; j < d; ++j) delta[j] *= o.alpha;
@@ -642,6 +841,7 @@ void project_one_cyclic(const Scene& s, const Targets& tg, const Opts& o, const 
 void project_one(const Scene& s, const Targets& tg, const Opts& o, const double* q0, double* q,
                  int8_t* status, int32_t* iters, double* resid, double* path = nullptr) {
   const int d = s.d, m = s.m;
+  const bool pw = has_piecewise_rows(s);
   std::vector<double> F(m), J(size_t(m) * d), delta(d);
   for (int j = 0; j < d; ++j) q[j] = q0[j];
   path_init(path);
@@ -658,7 +858,8 @@ void project_one(const Scene& s, const Targets& tg, const Opts& o, const double*
     jacobian(s, tg, q, J.data());
     if (!all_finite(J.data(), m * d)) { *status = ST_NONFINITE; return; }
     double smin = 0.0;
-    const bool ok = descent_step(m, d, J.data(), F.data(), o.lambda, delta.data(), &smin);
+    const bool ok = pw ? pinv_step(m, d, J.data(), F.data(), o.lambda, delta.data(), &smin)
+                       : descent_step(m, d, J.data(), F.data(), o.lambda, delta.data(), &smin);
     if (path) path[0] = std::min(path[0], smin);
     if (!ok) { *status = ST_SINGULAR; return; }
     for (int j = 0; j < d; ++j) delta[j] *= o.alpha;
@@ -821,6 +1022,11 @@ int oracle_vjp(const void* blob, size_t nbytes, int64_t n, const double* q, cons
     }
     std::vector<double> J(size_t(m) * d), At(size_t(d) * m), tau(m), w(d), sv(m);
     jacobian(s, tg, q + c * d, J.data());
+    if (has_piecewise_rows(s)) {  // rank varies: the projector from the SVD, no condition number
+      pinv_tangent(m, d, J.data(), g + c * d, out);
+      if (kappa) kappa[c] = NAN;
+      continue;
+    }
     for (int i = 0; i < m; ++i) for (int j = 0; j < d; ++j) At[size_t(i) * d + j] = J[size_t(i) * d + j];
     jacobi_singular_values(d, m, At.data(), sv.data());
     double smax = 0, smin = INFINITY;
@@ -898,6 +1104,7 @@ int oracle_vjp_exact(const void* blob, size_t nbytes, int64_t n, const double* q
   Scene s;
   if (!parse(blob, nbytes, s)) return 1;
   if (n < 0 || !(tol > 0) || max_iter < 0) return 2;
+  if (has_piecewise_rows(s)) return 3;  // the dual-number step is the QR one, which needs full row rank
   Targets tg = make_targets(s);
   const int d = s.d;
   Opts o{tol, max_iter, alpha, lambda, 0.0, 0};

@@ -16,13 +16,16 @@ depth-first preorder, so every subtree is a contiguous index range.
 
 The constraint blocks follow the paper: a TSR pose error (Eq. 1, with the TSR
 frame T_w^0 = T_ref and the grasp offset folded into the end-effector frame),
-a relative pose error between two end-effectors (Eq. 2), the centre-of-mass
-xy error of the humanoid's stability constraint (Fig. "digit constraints",
-in the equality-to-centroid form) plus the synthetic sphere, axis-alignment
-and linear constraints used for closed-form checks.
+optionally with finite bounds B^w per component (Sec. III), a relative pose
+error between two end-effectors (Eq. 2), the centre-of-mass xy error of the
+humanoid's stability constraint (the Digit constraint figure) in two forms,
+equality to the support-polygon centroid and distance to the support polygon,
+the closed-linkage rod lengths of the same figure, plus the synthetic sphere,
+axis-alignment and linear constraints used for closed-form checks.
 
 RNG: numpy PCG64 seeded with [config_id, stream]; streams 0 robot, 1 obstacles,
-2 workload, 3 finite-difference sample, 4 geodesic lengths, 5 extension particle draws.
+2 workload, 3 finite-difference sample, 4 geodesic lengths, 5 extension particle draws,
+6 reference configuration of the bounded-TSR arm.
 """
 from __future__ import annotations
 
@@ -39,6 +42,8 @@ FAMILY_PLANAR2 = 2
 FAMILY_ARM7_AXIS = 3
 FAMILY_DUAL14_REL = 4
 FAMILY_HUMANOID36 = 5
+FAMILY_DIGIT36 = 6
+FAMILY_ARM7_TSR = 7
 FAMILY_NAMES = {
     FAMILY_SPHERE: "sphere3",
     FAMILY_LINEAR: "linear",
@@ -46,6 +51,8 @@ FAMILY_NAMES = {
     FAMILY_ARM7_AXIS: "arm7_axis",
     FAMILY_DUAL14_REL: "dual14_rel",
     FAMILY_HUMANOID36: "humanoid36",
+    FAMILY_DIGIT36: "digit36",
+    FAMILY_ARM7_TSR: "arm7_tsr",
 }
 
 JOINT_REV = 0
@@ -57,14 +64,20 @@ BLK_AXIS = 2    # frame z-axis parallel to world z: rows (z_x, z_y)
 BLK_COM = 3     # centre-of-mass xy minus a target point
 BLK_SPHERE = 4  # q.q - 1
 BLK_LINEAR = 5  # A q - b
+BLK_DIST = 6    # closed linkage: ||p_b - p_a|| - L between the origins of frames a and b (L in target[0])
+BLK_HULL = 7    # centre-of-mass xy minus its nearest point of a convex polygon (zero inside)
+
+POSE_BOUNDED = 1  # Block.aux flag of a POSE block: rows are the excess over [lo, hi] (ext[0:6], ext[6:12])
+MAX_HULL_VERTICES = 8
 
 MAGIC = 0x5343434D  # 'MCCS'
-VERSION = 1
+VERSION = 1          # version 2: every block record is followed by 16 doubles of block data (ext)
 HEADER_INTS = 16
+N_EXT = 16
 
 # obstacle-free joint limits are not part of the method; none are stored.
 
-CONFIG_IDS = {"c0": 0, "c1": 1, "c2": 2, "c3": 3, "c4": 4}
+CONFIG_IDS = {"c0": 0, "c1": 1, "c2": 2, "c3": 3, "c4": 4, "c5": 5, "c6": 6}
 
 
 def rng_for(config_id: int, stream: int) -> np.random.Generator:
@@ -97,6 +110,8 @@ class Block:
     R: np.ndarray = field(default_factory=lambda: np.eye(3))
     p: np.ndarray = field(default_factory=lambda: np.zeros(3))
     target: np.ndarray = field(default_factory=lambda: np.zeros(3))
+    aux: int = 0        # POSE: POSE_BOUNDED; HULL: number of polygon vertices
+    ext: np.ndarray = field(default_factory=lambda: np.zeros(N_EXT))  # POSE bounds lo[6], hi[6]; HULL xy vertices
 
 
 @dataclass
@@ -122,7 +137,8 @@ class Scene:
         O = 0 if self.obstacles is None else len(self.obstacles)
         has_qref = 1 if self.qref is not None else 0
         has_lin = 1 if self.A is not None else 0
-        hdr = [MAGIC, VERSION, self.family, self.d, self.m, nj, len(self.frames),
+        v2 = any(b.aux != 0 or np.any(np.asarray(b.ext) != 0) for b in self.blocks)
+        hdr = [MAGIC, 2 if v2 else VERSION, self.family, self.d, self.m, nj, len(self.frames),
                len(self.blocks), S, O, has_qref, has_lin, 0, 0, 0, 0]
         out = [struct.pack("<16i", *hdr)]
         for j in self.joints:
@@ -137,10 +153,12 @@ class Scene:
             out.append(np.asarray(f.R, "<f8").reshape(9).tobytes())
             out.append(np.asarray(f.p, "<f8").reshape(3).tobytes())
         for b in self.blocks:
-            out.append(struct.pack("<6i", b.btype, b.fa, b.fb, b.mask, b.ref_from_qref, 0))
+            out.append(struct.pack("<6i", b.btype, b.fa, b.fb, b.mask, b.ref_from_qref, b.aux))
             out.append(np.asarray(b.R, "<f8").reshape(9).tobytes())
             out.append(np.asarray(b.p, "<f8").reshape(3).tobytes())
             out.append(np.asarray(b.target, "<f8").reshape(3).tobytes())
+            if v2:
+                out.append(np.asarray(b.ext, "<f8").reshape(N_EXT).tobytes())
         for s in (self.spheres if S else []):
             out.append(struct.pack("<2i", int(s[0]), 0))
             out.append(np.asarray(s[1:5], "<f8").tobytes())
@@ -160,6 +178,11 @@ def rot_x(a):
     return np.array([[1, 0, 0], [0, c, -s], [0, s, c]], dtype=np.float64)
 
 
+def rot_z(a):
+    c, s = math.cos(a), math.sin(a)
+    return np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]], dtype=np.float64)
+
+
 def dh_origin(a, d, alpha):
     """Fixed part of a standard DH link, Tz(d) Tx(a) Rx(alpha): rotation Rx(alpha), translation (a, 0, d)."""
     return rot_x(alpha), np.array([a, 0.0, d])
@@ -168,6 +191,51 @@ def dh_origin(a, d, alpha):
 def _uniform_sphere_points(rng, n):
     v = rng.standard_normal((n, 3))
     return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def bounded_pose_block(fa: int, lo, hi, R=None, p=None, mask: int = 0x3F) -> Block:
+    """TSR pose block (Eq. 1) with finite bounds B^w: component c of [t; log(R)^v] is constrained to
+    [lo[c], hi[c]] (+-inf for a free component)."""
+    ext = np.zeros(N_EXT)
+    ext[0:6] = np.asarray(lo, np.float64)
+    ext[6:12] = np.asarray(hi, np.float64)
+    return Block(BLK_POSE, fa=fa, mask=mask, R=np.eye(3) if R is None else np.asarray(R, np.float64),
+                 p=np.zeros(3) if p is None else np.asarray(p, np.float64), aux=POSE_BOUNDED, ext=ext)
+
+
+def hull_block(vertices) -> Block:
+    """Centre-of-mass block against a convex polygon given counter-clockwise (3 to 8 xy vertices)."""
+    v = np.asarray(vertices, np.float64).reshape(-1, 2)
+    assert 3 <= len(v) <= MAX_HULL_VERTICES
+    ext = np.zeros(N_EXT)
+    ext[:2 * len(v)] = v.reshape(-1)
+    return Block(BLK_HULL, aux=len(v), ext=ext)
+
+
+def dist_block(fa: int, fb: int, length: float = 0.0, from_qref: bool = False) -> Block:
+    """Closed-linkage block: the distance between the origins of frames fa and fb equals `length`, or
+    the distance at q_ref when from_qref is set."""
+    return Block(BLK_DIST, fa=fa, fb=fb, target=np.array([float(length), 0.0, 0.0]),
+                 ref_from_qref=1 if from_qref else 0)
+
+
+def convex_hull_ccw(points) -> np.ndarray:
+    """Counter-clockwise convex hull of 2-D points (Andrew's monotone chain), collinear points dropped."""
+    P = sorted({(float(x), float(y)) for x, y in np.asarray(points, np.float64).reshape(-1, 2)})
+
+    def cross(o, a, b):
+        return (a[0] - o[0]) * (b[1] - o[1]) - (a[1] - o[1]) * (b[0] - o[0])
+
+    lower, upper = [], []
+    for pt in P:
+        while len(lower) >= 2 and cross(lower[-2], lower[-1], pt) <= 0:
+            lower.pop()
+        lower.append(pt)
+    for pt in reversed(P):
+        while len(upper) >= 2 and cross(upper[-2], upper[-1], pt) <= 0:
+            upper.pop()
+        upper.append(pt)
+    return np.array(lower[:-1] + upper[:-1])
 
 
 # ---- C0: toy sphere -------------------------------------------------------
@@ -280,6 +348,25 @@ def arm7_axis_scene(config_id: int = 1, n_obstacles: int = 200) -> Scene:
                  spheres=np.array(spheres, np.float64), obstacles=obs, name="arm7_axis")
 
 
+# TSR of the arm-with-bounds batch (Sec. III, the upright-mug example): the TSR frame is the
+# end-effector pose at a reference configuration, the bounds B^w let the frame translate by up to
+# 0.1 m in x and y and 0.02 m in z and rotate by up to 0.05 rad about x and y (tilt) and 0.5 rad about z
+ARM7_TSR_LO = np.array([-0.1, -0.1, -0.02, -0.05, -0.05, -0.5])
+ARM7_TSR_HI = np.array([0.1, 0.1, 0.02, 0.05, 0.05, 0.5])
+
+
+def arm7_tsr_scene(config_id: int = 6, n_obstacles: int = 200) -> Scene:
+    """The 7-DoF DH arm of the C1 recipe (its own seed) with one TSR pose block with finite bounds on
+    its end-effector frame; T_w^0 is the end-effector pose at q_ref ~ U[-pi, pi]^7 (stream 6)."""
+    base = arm7_axis_scene(config_id, n_obstacles)
+    blk = bounded_pose_block(0, ARM7_TSR_LO, ARM7_TSR_HI)
+    blk.ref_from_qref = 1
+    qref = rng_for(config_id, 6).uniform(-math.pi, math.pi, 7)
+    return Scene(family=FAMILY_ARM7_TSR, d=7, m=6, joints=base.joints, masses=base.masses, coms=base.coms,
+                 frames=base.frames, blocks=[blk], spheres=base.spheres, obstacles=base.obstacles, qref=qref,
+                 name="arm7_tsr")
+
+
 def arm7_workload(config_id: int = 1, n_seg: int = 4096, n_pts: int = 32, noise: float = 0.1):
     """Segments between joint vectors uniform in [-pi, pi]^7, n_pts points each (endpoints included),
     plus N(0, noise^2) joint noise per point. Returns (q [N,7], geo_offsets)."""
@@ -347,11 +434,9 @@ def humanoid_geometry(r):
     return g
 
 
-def humanoid36_scene(config_id: int = 3, n_slabs: int = 4, bend: float = 0.3, slab_x=(0.35, 0.6),
-                     slab_h=(0.2, 1.6)) -> Scene:
-    """The 36-DoF humanoid with `n_slabs` shelf slabs of 25 x 5 obstacle spheres (r 0.03, pitch 0.05 m):
-    front edge x0 ~ U[slab_x], height ~ U[slab_h]. The defaults keep the slabs in front of the robot;
-    slab_x = (0.42, 0.5), slab_h = (1.0, 1.2) puts them in reach of the hands (a scene with collisions)."""
+def _humanoid_body(config_id: int, n_slabs: int, bend: float, slab_x, slab_h) -> dict:
+    """Joint tree, collision spheres, masses, the four end-effector frames, the nominal pose and the
+    shelf-slab obstacles of the 36-DoF humanoid (shared by its two constraint sets)."""
     r = rng_for(config_id, 0)
     g = humanoid_geometry(r)
     I = np.eye(3)
@@ -423,14 +508,6 @@ def humanoid36_scene(config_id: int = 3, n_slabs: int = 4, bend: float = 0.3, sl
               Frame(26, I, np.array([0.0, 0.0, -g["hand"]])),
               Frame(33, I, np.array([0.0, 0.0, -g["hand"]]))]
     qnom = humanoid_nominal(g, bend)
-    # feet at fixed SE(3) poses on the floor, flat, hip-width apart
-    bl = Block(BLK_POSE, fa=0, p=np.array([0.0, g["hip_w"], 0.0]))
-    br = Block(BLK_POSE, fa=1, p=np.array([0.0, -g["hip_w"], 0.0]))
-    # hands: fixed relative pose (the closed chain around the box), taken at the nominal pose
-    bh = Block(BLK_REL, fa=2, fb=3, ref_from_qref=1)
-    # CoM xy at the centroid of the support polygon (hull of the two 0.2 x 0.1 m soles, both centred on x = 0)
-    bc = Block(BLK_COM, target=np.array([0.0, 0.0, 0.0]))
-
     ro = rng_for(config_id, 1)
     obs = []
     for _ in range(n_slabs):
@@ -439,9 +516,64 @@ def humanoid36_scene(config_id: int = 3, n_slabs: int = 4, bend: float = 0.3, sl
         for iy in range(25):
             for ix in range(5):
                 obs.append([x0 + 0.05 * ix, -0.6 + 0.05 * iy, h, 0.03])
-    return Scene(family=FAMILY_HUMANOID36, d=36, m=20, joints=joints, masses=masses, coms=coms,
-                 frames=frames, blocks=[bl, br, bh, bc], spheres=np.array(spheres, np.float64),
-                 obstacles=np.array(obs, np.float64), qref=qnom, name="humanoid36")
+    return dict(g=g, joints=joints, masses=masses, coms=coms, frames=frames, spheres=spheres, qnom=qnom, obs=obs)
+
+
+def humanoid36_scene(config_id: int = 3, n_slabs: int = 4, bend: float = 0.3, slab_x=(0.35, 0.6),
+                     slab_h=(0.2, 1.6)) -> Scene:
+    """The 36-DoF humanoid with `n_slabs` shelf slabs of 25 x 5 obstacle spheres (r 0.03, pitch 0.05 m):
+    front edge x0 ~ U[slab_x], height ~ U[slab_h]. The defaults keep the slabs in front of the robot;
+    slab_x = (0.42, 0.5), slab_h = (1.0, 1.2) puts them in reach of the hands (a scene with collisions)."""
+    hb = _humanoid_body(config_id, n_slabs, bend, slab_x, slab_h)
+    g = hb["g"]
+    # feet at fixed SE(3) poses on the floor, flat, hip-width apart
+    bl = Block(BLK_POSE, fa=0, p=np.array([0.0, g["hip_w"], 0.0]))
+    br = Block(BLK_POSE, fa=1, p=np.array([0.0, -g["hip_w"], 0.0]))
+    # hands: fixed relative pose (the closed chain around the box), taken at the nominal pose
+    bh = Block(BLK_REL, fa=2, fb=3, ref_from_qref=1)
+    # CoM xy at the centroid of the support polygon (hull of the two 0.2 x 0.1 m soles, both centred on x = 0)
+    bc = Block(BLK_COM, target=np.array([0.0, 0.0, 0.0]))
+
+    return Scene(family=FAMILY_HUMANOID36, d=36, m=20, joints=hb["joints"], masses=hb["masses"], coms=hb["coms"],
+                 frames=hb["frames"], blocks=[bl, br, bh, bc], spheres=np.array(hb["spheres"], np.float64),
+                 obstacles=np.array(hb["obs"], np.float64), qref=hb["qnom"], name="humanoid36")
+
+
+# sole contact patch of each foot in its sole frame (x forward, y left), for the support polygon
+DIGIT_SOLE_X = (-0.03, 0.05)
+DIGIT_SOLE_Y = (-0.03, 0.03)
+DIGIT_TOE_OUT = 0.1  # foot yaw (rad), left +, right -
+
+
+def digit36_scene(config_id: int = 5, n_slabs: int = 4, bend: float = 0.3, slab_x=(0.35, 0.6),
+                  slab_h=(0.2, 1.6)) -> Scene:
+    """The humanoid tree with the Digit constraint set of the paper's constraint figure: both feet at
+    fixed poses (toed out by DIGIT_TOE_OUT), the hands' fixed relative pose, the CoM xy within the
+    support polygon (the convex hull of the two sole contact patches at the feet's poses; the rows are
+    the CoM minus its nearest point of the polygon, zero inside) and, per leg, a closed-linkage rod of
+    fixed length between a point on the hip-roll link and a point on the shin (the length at the
+    nominal pose)."""
+    hb = _humanoid_body(config_id, n_slabs, bend, slab_x, slab_h)
+    g = hb["g"]
+    I = np.eye(3)
+    frames = list(hb["frames"]) + [
+        Frame(7, I, np.array([0.06, 0.0, -0.05])),    # 4: left hip rod end
+        Frame(9, I, np.array([0.05, 0.0, -0.12])),    # 5: left tarsus rod end
+        Frame(13, I, np.array([0.06, 0.0, -0.05])),   # 6: right hip rod end
+        Frame(15, I, np.array([0.05, 0.0, -0.12]))]   # 7: right tarsus rod end
+    Rl, Rr = rot_z(DIGIT_TOE_OUT), rot_z(-DIGIT_TOE_OUT)
+    pl, pr = np.array([0.0, g["hip_w"], 0.0]), np.array([0.0, -g["hip_w"], 0.0])
+    bl = Block(BLK_POSE, fa=0, R=Rl, p=pl)
+    br = Block(BLK_POSE, fa=1, R=Rr, p=pr)
+    bh = Block(BLK_REL, fa=2, fb=3, ref_from_qref=1)
+    corners = np.array([[x, y, 0.0] for x in DIGIT_SOLE_X for y in DIGIT_SOLE_Y])
+    patch = np.concatenate([(corners @ Rl.T + pl)[:, :2], (corners @ Rr.T + pr)[:, :2]])
+    bc = hull_block(convex_hull_ccw(patch))
+    dl = dist_block(4, 5, from_qref=True)
+    dr = dist_block(6, 7, from_qref=True)
+    return Scene(family=FAMILY_DIGIT36, d=36, m=22, joints=hb["joints"], masses=hb["masses"], coms=hb["coms"],
+                 frames=frames, blocks=[bl, br, bh, bc, dl, dr], spheres=np.array(hb["spheres"], np.float64),
+                 obstacles=np.array(hb["obs"], np.float64), qref=hb["qnom"], name="digit36")
 
 
 def humanoid_nominal(g, bend=0.3):
@@ -523,6 +655,20 @@ def make_config(name: str, small: bool = False):
         return dict(name=name, scene=sc, tol=1e-6, max_iter=40,
                     endpoints=raw_endpoints(sc, 4, n_geo, humanoid_noise_sigma()),
                     geo_offsets=geodesic_lengths(4, n_geo, 8, 64))
+    if name == "c5":
+        # the Digit constraint set on the humanoid (closed linkages, CoM within the support polygon)
+        sc = digit36_scene(5)
+        n_geo = 32 if small else 2048
+        return dict(name=name, scene=sc, tol=1e-6, max_iter=40,
+                    endpoints=raw_endpoints(sc, 5, n_geo, humanoid_noise_sigma()),
+                    geo_offsets=np.arange(n_geo + 1, dtype=np.int32) * 32)
+    if name == "c6":
+        # the 7-DoF arm with a bounded TSR: geodesics between projected endpoints q_ref + N(0, 0.2^2)
+        sc = arm7_tsr_scene(6)
+        n_geo = 64 if small else 4096
+        return dict(name=name, scene=sc, tol=1e-6, max_iter=30,
+                    endpoints=raw_endpoints(sc, 6, n_geo, 0.2),
+                    geo_offsets=np.arange(n_geo + 1, dtype=np.int32) * 32)
     raise ValueError(name)
 
 
