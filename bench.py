@@ -135,7 +135,7 @@ def other_workloads(M, S, FL, torch, steps):
     throughput, iteration statistics, algorithmic FLOP rate and HBM rate (inputs, outputs, status,
     iterations, residual and verdict bytes) of the whole projection step."""
     rows = {}
-    for name in ("c0", "c1", "c2"):
+    for name in ("c0", "c1", "c2", "c5", "c6"):
         cfg = S.make_config(name)
         sc = cfg["scene"]
         G = M.Problem(sc.to_blob())

@@ -66,8 +66,14 @@ enum {
   MC_FAMILY_PLANAR2 = 2,    /* planar 2R arm, tip position (x, y) pose block                    */
   MC_FAMILY_ARM7_AXIS = 3,  /* 7-DoF serial arm, end-effector z parallel to world z (2 rows)    */
   MC_FAMILY_DUAL14_REL = 4, /* two 7-DoF arms, relative end-effector pose of Eq. 2 (6 rows)     */
-  MC_FAMILY_HUMANOID36 = 5  /* 36-DoF humanoid tree: feet poses (12), hands relative pose (6),
+  MC_FAMILY_HUMANOID36 = 5, /* 36-DoF humanoid tree: feet poses (12), hands relative pose (6),
                                centre-of-mass xy (2)                                           */
+  MC_FAMILY_DIGIT36 = 6,    /* the humanoid tree with the Digit constraint set (the paper's
+                               Digit constraint figure): feet poses (12), hands relative pose
+                               (6), CoM xy minus its nearest point of the support polygon (2,
+                               zero inside), closed-linkage rod lengths (2)                    */
+  MC_FAMILY_ARM7_TSR = 7    /* 7-DoF serial arm, TSR pose block of Eq. 1 with finite bounds B^w
+                               (Sec. III): each component's excess over its interval (6)       */
 };
 
 typedef struct mc_problem mc_problem; /* opaque; device-resident scene */
@@ -111,13 +117,15 @@ typedef struct {
    check on, variant auto, stacked mode, launch shape auto). */
 void mc_default_opts(mc_project_opts* opts);
 
-/* Create a problem from a scene blob (magic 'MCCS', version 1: the little-endian layout written
-   by Scene.to_blob in paper_2604_13323_amd/scenes.py, a 16-int header followed by joints, links,
-   frames, constraint blocks, robot spheres, obstacles and the optional q_ref, A, b):
+/* Create a problem from a scene blob (magic 'MCCS', version 1 or 2: the little-endian layout
+   written by Scene.to_blob in paper_2604_13323_amd/scenes.py, a 16-int header followed by joints,
+   links, frames, constraint blocks, robot spheres, obstacles and the optional q_ref, A, b; in
+   version 2 every block record is followed by 16 doubles of block data: the bounds lo[6], hi[6] of
+   a bounded pose block, the counter-clockwise xy vertices of a support polygon):
    parses and validates the blob on the host, checks that its kinematic structure matches a
-   compiled family, derives the constants the kernels need (reference poses of blocks flagged
-   ref_from_qref, subtree masses, link bounding spheres, obstacle clusters) and copies them
-   to the current HIP device. The blob is not retained. *out receives the handle.
+   compiled family, derives the constants the kernels need (reference poses and rod lengths of
+   blocks flagged ref_from_qref, support-polygon edges and normals, subtree masses, link bounding
+   spheres, obstacle clusters) and copies them to the current HIP device. The blob is not retained. *out receives the handle.
    Errors: MC_ERR_INVALID_ARG (null, malformed blob), MC_ERR_UNSUPPORTED (no kernel for this
    structure), MC_ERR_OOM / MC_ERR_HIP. */
 mc_status mc_problem_create(const void* scene_blob, size_t nbytes, mc_problem** out);

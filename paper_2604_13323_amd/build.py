@@ -52,7 +52,7 @@ def build(force: bool = True, jobs: int | None = None, verbose: bool = True) -> 
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     # the largest translation units first
-    srcs.sort(key=lambda p: ("humanoid" not in p, "dual" not in p, p))
+    srcs.sort(key=lambda p: ("humanoid" not in p and "digit" not in p, "dual" not in p, p))
     jobs = jobs or min(len(srcs), max(1, os.cpu_count() or 4))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, force), srcs))

@@ -32,7 +32,7 @@ mc_status hip_fail(hipError_t e, const char* what) {
 // ------------------------------------------------------------------ host scene
 struct HJoint { int parent, type, axis; double R[9], p[3]; };
 struct HFrame { int link; double R[9], p[3]; };
-struct HBlock { int type, fa, fb, mask, ref_from_qref; double R[9], p[3], target[3]; };
+struct HBlock { int type, fa, fb, mask, ref_from_qref, aux; double R[9], p[3], target[3], ext[16]; };
 struct HSphere { int link; double c[3], r; };
 struct HScene {
   int family = 0, d = 0, m = 0;
@@ -65,7 +65,8 @@ bool parse_blob(const void* blob, size_t nbytes, HScene& s, std::string& err) {
   int32_t h[16];
   for (int i = 0; i < 16; ++i) h[i] = c.get<int32_t>();
   if (!c.ok || h[0] != 0x5343434D) { err = "scene blob: bad magic or truncated header"; return false; }
-  if (h[1] != 1) { err = "scene blob: unsupported version"; return false; }
+  if (h[1] != 1 && h[1] != 2) { err = "scene blob: unsupported version"; return false; }
+  const bool v2 = h[1] == 2;  // every block record is followed by 16 doubles of block data
   s.family = h[2]; s.d = h[3]; s.m = h[4];
   const int nj = h[5], nf = h[6], nb = h[7], ns = h[8], no = h[9], has_qref = h[10], has_lin = h[11];
   if (s.d <= 0 || s.m <= 0 || nj < 0 || nf < 0 || nb <= 0 || ns < 0 || no < 0 || nj > 4096 || nf > 4096 ||
@@ -84,8 +85,10 @@ bool parse_blob(const void* blob, size_t nbytes, HScene& s, std::string& err) {
   s.blocks.resize(nb);
   for (auto& b : s.blocks) {
     b.type = c.get<int32_t>(); b.fa = c.get<int32_t>(); b.fb = c.get<int32_t>(); b.mask = c.get<int32_t>();
-    b.ref_from_qref = c.get<int32_t>(); c.get<int32_t>();
+    b.ref_from_qref = c.get<int32_t>(); b.aux = c.get<int32_t>();
     c.getd(b.R, 9); c.getd(b.p, 3); c.getd(b.target, 3);
+    for (int k = 0; k < 16; ++k) b.ext[k] = 0.0;
+    if (v2) c.getd(b.ext, 16);
   }
   s.spheres.resize(ns);
   for (auto& sp : s.spheres) { sp.link = c.get<int32_t>(); c.get<int32_t>(); c.getd(sp.c, 3); sp.r = c.get<double>(); }
@@ -190,7 +193,25 @@ bool matches_topology(const HScene& s, std::string& err) {
     if ((B.type == B_POSE || B.type == B_REL || B.type == B_AXIS) && B.fa != Topo::bfa[b]) { err = "block frame mismatch"; return false; }
     if (B.type == B_REL && B.fb != Topo::bfb[b]) { err = "block frame mismatch"; return false; }
     if ((B.type == B_POSE || B.type == B_REL) && B.mask != Topo::bmask[b]) { err = "block row mask mismatch"; return false; }
-    if (B.type == B_COM && !Topo::has_com) { err = "unexpected CoM block"; return false; }
+    if ((B.type == B_COM || B.type == B_HULL) && !Topo::has_com) { err = "unexpected CoM block"; return false; }
+    if (B.type == B_DIST && (B.fa != Topo::bfa[b] || B.fb != Topo::bfb[b])) { err = "block frame mismatch"; return false; }
+    if (B.type == B_POSE) {
+      if ((B.aux & BF_BOUNDED) != (Topo::bflags[b] & BF_BOUNDED)) { err = "pose block bounds flag mismatch"; return false; }
+      if (B.aux & BF_BOUNDED)
+        for (int c = 0; c < 6; ++c)
+          if (!(B.ext[c] <= B.ext[6 + c])) { err = "pose block bounds: lo > hi or NaN"; return false; }
+    }
+    if (B.type == B_HULL) {  // a convex polygon given counter-clockwise, 3 to MAXHV vertices
+      if (B.aux < 3 || B.aux > MAXHV) { err = "support polygon: 3 to 8 vertices"; return false; }
+      for (int i = 0; i < B.aux; ++i) {
+        const double* a = B.ext + 2 * i;
+        const double* c = B.ext + 2 * ((i + 1) % B.aux);
+        const double* e = B.ext + 2 * ((i + 2) % B.aux);
+        if (!((c[0] - a[0]) * (e[1] - c[1]) - (c[1] - a[1]) * (e[0] - c[0]) > 0.0)) {
+          err = "support polygon: not convex and counter-clockwise"; return false;
+        }
+      }
+    }
   }
   for (const auto& sp : s.spheres)
     if (sp.link < 0 || !Topo::may_have_spheres(sp.link)) { err = "sphere on a link without geometry slot"; return false; }
@@ -206,6 +227,8 @@ const FamilyOps* ops_for(int family, int f64) {
     case MC_FAMILY_ARM7_AXIS: return f64 ? &ops_arm7_axis_f64 : &ops_arm7_axis_f32;
     case MC_FAMILY_DUAL14_REL: return f64 ? &ops_dual14_rel_f64 : &ops_dual14_rel_f32;
     case MC_FAMILY_HUMANOID36: return f64 ? &ops_humanoid36_f64 : &ops_humanoid36_f32;
+    case MC_FAMILY_DIGIT36: return f64 ? &ops_digit36_f64 : &ops_digit36_f32;
+    case MC_FAMILY_ARM7_TSR: return f64 ? &ops_arm7_tsr_f64 : &ops_arm7_tsr_f32;
   }
   return nullptr;
 }
@@ -230,6 +253,8 @@ bool validate_family(const HScene& s, std::string& err) {
     case MC_FAMILY_ARM7_AXIS: return matches_topology<TopoArm7Axis>(s, err);
     case MC_FAMILY_DUAL14_REL: return matches_topology<TopoDual14Rel>(s, err);
     case MC_FAMILY_HUMANOID36: return matches_topology<TopoHumanoid36>(s, err);
+    case MC_FAMILY_DIGIT36: return matches_topology<TopoDigit36>(s, err);
+    case MC_FAMILY_ARM7_TSR: return matches_topology<TopoArm7Tsr>(s, err);
   }
   err = "unknown scene family " + std::to_string(s.family);
   return false;
@@ -295,6 +320,23 @@ void fill_tp(TP<T>& t, const HScene& s, const std::vector<HT>& tref, const std::
     for (int i = 0; i < 3; ++i) for (int k = 0; k < 3; ++k) t.refRt[b][3 * i + k] = T(r.R[3 * k + i]);
     for (int k = 0; k < 3; ++k) t.refp[b][k] = T(r.p[k]);
     for (int k = 0; k < 3; ++k) t.target[b][k] = T(s.blocks[b].target[k]);
+    if (s.blocks[b].type == B_POSE && (s.blocks[b].aux & BF_BOUNDED))
+      for (int c = 0; c < 6; ++c) {
+        t.blo[b][c] = T(s.blocks[b].ext[c]);
+        t.bhi[b][c] = T(s.blocks[b].ext[6 + c]);
+      }
+    if (s.blocks[b].type == B_HULL) {
+      const int nv = s.blocks[b].aux;
+      const double* V = s.blocks[b].ext;
+      for (int i = 0; i < nv && i < MAXHV; ++i) {
+        const double ax = V[2 * i], ay = V[2 * i + 1];
+        const double ex = V[2 * ((i + 1) % nv)] - ax, ey = V[2 * ((i + 1) % nv) + 1] - ay;
+        const double len = std::sqrt(ex * ex + ey * ey);
+        t.hull_e[i][0] = T(ax); t.hull_e[i][1] = T(ay); t.hull_e[i][2] = T(ex); t.hull_e[i][3] = T(ey);
+        // outward normal of a counter-clockwise polygon: the edge direction turned clockwise
+        t.hull_n[i][0] = T(ey / len); t.hull_n[i][1] = T(-ex / len); t.hull_n[i][2] = T(1.0 / (len * len));
+      }
+    }
   }
   t.inv_total_mass = Mtot > 0 ? T(1.0 / Mtot) : T(0);
   for (int l = 0; l < MAXJ; ++l)
@@ -816,6 +858,11 @@ mc_status mc_problem_create(const void* blob, size_t nbytes, mc_problem** out) {
     if (B.ref_from_qref && B.type == B_POSE) tref[b] = frame_at(B.fa);
     else if (B.ref_from_qref && B.type == B_REL) tref[b] = ht_mul(ht_inv(frame_at(B.fa)), frame_at(B.fb));
     else tref[b] = ht_make(B.R, B.p);
+    if (B.ref_from_qref && B.type == B_DIST) {  // the rod length at q_ref
+      const HT a = frame_at(B.fa), c = frame_at(B.fb);
+      const double dx = c.p[0] - a.p[0], dy = c.p[1] - a.p[1], dz = c.p[2] - a.p[2];
+      s.blocks[b].target[0] = std::sqrt(dx * dx + dy * dy + dz * dz);
+    }
   }
   // subtree masses (joints are in depth-first preorder; parent < child)
   std::vector<double> submass(s.joints.size(), 0.0);
@@ -833,6 +880,9 @@ mc_status mc_problem_create(const void* blob, size_t nbytes, mc_problem** out) {
   hp->c.dof = s.d;
   hp->c.rows = s.m;
   hp->c.lin_m = s.family == MC_FAMILY_LINEAR ? s.m : 0;
+  hp->c.hull_nv = 0;
+  for (const auto& B : s.blocks)
+    if (B.type == B_HULL) hp->c.hull_nv = B.aux;
   CollConsts& K = hp->k;
 
   // robot spheres grouped by link, link bounding spheres

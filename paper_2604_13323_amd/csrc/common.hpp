@@ -16,9 +16,10 @@
 namespace mc {
 
 constexpr int MAXJ = 36;    // joints (= DoF of kinematic families)
-constexpr int MAXF = 4;     // end-effector frames
-constexpr int MAXB = 4;     // constraint blocks
-constexpr int MAXM = 20;    // stacked rows
+constexpr int MAXF = 8;     // end-effector frames
+constexpr int MAXB = 6;     // constraint blocks
+constexpr int MAXM = 22;    // stacked rows
+constexpr int MAXHV = 8;    // support-polygon vertices
 constexpr int MAXS = 320;   // robot collision spheres
 constexpr int MAXC = 128;   // obstacle clusters
 constexpr int MAXO = 2048;  // obstacle spheres
@@ -26,7 +27,8 @@ constexpr int LIN_D = 8;    // linear family: padded d
 constexpr int LIN_M = 6;    // linear family: padded m
 
 enum : int { REV = 0, PRI = 1 };
-enum : int { B_POSE = 0, B_REL = 1, B_AXIS = 2, B_COM = 3, B_SPHERE = 4, B_LINEAR = 5 };
+enum : int { B_POSE = 0, B_REL = 1, B_AXIS = 2, B_COM = 3, B_SPHERE = 4, B_LINEAR = 5, B_DIST = 6, B_HULL = 7 };
+constexpr int BF_BOUNDED = 1;  // POSE block flag: rows are the excess over finite bounds
 enum : int { ST_CONVERGED = 0, ST_MAX_ITER = 1, ST_SINGULAR = 2, ST_DIVERGED = 3, ST_NONFINITE = 4 };
 enum : int { V_FREE = 0, V_HIT = 1, V_UNCHECKED = 2 };
 
@@ -38,7 +40,11 @@ struct TP {
   T fp[MAXF][3];       // end-effector frame offset translation
   T refRt[MAXB][9];    // R_ref^T of pose / relative-pose blocks
   T refp[MAXB][3];     // p_ref
-  T target[MAXB][3];   // centre-of-mass target (x, y)
+  T target[MAXB][3];   // centre-of-mass target (x, y); rod length (closed-linkage blocks)
+  T blo[MAXB][6];      // bounded pose blocks: lower and upper bound of each component of [t; log(R)^v]
+  T bhi[MAXB][6];
+  T hull_e[MAXHV][4];  // support polygon edge i: start vertex (x, y) and edge vector (x, y)
+  T hull_n[MAXHV][4];  // its outward unit normal (x, y) and 1 / |edge|^2
   T mass[MAXJ];        // link masses
   T mcom[MAXJ][3];     // mass * local centre of mass
   T submass[MAXJ];     // mass of the subtree rooted at joint j
@@ -54,7 +60,7 @@ struct TP {
 struct alignas(16) Consts {
   TP<double> d;
   TP<float> f;
-  int32_t dof, rows, lin_m, pad;
+  int32_t dof, rows, lin_m, hull_nv;
 };
 
 constexpr int MAXSUP = 32;  // groups of obstacle clusters

@@ -77,25 +77,35 @@ struct QGlob {  // configuration i of a [D][ld] array in global memory
 };
 
 // ------------------------------------------------------------------ Cholesky
+// Rows a lane has dropped (bits of Model::DROPPABLE; none for models that never drop rows).
+template <class Model, class SDT>
+__device__ __forceinline__ uint32_t drop_bits(const SDT& sd) {
+  if constexpr (Model::DROPPABLE != 0) return sd.drop;
+  else return 0u;
+}
+
 // In-place right-looking Cholesky of the packed lower triangle G (structural zeros of the
 // factor skipped at compile time). Returns false on a non-positive or non-finite pivot, or a
 // pivot below floor. invd receives 1 / L_ii; kappa the estimate (max L_ii / min L_ii)^2.
+// A dropped row (its G row and column are zero) gets the unit pivot and takes no part in kappa.
 template <class Model, class S, uint32_t RM = ~uint32_t(0)>
-__device__ __forceinline__ bool cholesky(S* G, S* invd, S& kappa, S floor) {
+__device__ __forceinline__ bool cholesky(S* G, S* invd, S& kappa, S floor, uint32_t drop = 0u) {
   constexpr int M = Model::M;
   bool ok = true;
   S dmin = S(3.0e38), dmax = S(0);
   sfor<0, M>([&](auto K) {
     constexpr int k = decltype(K)::value;
     if constexpr (((RM >> k) & 1u) != 0) {
-    const S d = G[pidx(k, k)];
-    ok = ok && (d > floor) && finite_t(d);
+    bool dk = false;
+    if constexpr (((Model::DROPPABLE >> k) & 1u) != 0) dk = ((drop >> k) & 1u) != 0;
+    const S d = dk ? S(1) : G[pidx(k, k)];
+    ok = ok && (dk || ((d > floor) && finite_t(d)));
     const S r = rsqrt_t(d);
     const S l = d * r;
     G[pidx(k, k)] = l;
     invd[k] = r;
-    dmin = l < dmin ? l : dmin;
-    dmax = l > dmax ? l : dmax;
+    dmin = (dk || !(l < dmin)) ? dmin : l;
+    dmax = (dk || !(l > dmax)) ? dmax : l;
     sfor<k + 1, M>([&](auto I) {
       constexpr int i = decltype(I)::value;
       if constexpr (Model::lnz(i, k) && ((RM >> i) & 1u)) G[pidx(i, k)] *= r;
@@ -111,7 +121,8 @@ __device__ __forceinline__ bool cholesky(S* G, S* invd, S& kappa, S floor) {
     });
     }
   });
-  const S ratio = dmax / dmin;
+  S ratio = dmax / dmin;
+  if constexpr (Model::DROPPABLE != 0) ratio = dmax > S(0) ? ratio : S(0);  // every row dropped
   kappa = ratio * ratio;
   return ok && finite_t(kappa);
 }
@@ -166,7 +177,7 @@ __device__ __forceinline__ bool descent_step(const Q& q, S* rhs, const typename 
     }
   });
   S invd[M], kappa;
-  if (!cholesky<Model, S, RM>(G, invd, kappa, floor_rel * maxd)) return false;
+  if (!cholesky<Model, S, RM>(G, invd, kappa, floor_rel * maxd, drop_bits<Model>(sd))) return false;
   if (!(double(kappa) <= cond_thr)) return false;
   chol_solve<Model, S, RM>(G, invd, rhs);
   Model::template jty<S, RM>(q, C, sd, rhs, dq);
@@ -666,7 +677,7 @@ __device__ __forceinline__ void vjp64(const VjpArgs& a, int dof, int64_t i, cons
   Model::template jv<double>(q, C, sd, g, v);
   double maxd = 0.0;
   for (int r = 0; r < M; ++r) maxd = fmax(maxd, G[pidx(r, r)]);
-  if (cholesky<Model, double>(G, invd, kappa, kFloorF64 * maxd)) {
+  if (cholesky<Model, double>(G, invd, kappa, kFloorF64 * maxd, drop_bits<Model>(sd))) {
     chol_solve<Model, double>(G, invd, v);
     Model::template jty<double>(q, C, sd, v, VjpOut<IO, double>{static_cast<IO*>(a.g_in) + i, a.ld, g, dof});
   } else {
@@ -700,7 +711,7 @@ __global__ void __launch_bounds__(64) k_vjp(VjpArgs a) {
     Model::template residual<float>(q, C, F, sd);
     Model::template gram<float, false>(q, C, sd, G, g, v);
     Model::template jv<float>(q, C, sd, g, v);
-    if (cholesky<Model, float>(G, invd, kappa, kFloorF32) && double(kappa) <= a.cond_thr) {
+    if (cholesky<Model, float>(G, invd, kappa, kFloorF32, drop_bits<Model>(sd)) && double(kappa) <= a.cond_thr) {
       chol_solve<Model, float>(G, invd, v);
       Model::template jty<float>(q, C, sd, v, VjpOut<IO, float>{static_cast<IO*>(a.g_in) + i, a.ld, g, dof});
     } else {
@@ -793,7 +804,7 @@ __device__ __forceinline__ bool gram64(const QLds& q, const Consts& C, double la
     G[pidx(r, r)] += lambda;
     maxd = fmax(maxd, G[pidx(r, r)]);
   }
-  return cholesky<Model, double>(G, invd, kappa, kFloorF64 * maxd);
+  return cholesky<Model, double>(G, invd, kappa, kFloorF64 * maxd, drop_bits<Model>(sd));
 }
 
 // k FP64 Newton steps from the input (replaying the forward pass's path); false on a failure.
@@ -816,14 +827,16 @@ __device__ __forceinline__ bool replay(const VjpxArgs& a, int dof, int64_t i, in
 
 // Accumulate coef * (gradient of c.F at q + t u/|u|) into w (the FP64 cotangent tile: the two
 // evaluations of a central difference add nearly cancelling terms of size |u| |grad| / 2h).
+// Rows that a lane may drop keep the base point's choice (base: the step data at q).
 template <class Model>
 __device__ __forceinline__ void grad_axpy(const QLds& q, const FLds& u, double t, const Consts& C, const double* c,
-                                          double coef, const QLds& w) {
+                                          double coef, const QLds& w, const typename Model::template SD<double>& base) {
   constexpr int M = Model::M;
   const QShift qs{q, u, t};
   typename Model::template SD<double> sd;
   double F[M];
   Model::template residual<double>(qs, C, F, sd);
+  if constexpr (Model::DROPPABLE != 0) Model::freeze_rows(sd, base);
   Model::template jty<double>(qs, C, sd, c, fn_sink<double>([&](int j, double acc) { w.set(j, w.at(j) + coef * acc); }));
 }
 
@@ -890,8 +903,8 @@ __global__ void __launch_bounds__(64) k_vjp_exact(VjpxArgs a) {
     // w -= alpha H(y.F) a: central difference of the gradient J^T y along a / |a|, times |a| / 2h
     if (vn > 0.0) {
       const double coef = al * vn / (2.0 * h);
-      grad_axpy<Model>(q, v, h / vn, C, F, -coef, w);
-      grad_axpy<Model>(q, v, -h / vn, C, F, coef, w);
+      grad_axpy<Model>(q, v, h / vn, C, F, -coef, w, sd);
+      grad_axpy<Model>(q, v, -h / vn, C, F, coef, w, sd);
     }
     // v <- delta = J^T y, then w += alpha H(z.F) delta
     Model::template jty<double>(q, C, sd, F, fn_sink<double>([&](int j, double acc) { v.set(j, float(acc)); }));
@@ -900,8 +913,8 @@ __global__ void __launch_bounds__(64) k_vjp_exact(VjpxArgs a) {
     dn = sqrt(dn);
     if (dn > 0.0) {
       const double coef = al * dn / (2.0 * h);
-      grad_axpy<Model>(q, v, h / dn, C, z, coef, w);
-      grad_axpy<Model>(q, v, -h / dn, C, z, -coef, w);
+      grad_axpy<Model>(q, v, h / dn, C, z, coef, w, sd);
+      grad_axpy<Model>(q, v, -h / dn, C, z, -coef, w, sd);
     }
   }
   for (int c = 0; c < dof; ++c) out[int64_t(c) * a.ld] = ok ? IO(w.at(c)) : IO(__builtin_nan(""));
@@ -957,7 +970,7 @@ __global__ void __launch_bounds__(64) k_eval_cond(const DevProblem* Pp, int64_t 
     maxd = G[pidx(r, r)] > maxd ? G[pidx(r, r)] : maxd;
   }
   const S floor = std::is_same<S, float>::value ? S(kFloorF32) : S(kFloorF64);
-  const bool ok = cholesky<Model, S>(G, invd, kappa, floor * maxd);
+  const bool ok = cholesky<Model, S>(G, invd, kappa, floor * maxd, drop_bits<Model>(sd));
   st_io<IO>(kappa_out, i, ok ? double(kappa) : __builtin_huge_val());
 }
 

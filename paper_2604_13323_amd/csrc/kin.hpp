@@ -19,6 +19,14 @@
 //   REL   (Eq. 2)  T_err = T_ref^-1 (T_a^-1 T_b), rows [t; log(R)^v].
 //   AXIS           (R_f e_z)_x, (R_f e_z)_y  (frame z-axis parallel to world z).
 //   COM   (Digit constraint figure, equality form) sum_l m_l c_l / M |_xy - target.
+//   HULL  (Digit constraint figure) that CoM xy minus its nearest point of a convex polygon, zero
+//         inside; in an edge region written in the edge's frame, [n.d, 0].
+//   DIST  (Digit constraint figure, closed linkage) ||p_b - p_a|| - L between two frame origins.
+//   A POSE block flagged BF_BOUNDED has finite bounds: a row is its component's excess over the
+//   interval [lo, hi].
+// Rows that vanish on a region (a bounded component inside its interval, polygon rows inside the
+// polygon, the second polygon row of an edge region) are dropped per lane: zero residual, zero
+// Jacobian row, and a unit Cholesky pivot, so the step is the minimum-norm step of the rows left.
 //
 // Analytic Jacobian columns (for a revolute joint j; prismatic in brackets):
 //   POSE  [W (z_j x (p_f - o_j)); A z_j]    [W z_j; 0],   W = R_ref^T, A = J_l^-1(w) W
@@ -27,6 +35,8 @@
 //   AXIS  (z_j x u)_xy with u = R_f e_z         [0]
 //   COM   (z_j x (S_j - M_j o_j))_xy / M        [(M_j / M) z_j,xy]
 //         S_j = sum of m_l c_l over the subtree of j, M_j its mass.
+//   HULL  H c with c the COM column and H the lane's 2 x 2 row map (edge frame, identity, or 0)
+//   DIST  s_j u.(z_j x (p_e - o_j)), p_e the moving end   [s_j u.z_j],  u = (p_b - p_a) / |p_b - p_a|
 #pragma once
 
 #include "common.hpp"
@@ -46,6 +56,7 @@ struct TopoPlanar2 {
   static constexpr int bfa[NB] = {0};
   static constexpr int bfb[NB] = {-1};
   static constexpr int bmask[NB] = {0x3};
+  static constexpr int bflags[NB] = {0};
   static constexpr bool has_com = false;
   static constexpr bool massless(int) { return true; }
   static constexpr bool may_have_spheres(int) { return true; }
@@ -63,6 +74,7 @@ struct TopoArm7Axis {
   static constexpr int bfa[NB] = {0};
   static constexpr int bfb[NB] = {-1};
   static constexpr int bmask[NB] = {0};
+  static constexpr int bflags[NB] = {0};
   static constexpr bool has_com = false;
   static constexpr bool massless(int) { return true; }
   static constexpr bool may_have_spheres(int) { return true; }
@@ -80,6 +92,7 @@ struct TopoDual14Rel {
   static constexpr int bfa[NB] = {0};
   static constexpr int bfb[NB] = {1};
   static constexpr int bmask[NB] = {0x3F};
+  static constexpr int bflags[NB] = {0};
   static constexpr bool has_com = false;
   static constexpr bool massless(int) { return true; }
   static constexpr bool may_have_spheres(int) { return true; }
@@ -117,9 +130,69 @@ struct TopoHumanoid36 {
   static constexpr int bfa[NB] = {0, 1, 2, -1};
   static constexpr int bfb[NB] = {-1, -1, 3, -1};
   static constexpr int bmask[NB] = {0x3F, 0x3F, 0x3F, 0};
+  static constexpr int bflags[NB] = {0, 0, 0, 0};
   static constexpr bool has_com = true;
   static constexpr bool massless(int j) { return j < 5; }     // the base's intermediate links
   static constexpr bool may_have_spheres(int j) { return j >= 5; }
+};
+
+// The humanoid tree with the Digit constraint set: feet poses, hands relative pose, CoM within the
+// support polygon, and one closed-linkage rod per leg (hip-roll link to shin).
+struct TopoDigit36 {
+  static constexpr int family = 6;
+  static constexpr int NJ = 36, NF = 8, NB = 6, M = 22;
+  static constexpr int parent[NJ] = {-1, 0, 1, 2, 3, 4,
+                                     5, 6, 7, 8, 9, 10,
+                                     5, 12, 13, 14, 15, 16,
+                                     5, 18,
+                                     19, 20, 21, 22, 23, 24, 25,
+                                     19, 27, 28, 29, 30, 31, 32,
+                                     19, 34};
+  static constexpr int jtype[NJ] = {PRI, PRI, PRI, REV, REV, REV,
+                                    REV, REV, REV, REV, REV, REV,
+                                    REV, REV, REV, REV, REV, REV,
+                                    REV, REV,
+                                    REV, REV, REV, REV, REV, REV, REV,
+                                    REV, REV, REV, REV, REV, REV, REV,
+                                    REV, REV};
+  static constexpr int axis[NJ] = {0, 1, 2, 2, 1, 0,
+                                   2, 0, 1, 1, 1, 0,
+                                   2, 0, 1, 1, 1, 0,
+                                   2, 1,
+                                   1, 0, 2, 1, 2, 1, 0,
+                                   1, 0, 2, 1, 2, 1, 0,
+                                   2, 1};
+  static constexpr bool origin_rot = false, frame_rot = false;
+  // left sole, right sole, left palm, right palm, rod ends: left hip, left shin, right hip, right shin
+  static constexpr int frame_link[NF] = {11, 17, 26, 33, 7, 9, 13, 15};
+  static constexpr int btype[NB] = {B_POSE, B_POSE, B_REL, B_HULL, B_DIST, B_DIST};
+  static constexpr int bfa[NB] = {0, 1, 2, -1, 4, 6};
+  static constexpr int bfb[NB] = {-1, -1, 3, -1, 5, 7};
+  static constexpr int bmask[NB] = {0x3F, 0x3F, 0x3F, 0, 0, 0};
+  static constexpr int bflags[NB] = {0, 0, 0, 0, 0, 0};
+  static constexpr bool has_com = true;
+  static constexpr bool massless(int j) { return j < 5; }
+  static constexpr bool may_have_spheres(int j) { return j >= 5; }
+};
+
+// The 7-DoF arm with one TSR pose block of finite bounds on its end-effector frame (all six
+// components; a free component has infinite bounds).
+struct TopoArm7Tsr {
+  static constexpr int family = 7;
+  static constexpr int NJ = 7, NF = 1, NB = 1, M = 6;
+  static constexpr int parent[NJ] = {-1, 0, 1, 2, 3, 4, 5};
+  static constexpr int jtype[NJ] = {REV, REV, REV, REV, REV, REV, REV};
+  static constexpr int axis[NJ] = {2, 2, 2, 2, 2, 2, 2};
+  static constexpr bool origin_rot = true, frame_rot = true;
+  static constexpr int frame_link[NF] = {6};
+  static constexpr int btype[NB] = {B_POSE};
+  static constexpr int bfa[NB] = {0};
+  static constexpr int bfb[NB] = {-1};
+  static constexpr int bmask[NB] = {0x3F};
+  static constexpr int bflags[NB] = {BF_BOUNDED};
+  static constexpr bool has_com = false;
+  static constexpr bool massless(int) { return true; }
+  static constexpr bool may_have_spheres(int) { return true; }
 };
 
 // ------------------------------------------------------------------ structure
@@ -137,7 +210,8 @@ struct KInfo {
     return c;
   }
   static constexpr int brows(int b) {
-    return (Topo::btype[b] == B_POSE || Topo::btype[b] == B_REL) ? popc6(Topo::bmask[b]) : 2;
+    return (Topo::btype[b] == B_POSE || Topo::btype[b] == B_REL) ? popc6(Topo::bmask[b])
+                                                                   : (Topo::btype[b] == B_DIST ? 1 : 2);
   }
   static constexpr int brow0(int b) {
     int r = 0;
@@ -151,11 +225,11 @@ struct KInfo {
     const int t = Topo::btype[b];
     if (t == B_POSE) return anc(j, flink(Topo::bfa[b])) ? 1 : 0;
     if (t == B_AXIS) return (anc(j, flink(Topo::bfa[b])) && Topo::jtype[j] == REV) ? 1 : 0;
-    if (t == B_REL) {
+    if (t == B_REL || t == B_DIST) {
       const bool a = anc(j, flink(Topo::bfa[b])), bb = anc(j, flink(Topo::bfb[b]));
       return a == bb ? 0 : (bb ? 1 : -1);
     }
-    if (t == B_COM) return 1;
+    if (t == B_COM || t == B_HULL) return 1;
     return 0;
   }
   static constexpr int row_block(int r) {
@@ -178,14 +252,24 @@ struct KInfo {
     }
     return k;
   }
-  // row r is structurally nonzero in column j
-  static constexpr bool rdep(int r, int j) {
+  // row r is structurally nonzero in column j (tabulated once: the pattern computations below
+  // query it many times)
+  static constexpr bool rdep_eval(int r, int j) {
     const int b = row_block(r);
     if (dep(b, j) == 0) return false;
     const int t = Topo::btype[b];
     if ((t == B_POSE || t == B_REL) && row_comp(r) >= 3 && Topo::jtype[j] == PRI) return false;
     return true;
   }
+  struct RD { bool v[MAXM][MAXJ]; };
+  static constexpr RD rd_table() {
+    RD t{};
+    for (int r = 0; r < M; ++r)
+      for (int j = 0; j < NJ; ++j) t.v[r][j] = rdep_eval(r, j);
+    return t;
+  }
+  static constexpr RD RDT = rd_table();
+  static constexpr bool rdep(int r, int j) { return RDT.v[r][j]; }
   static constexpr bool gnz(int r1, int r2) {
     for (int j = 0; j < NJ; ++j)
       if (rdep(r1, j) && rdep(r2, j)) return true;
@@ -216,8 +300,19 @@ struct KInfo {
   static constexpr int complete_link(int b) {
     const int t = Topo::btype[b];
     if (t == B_POSE || t == B_AXIS) return flink(Topo::bfa[b]);
-    if (t == B_REL) return flink(Topo::bfa[b]) > flink(Topo::bfb[b]) ? flink(Topo::bfa[b]) : flink(Topo::bfb[b]);
+    if (t == B_REL || t == B_DIST)
+      return flink(Topo::bfa[b]) > flink(Topo::bfb[b]) ? flink(Topo::bfa[b]) : flink(Topo::bfb[b]);
     return NJ - 1;
+  }
+  // rows that may be dropped per lane (bounded pose components, polygon rows)
+  static constexpr bool droppable(int b) {
+    return Topo::btype[b] == B_HULL || (Topo::btype[b] == B_POSE && (Topo::bflags[b] & BF_BOUNDED));
+  }
+  static constexpr uint32_t drop_rows() {
+    uint32_t m = 0;
+    for (int b = 0; b < NB; ++b)
+      if (droppable(b)) m |= brmask(b);
+    return m;
   }
 };
 
@@ -240,6 +335,7 @@ struct Kin {
   static constexpr int NBLK = NB;                  // constraint blocks (the cyclic mode steps them in order)
   static constexpr uint32_t ALL = ~uint32_t(0);
   static constexpr uint32_t block_rows_mask(int b) { return KI::brmask(b); }
+  static constexpr uint32_t DROPPABLE = KI::drop_rows();  // rows a lane may drop (see the header)
   template <uint32_t RM>
   static constexpr bool sel(int b) { return (KI::brmask(b) & RM) != 0; }
   static constexpr bool in_rows(uint32_t rm, int r) { return (rm >> r) & 1u; }
@@ -251,9 +347,25 @@ struct Kin {
     S pend[NB][3];    // end point of pose / relative-pose blocks
     S W[NB][9];       // REL: (R_a R_ref)^T
     S A[NB][9];       // J_l^-1(w) W
-    S u[NB][3];       // AXIS: frame z axis
+    S u[NB][3];       // AXIS: frame z axis; DIST: unit vector from end a to end b
+    S pa[NB][3];      // DIST: end a (pend holds end b)
+    S H[NB][4];       // HULL: the lane's 2 x 2 row map (row-major)
     S Qe[NJ + 1][3];  // prefix sums of m_l c_l at the subtree ends
+    uint32_t drop = 0;  // rows dropped in this lane (bits of DROPPABLE)
   };
+
+  // Take the base point's choice of rows (dropped rows, polygon row map) into sd: the rows are then
+  // the smooth piece that is active at the base point, which the central differences of the exact
+  // VJP must differentiate even where a shifted point lies across a region boundary.
+  template <class S>
+  static __device__ __forceinline__ void freeze_rows(SD<S>& sd, const SD<S>& base) {
+    sd.drop = base.drop;
+    sfor<0, NB>([&](auto BI) {
+      constexpr int b = decltype(BI)::value;
+      if constexpr (Topo::btype[b] == B_HULL)
+        for (int k = 0; k < 4; ++k) sd.H[b][k] = base.H[b][k];
+    });
+  }
 
   // Joint coordinate in the pass precision. FP32 passes take revolute angles reduced to
   // [-pi, pi] in FP64 first, so large angles keep full FP32 accuracy in sine and cosine.
@@ -372,12 +484,30 @@ struct Kin {
     });
   }
 
+  // rows of a pose error with finite bounds: each component's excess over [lo, hi], dropped inside
+  template <int b, class S>
+  static __device__ __forceinline__ void put_bounded_rows(const double* t, const double* w, const TP<double>& Pd,
+                                                          S* F, double& n2, uint32_t& drop) {
+    constexpr int r0 = KI::brow0(b);
+    sfor<0, KI::brows(b)>([&](auto K) {
+      constexpr int r = r0 + decltype(K)::value;
+      constexpr int c = KI::row_comp(r);
+      const double v = c < 3 ? t[c] : w[c - 3];
+      const double lo = Pd.blo[b][c], hi = Pd.bhi[b][c];
+      const double e = v > hi ? v - hi : (v < lo ? v - lo : 0.0);
+      const bool in = !(v > hi) && !(v < lo);
+      drop = in ? (drop | (1u << r)) : (drop & ~(1u << r));
+      F[r] = S(e);
+      n2 += e * e;
+    });
+  }
+
   template <class S, int b>
   static __device__ __forceinline__ void block_rows(const Rig<double>* Fr, const Consts& P0, S* F, double& n2, SD<S>& sd) {
     constexpr int t = Topo::btype[b];
     constexpr int r0 = KI::brow0(b);
     // the block's constants are read only once its frames exist
-    constexpr int flast = (t == B_REL) ? Topo::bfb[b] : Topo::bfa[b];
+    constexpr int flast = (t == B_REL || t == B_DIST) ? Topo::bfb[b] : Topo::bfa[b];
     const Consts& P = after_cp(P0, Fr[flast < 0 ? 0 : flast].p[2]);
     if constexpr (t == B_POSE) {
       constexpr int fa = Topo::bfa[b];
@@ -387,7 +517,8 @@ struct Kin {
       matvec3(Rt, dp, tt);
       matmul3(Rt, Fr[fa].R, Re);
       so3_log_jlinv(Re, w, Jl);
-      put_pose_rows<b>(tt, w, F, n2);
+      if constexpr ((Topo::bflags[b] & BF_BOUNDED) != 0) put_bounded_rows<b>(tt, w, P.d, F, n2, sd.drop);
+      else put_pose_rows<b>(tt, w, F, n2);
       matmul3(Jl, Rt, A);
       for (int k = 0; k < 3; ++k) sd.pend[b][k] = S(Fr[fa].p[k]);
       for (int k = 0; k < 9; ++k) sd.A[b][k] = S(A[k]);
@@ -410,6 +541,19 @@ struct Kin {
       for (int k = 0; k < 3; ++k) sd.pend[b][k] = S(Fr[fb].p[k]);
       for (int k = 0; k < 9; ++k) sd.W[b][k] = S(W[k]);
       for (int k = 0; k < 9; ++k) sd.A[b][k] = S(A[k]);
+    } else if constexpr (t == B_DIST) {
+      constexpr int fa = Topo::bfa[b], fb = Topo::bfb[b];
+      const double dv[3] = {Fr[fb].p[0] - Fr[fa].p[0], Fr[fb].p[1] - Fr[fa].p[1], Fr[fb].p[2] - Fr[fa].p[2]};
+      const double len = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+      const double e = len - P.d.target[b][0];
+      F[r0] = S(e);
+      n2 += e * e;
+      const double il = 1.0 / len;
+      for (int k = 0; k < 3; ++k) {
+        sd.u[b][k] = S(dv[k] * il);
+        sd.pend[b][k] = S(Fr[fb].p[k]);
+        sd.pa[b][k] = S(Fr[fa].p[k]);
+      }
     } else if constexpr (t == B_AXIS) {
       constexpr int fa = Topo::bfa[b];
       F[r0] = S(Fr[fa].R[2]);
@@ -419,6 +563,60 @@ struct Kin {
       sd.u[b][1] = S(Fr[fa].R[5]);
       sd.u[b][2] = S(Fr[fa].R[8]);
     }
+  }
+
+  // Polygon rows of the CoM point (x, y): the nearest point of the polygon's boundary, edge by edge
+  // (projection onto each segment, clamped to its ends). Inside (left of every edge): both rows
+  // dropped. Nearest point inside an edge: rows [n.(x - c), 0] in the edge's frame, the second
+  // dropped, row map H = [n; 0]. Nearest point a vertex v: rows x - v, H = I.
+  template <class S, int b>
+  static __device__ __forceinline__ void hull_rows(double x, double y, const Consts& P, S* F, double& n2, SD<S>& sd) {
+    constexpr int r0 = KI::brow0(b);
+    const int nv = P.hull_nv;
+    bool inside = true, on_edge = false;
+    double best = 1e300, bx = 0.0, by = 0.0, bnx = 0.0, bny = 0.0;
+    for (int i = 0; i < MAXHV; ++i) {
+      if (i < nv) {
+        const double* e = P.d.hull_e[i];
+        const double* nn = P.d.hull_n[i];
+        const double dx = x - e[0], dy = y - e[1];
+        inside = inside && (e[2] * dy - e[3] * dx >= 0.0);
+        const double t = (dx * e[2] + dy * e[3]) * nn[2];
+        const double tc = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+        const double cx = e[0] + tc * e[2], cy = e[1] + tc * e[3];
+        const double d2 = (x - cx) * (x - cx) + (y - cy) * (y - cy);
+        if (d2 < best) {
+          best = d2;
+          bx = cx;
+          by = cy;
+          on_edge = t > 0.0 && t < 1.0;
+          bnx = nn[0];
+          bny = nn[1];
+        }
+      }
+    }
+    double f0, f1, h[4];
+    uint32_t dm;
+    if (inside) {
+      f0 = f1 = 0.0;
+      h[0] = h[1] = h[2] = h[3] = 0.0;
+      dm = 3u;
+    } else if (on_edge) {
+      f0 = bnx * (x - bx) + bny * (y - by);
+      f1 = 0.0;
+      h[0] = bnx; h[1] = bny; h[2] = 0.0; h[3] = 0.0;
+      dm = 2u;
+    } else {
+      f0 = x - bx;
+      f1 = y - by;
+      h[0] = 1.0; h[1] = 0.0; h[2] = 0.0; h[3] = 1.0;
+      dm = 0u;
+    }
+    F[r0] = S(f0);
+    F[r0 + 1] = S(f1);
+    n2 += f0 * f0 + f1 * f1;
+    for (int k = 0; k < 4; ++k) sd.H[b][k] = S(h[k]);
+    sd.drop = (sd.drop & ~(3u << r0)) | (dm << r0);
   }
 
   // Residual pass in FP64: returns ||F(q)||^2 (FP64); F in the step precision S and the
@@ -462,6 +660,9 @@ struct Kin {
         F[r0] = S(e0);
         F[r0 + 1] = S(e1);
         n2 += e0 * e0 + e1 * e1;
+      } else if constexpr (Topo::btype[b] == B_HULL && sel<RM>(b)) {
+        const TP<double>& Pd = after_cp(P.d, cm[1]);
+        hull_rows<S, b>(cm[0] * Pd.inv_total_mass, cm[1] * Pd.inv_total_mass, P, F, n2, sd);
       }
     });
     return n2;
@@ -497,25 +698,46 @@ struct Kin {
           constexpr int c = KI::row_comp(r);
           if constexpr (KI::rdep(r, j)) {
             const S v = c < 3 ? lin[c] : ang[c - 3];
-            col[r] = sg > 0 ? v : -v;
+            if constexpr (((DROPPABLE >> r) & 1u) != 0) col[r] = ((sd.drop >> r) & 1u) ? S(0) : (sg > 0 ? v : -v);
+            else col[r] = sg > 0 ? v : -v;
           }
         });
+      } else if constexpr (sg != 0 && t == B_DIST) {
+        S v;
+        if constexpr (rev) {
+          const S* pe = sg > 0 ? sd.pend[b] : sd.pa[b];
+          const S r[3] = {pe[0] - o[0], pe[1] - o[1], pe[2] - o[2]};
+          S tv[3];
+          cross3(z, r, tv);
+          v = sd.u[b][0] * tv[0] + sd.u[b][1] * tv[1] + sd.u[b][2] * tv[2];
+        } else {
+          v = sd.u[b][0] * z[0] + sd.u[b][1] * z[1] + sd.u[b][2] * z[2];
+        }
+        col[r0] = sg > 0 ? v : -v;
       } else if constexpr (sg != 0 && t == B_AXIS) {
         col[r0] = z[1] * sd.u[b][2] - z[2] * sd.u[b][1];
         col[r0 + 1] = z[2] * sd.u[b][0] - z[0] * sd.u[b][2];
-      } else if constexpr (sg != 0 && t == B_COM) {
+      } else if constexpr (sg != 0 && (t == B_COM || t == B_HULL)) {
         constexpr int e = KI::sub_end(j);
         const S iM = T.inv_total_mass;
+        S c0, c1;
         if constexpr (rev) {
           const S Mj = T.submass[j];
           S Sp[3];
           for (int k = 0; k < 3; ++k) Sp[k] = sd.Qe[e][k] - Qr[k] - Mj * o[k];
-          col[r0] = (z[1] * Sp[2] - z[2] * Sp[1]) * iM;
-          col[r0 + 1] = (z[2] * Sp[0] - z[0] * Sp[2]) * iM;
+          c0 = (z[1] * Sp[2] - z[2] * Sp[1]) * iM;
+          c1 = (z[2] * Sp[0] - z[0] * Sp[2]) * iM;
         } else {
           const S f = T.submass[j] * iM;
-          col[r0] = z[0] * f;
-          col[r0 + 1] = z[1] * f;
+          c0 = z[0] * f;
+          c1 = z[1] * f;
+        }
+        if constexpr (t == B_COM) {
+          col[r0] = c0;
+          col[r0 + 1] = c1;
+        } else {
+          col[r0] = sd.H[b][0] * c0 + sd.H[b][1] * c1;
+          col[r0 + 1] = sd.H[b][2] * c0 + sd.H[b][3] * c1;
         }
       }
     });

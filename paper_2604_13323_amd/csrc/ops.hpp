@@ -116,6 +116,8 @@ MC_FAMILY_TABLE(planar2)
 MC_FAMILY_TABLE(arm7_axis)
 MC_FAMILY_TABLE(dual14_rel)
 MC_FAMILY_TABLE(humanoid36)
+MC_FAMILY_TABLE(digit36)
+MC_FAMILY_TABLE(arm7_tsr)
 #undef MC_FAMILY_TABLE
 
 }  // namespace mc

@@ -45,6 +45,7 @@ struct SphereModel {
   static constexpr int D = 3, M = 1;
   static constexpr bool fixed_dof = false;  // the scene's d (at most D) is read at run time
   static constexpr int NBLK = 1;
+  static constexpr uint32_t DROPPABLE = 0;  // no row is ever dropped
   static constexpr uint32_t ALL = ~uint32_t(0);
   static constexpr uint32_t block_rows_mask(int) { return ALL; }
   static constexpr bool lnz(int, int) { return true; }
@@ -110,6 +111,7 @@ struct LinearModel {
   static constexpr int D = LIN_D, M = LIN_M;
   static constexpr bool fixed_dof = false;  // the scene's d (at most D) is read at run time
   static constexpr int NBLK = 1;
+  static constexpr uint32_t DROPPABLE = 0;  // no row is ever dropped
   static constexpr uint32_t ALL = ~uint32_t(0);
   static constexpr uint32_t block_rows_mask(int) { return ALL; }
   static constexpr bool lnz(int, int) { return true; }

@@ -29,9 +29,9 @@ def _ancestor(parents, j, l):
 def _block_rows(b, m_total):
     if b.btype in (S.BLK_POSE, S.BLK_REL):
         return bin(b.mask & 0x3F).count("1")
-    if b.btype in (S.BLK_AXIS, S.BLK_COM):
+    if b.btype in (S.BLK_AXIS, S.BLK_COM, S.BLK_HULL):
         return 2
-    if b.btype == S.BLK_SPHERE:
+    if b.btype in (S.BLK_SPHERE, S.BLK_DIST):
         return 1
     return m_total
 
@@ -49,7 +49,7 @@ def jacobian_pattern(sc: S.Scene) -> np.ndarray:
                 jt = sc.joints[j].jtype
                 if b.btype == S.BLK_POSE:
                     dep = _ancestor(parents, j, sc.frames[b.fa].link)
-                elif b.btype == S.BLK_REL:
+                elif b.btype in (S.BLK_REL, S.BLK_DIST):
                     dep = _ancestor(parents, j, sc.frames[b.fa].link) != _ancestor(parents, j, sc.frames[b.fb].link)
                 elif b.btype == S.BLK_AXIS:
                     dep = _ancestor(parents, j, sc.frames[b.fa].link) and jt == S.JOINT_REV
@@ -118,6 +118,11 @@ def iteration_flops(sc: S.Scene) -> dict:
         elif b.btype == S.BLK_COM:
             res += 24 * massive + 4
             cols += 6 * massive
+        elif b.btype == S.BLK_HULL:  # CoM sums, then per polygon edge: side test, clamp, distance
+            res += 24 * massive + 4 + 20 * b.aux
+            cols += 6 * massive
+        elif b.btype == S.BLK_DIST:  # difference, length, reciprocal, unit vector
+            res += 3 + 5 + 1 + 3
     res += 2 * m  # norm
     r = 0
     for b in sc.blocks:
@@ -133,6 +138,10 @@ def iteration_flops(sc: S.Scene) -> dict:
                 cols += 6
             elif b.btype == S.BLK_COM:
                 cols += 17 if rev else 3
+            elif b.btype == S.BLK_HULL:  # the CoM column and its 2 x 2 row map
+                cols += (17 if rev else 3) + 6
+            elif b.btype == S.BLK_DIST:  # u . (z x r) or u . z
+                cols += 20 if rev else 5
         r += nr
     nnz_col = Jp.sum(axis=0)
     gram = int(sum(2 * k * (k + 1) // 2 for k in nnz_col))
