@@ -145,7 +145,10 @@ def other_workloads(M, S, FL, torch, steps):
             q, _, _ = build_batch(G, cfg, torch)
         n = q.shape[1]
         kw = dict(tol=cfg["tol"], max_iter=cfg["max_iter"])
+        G.fallback_count(reset=True)
         out = G.project(q, variant="fused", **kw)
+        torch.cuda.synchronize()
+        fallbacks = G.fallback_count(reset=True)  # configurations continued in FP64 in one step
         ms = timed(lambda: G.project(q, variant="fused", out=out, **kw), steps, 2, torch)
         st = out.status.cpu().numpy()
         it = out.iters.cpu().numpy().astype(np.int64)
@@ -156,7 +159,7 @@ def other_workloads(M, S, FL, torch, steps):
                           converged_frac=float(conv.mean()), iters_mean=float(it.mean()),
                           iters_p99=float(np.percentile(it, 99)),
                           collision_free_frac_of_converged=float((vd[conv] == 0).mean()) if conv.any() else None,
-                          fp64_fallbacks=G.fallback_count(reset=True),
+                          fp64_fallbacks_per_step=fallbacks, fp64_fallback_frac=fallbacks / n,
                           tflops_algorithmic=FL.batch_flops(sc, it) / (ms * 1e-3) / 1e12,
                           hbm_gbs_algorithmic=byts / (ms * 1e-3) / 1e9)
         log(f"{name}: {n} configurations, {ms:.3f} ms/step, {rows[name]['converged_per_s']:.4g} converged/s")

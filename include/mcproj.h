@@ -197,7 +197,11 @@ mc_status project_batch_noalloc(const mc_problem* p, int64_t n,
    spheres, collision when ||c_i - o_j||^2 < (r_i + r_j)^2 for some pair).
    verdict uint8[n]: MC_FREE or MC_COLLIDES. min_signed_dist (nullable, dtype[n]): minimum over
    all pairs of ||c_i - o_j|| - (r_i + r_j) (+inf without geometry); requesting it forces the
-   exhaustive pair loop. */
+   exhaustive pair loop. Without it, the kinematic families run the broad phase of the fused
+   projection (link bounds against the box around all obstacles) and the exact pair tests only for
+   the configurations it flags, through the problem's check queue: that queue grows to the largest
+   batch seen like project_batch's (a growth allocates and synchronises; a call of the same or a
+   smaller size allocates nothing), and calls on one handle must not overlap. */
 mc_status check_batch(const mc_problem* p, int64_t n, const void* q, int64_t ld, mc_dtype dtype,
                       uint8_t* verdict, void* min_signed_dist, void* stream);
 

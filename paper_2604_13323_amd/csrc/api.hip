@@ -1274,8 +1274,30 @@ mc_status check_batch(const mc_problem* p, int64_t n, const void* q, int64_t ld,
   c.status = nullptr;
   c.verdict = verdict;
   c.minsd = min_signed_dist;
-  hipError_t e = ops->check(c, min_signed_dist != nullptr, static_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return hip_fail(e, "check_batch: launch");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (min_signed_dist || !ops->check_broad || !ops->check_tail) {
+    if ((e = ops->check(c, min_signed_dist != nullptr, s)) != hipSuccess) return hip_fail(e, "check_batch: launch");
+    return MC_OK;
+  }
+  // verdicts only: the broad phase of the fused projection, then the exact-check tail on the
+  // configurations it queues (the problem's queue, grown to the largest batch seen)
+  if ((e = grow_defer(p, n, ops->dof_max)) != hipSuccess) return hip_fail(e, "check_batch: queue allocation");
+  ProjArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.P = p->dev;
+  a.verdict = verdict;
+  a.chk_count = p->counter + 3;
+  a.chk_idx = p->chk_idx;
+  a.chk_q = p->chk_q;
+  a.defer_cap = p->defer_cap;
+  a.n_sph = p->n_sph;
+  a.n_obs = p->n_obs;
+  hipLaunchKernelGGL(k_reset_u32, dim3(1), dim3(64), 0, s, p->counter + 3, 1);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "check_batch: reset");
+  if ((e = ops->check_broad(c, a.chk_count, a.chk_idx, a.chk_q, a.defer_cap, s)) != hipSuccess)
+    return hip_fail(e, "check_batch: broad-phase launch");
+  if ((e = ops->check_tail(a, 4 * p->n_cu, s)) != hipSuccess) return hip_fail(e, "check_batch: exact-check launch");
   return MC_OK;
 }
 

@@ -352,8 +352,8 @@ __device__ __forceinline__ void store_result(const ProjArgs& a, int dof, int64_t
 // Dynamic LDS: D * blockDim doubles.
 // Append the calling lane's FP64 configuration to a queue (slot < defer_cap: the queues are
 // sized for the batch).
-template <class Model>
-__device__ __forceinline__ unsigned queue_q(const QLds& q, unsigned* count, double* qbuf, int64_t cap) {
+template <class Model, class Q>
+__device__ __forceinline__ unsigned queue_q(const Q& q, unsigned* count, double* qbuf, int64_t cap) {
   const unsigned slot = atomicAdd(count, 1u);
   double* dst = qbuf + slot;
   for (int c = 0; c < Model::D; ++c) {
@@ -596,6 +596,25 @@ __global__ void __launch_bounds__(256) k_check(CheckArgs a) {
     const bool hit = Model::template check_group<L>(q, C, K, K.sph, obs_of(a.P));
     if (lead) a.verdict[i] = hit ? V_HIT : V_FREE;
   }
+}
+
+// check_batch without distances, first pass: one lane per configuration, the FP32 walk of the link
+// bounds against the box around all obstacles (the same broad phase as the fused projection). A
+// configuration with no link near the box is FREE; the others are marked FREE and queued (index,
+// FP64 configuration) for k_check_tail, which overwrites the verdict of those it finds colliding.
+template <class Model, class IO>
+__global__ void __launch_bounds__(256) k_check_broad(CheckArgs a, unsigned* count, int32_t* idx, double* qbuf,
+                                                     int64_t cap) {
+  const Consts& C = consts_of(a.P);
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  if (a.status && a.status[i] != ST_CONVERGED) {
+    a.verdict[i] = V_UNCHECKED;
+    return;
+  }
+  const QGlob<IO> q{static_cast<const IO*>(a.q), a.ld, i, dof_of<Model>(C)};
+  a.verdict[i] = V_FREE;
+  if (Model::broad_flag(q, C)) idx[queue_q<Model>(q, count, qbuf, cap)] = int32_t(i);
 }
 
 struct VjpArgs {

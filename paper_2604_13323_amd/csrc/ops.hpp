@@ -22,6 +22,10 @@ struct FamilyOps {
   hipError_t (*project_tail)(const ProjArgs& a, int grid, hipStream_t s);  // FP32 mode only
   hipError_t (*check_tail)(const ProjArgs& a, int grid, hipStream_t s);
   hipError_t (*check)(const CheckArgs& a, int minsd, hipStream_t s);
+  // check_batch's broad phase (verdicts only), whose queue check_tail finishes; null where the
+  // model has no broad phase
+  hipError_t (*check_broad)(const CheckArgs& a, unsigned* count, int32_t* idx, double* qbuf, int64_t cap,
+                            hipStream_t s);
   hipError_t (*vjp)(const VjpArgs& a, hipStream_t s);
   hipError_t (*vjp_tail)(const VjpArgs& a, int grid, hipStream_t s);  // FP32 mode only
   hipError_t (*vjp_exact)(const VjpxArgs& a, hipStream_t s);
@@ -53,6 +57,8 @@ struct OpsImpl {
   static hipError_t check_tail(const ProjArgs& a, int grid, hipStream_t s);
   static hipError_t vjp_tail(const VjpArgs& a, int grid, hipStream_t s);
   static hipError_t check(const CheckArgs& a, int minsd, hipStream_t s);
+  static hipError_t check_broad(const CheckArgs& a, unsigned* count, int32_t* idx, double* qbuf, int64_t cap,
+                                hipStream_t s);
   static hipError_t vjp(const VjpArgs& a, hipStream_t s);
   static hipError_t vjp_exact(const VjpxArgs& a, hipStream_t s);
   static hipError_t eval_fj(const DevProblem* P, int64_t n, const void* q, int64_t ld, void* F, void* J, hipStream_t s);
@@ -95,7 +101,11 @@ struct OpsImpl {
       o.vjp_tail = &vjp_tail;
     }
     o.check_tail = nullptr;
-    if constexpr (Model::broad_in_residual) o.check_tail = &check_tail;
+    o.check_broad = nullptr;
+    if constexpr (Model::broad_in_residual) {
+      o.check_tail = &check_tail;
+      o.check_broad = &check_broad;
+    }
     o.check = &check;
     o.vjp = &vjp;
     o.vjp_exact = &vjp_exact;

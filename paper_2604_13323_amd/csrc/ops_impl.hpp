@@ -67,6 +67,16 @@ hipError_t OpsImpl<Model, IO, S>::check(const CheckArgs& a, int minsd, hipStream
   return hipGetLastError();
 }
 template <class Model, class IO, class S>
+hipError_t OpsImpl<Model, IO, S>::check_broad(const CheckArgs& a, unsigned* count, int32_t* idx, double* qbuf,
+                                              int64_t cap, hipStream_t s) {
+  if constexpr (Model::broad_in_residual) {
+    hipLaunchKernelGGL((k_check_broad<Model, IO>), dim3(blocks_for(a.n, 256)), dim3(256), 0, s, a, count, idx, qbuf, cap);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;  // not in the launch table of such a model
+  }
+}
+template <class Model, class IO, class S>
 hipError_t OpsImpl<Model, IO, S>::vjp(const VjpArgs& a, hipStream_t s) {
   hipLaunchKernelGGL((k_vjp<Model, IO, S>), dim3(blocks_for(a.n, 64)), dim3(64),
                      lds_bytes(64) + size_t(Model::D) * sizeof(S) * 64, s, a);
@@ -123,7 +133,8 @@ int OpsImpl<Model, IO, S>::persistent_wide_blocks_per_cu() {
 #define MC_INST_TAIL(O) template hipError_t O::project_tail(const mc::ProjArgs&, int, hipStream_t);
 #define MC_INST_CHECK(O)                                                                             \
   template hipError_t O::check_tail(const mc::ProjArgs&, int, hipStream_t);                           \
-  template hipError_t O::check(const mc::CheckArgs&, int, hipStream_t);
+  template hipError_t O::check(const mc::CheckArgs&, int, hipStream_t);                                \
+  template hipError_t O::check_broad(const mc::CheckArgs&, unsigned*, int32_t*, double*, int64_t, hipStream_t);
 #define MC_INST_VJP(O) template hipError_t O::vjp(const mc::VjpArgs&, hipStream_t);
 #define MC_INST_VJP_TAIL(O) template hipError_t O::vjp_tail(const mc::VjpArgs&, int, hipStream_t);
 #define MC_INST_VJP_EXACT(O) template hipError_t O::vjp_exact(const mc::VjpxArgs&, hipStream_t);

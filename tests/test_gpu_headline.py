@@ -96,6 +96,13 @@ def test_long_exact_check_queue_with_hits_matches_oracle(mc):
     vo, _ = check_verdicts(P, r)
     assert vo.mean() > 0.3, vo.mean()
     compare(P, q, r, tol, mi, 1e-4, max_band=0.3)
+    # check_batch on the same outputs: its broad phase queues as many, and the long-queue tail
+    # gives the fused step's verdicts on the converged ones
+    v = G.check(r.q)
+    torch.cuda.synchronize()
+    assert G.queue_counts()[3] >= queued
+    conv = r.status == CONV
+    assert torch.equal(v[conv], r.verdict[conv])
 
 
 def test_short_exact_check_queue_plain_and_check_batch_with_hits(mc):
