@@ -127,6 +127,11 @@ template <class T> struct Rig { T R[9]; T p[3]; };
 // them, which would keep every intermediate live across the solve).
 __device__ __forceinline__ float opaque(float x) { asm volatile("" : "+v"(x)); return x; }
 __device__ __forceinline__ double opaque(double x) { asm volatile("" : "+v"(x)); return x; }
+// Conversion of an FP64 result to the step precision S, pinned where it is written: the compiler
+// would otherwise sink the conversion to the value's uses and keep the FP64 value (two registers)
+// live through the kinematic walks in between.
+template <class S>
+__device__ __forceinline__ S to_step(double x) { return opaque(S(x)); }
 
 // Ordering helper for the unrolled walks: an empty asm that claims to read `dep` and rewrite
 // `x`, so x (and everything computed from it) cannot be scheduled before dep exists. Costs no

@@ -35,7 +35,8 @@
 //   AXIS  (z_j x u)_xy with u = R_f e_z         [0]
 //   COM   (z_j x (S_j - M_j o_j))_xy / M        [(M_j / M) z_j,xy]
 //         S_j = sum of m_l c_l over the subtree of j, M_j its mass.
-//   HULL  H c with c the COM column and H the lane's 2 x 2 row map (edge frame, identity, or 0)
+//   HULL  H c with c the COM column and H the lane's 2 x 2 row map (edge frame, identity, or 0;
+//         its lower-left entry is always 0)
 //   DIST  s_j u.(z_j x (p_e - o_j)), p_e the moving end   [s_j u.z_j],  u = (p_b - p_a) / |p_b - p_a|
 #pragma once
 
@@ -349,7 +350,7 @@ struct Kin {
     S A[NB][9];       // J_l^-1(w) W
     S u[NB][3];       // AXIS: frame z axis; DIST: unit vector from end a to end b
     S pa[NB][3];      // DIST: end a (pend holds end b)
-    S H[NB][4];       // HULL: the lane's 2 x 2 row map (row-major)
+    S H[NB][3];       // HULL: the lane's 2 x 2 row map [h0 h1; 0 h2]
     S Qe[NJ + 1][3];  // prefix sums of m_l c_l at the subtree ends
     uint32_t drop = 0;  // rows dropped in this lane (bits of DROPPABLE)
   };
@@ -363,7 +364,7 @@ struct Kin {
     sfor<0, NB>([&](auto BI) {
       constexpr int b = decltype(BI)::value;
       if constexpr (Topo::btype[b] == B_HULL)
-        for (int k = 0; k < 4; ++k) sd.H[b][k] = base.H[b][k];
+        for (int k = 0; k < 3; ++k) sd.H[b][k] = base.H[b][k];
     });
   }
 
@@ -479,7 +480,7 @@ struct Kin {
     sfor<0, KI::brows(b)>([&](auto K) {
       constexpr int c = KI::row_comp(r0 + decltype(K)::value);
       const double v = c < 3 ? t[c] : w[c - 3];
-      F[r0 + decltype(K)::value] = S(v);
+      F[r0 + decltype(K)::value] = to_step<S>(v);
       n2 += v * v;
     });
   }
@@ -497,7 +498,7 @@ struct Kin {
       const double e = v > hi ? v - hi : (v < lo ? v - lo : 0.0);
       const bool in = !(v > hi) && !(v < lo);
       drop = in ? (drop | (1u << r)) : (drop & ~(1u << r));
-      F[r] = S(e);
+      F[r] = to_step<S>(e);
       n2 += e * e;
     });
   }
@@ -520,8 +521,8 @@ struct Kin {
       if constexpr ((Topo::bflags[b] & BF_BOUNDED) != 0) put_bounded_rows<b>(tt, w, P.d, F, n2, sd.drop);
       else put_pose_rows<b>(tt, w, F, n2);
       matmul3(Jl, Rt, A);
-      for (int k = 0; k < 3; ++k) sd.pend[b][k] = S(Fr[fa].p[k]);
-      for (int k = 0; k < 9; ++k) sd.A[b][k] = S(A[k]);
+      for (int k = 0; k < 3; ++k) sd.pend[b][k] = to_step<S>(Fr[fa].p[k]);
+      for (int k = 0; k < 9; ++k) sd.A[b][k] = to_step<S>(A[k]);
     } else if constexpr (t == B_REL) {
       constexpr int fa = Topo::bfa[b], fb = Topo::bfb[b];
       const double* Rt = P.d.refRt[b];
@@ -538,30 +539,30 @@ struct Kin {
       so3_log_jlinv(Re, w, Jl);
       put_pose_rows<b>(tt, w, F, n2);
       matmul3(Jl, W, A);
-      for (int k = 0; k < 3; ++k) sd.pend[b][k] = S(Fr[fb].p[k]);
-      for (int k = 0; k < 9; ++k) sd.W[b][k] = S(W[k]);
-      for (int k = 0; k < 9; ++k) sd.A[b][k] = S(A[k]);
+      for (int k = 0; k < 3; ++k) sd.pend[b][k] = to_step<S>(Fr[fb].p[k]);
+      for (int k = 0; k < 9; ++k) sd.W[b][k] = to_step<S>(W[k]);
+      for (int k = 0; k < 9; ++k) sd.A[b][k] = to_step<S>(A[k]);
     } else if constexpr (t == B_DIST) {
       constexpr int fa = Topo::bfa[b], fb = Topo::bfb[b];
       const double dv[3] = {Fr[fb].p[0] - Fr[fa].p[0], Fr[fb].p[1] - Fr[fa].p[1], Fr[fb].p[2] - Fr[fa].p[2]};
       const double len = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
       const double e = len - P.d.target[b][0];
-      F[r0] = S(e);
+      F[r0] = to_step<S>(e);
       n2 += e * e;
       const double il = 1.0 / len;
       for (int k = 0; k < 3; ++k) {
-        sd.u[b][k] = S(dv[k] * il);
-        sd.pend[b][k] = S(Fr[fb].p[k]);
-        sd.pa[b][k] = S(Fr[fa].p[k]);
+        sd.u[b][k] = to_step<S>(dv[k] * il);
+        sd.pend[b][k] = to_step<S>(Fr[fb].p[k]);
+        sd.pa[b][k] = to_step<S>(Fr[fa].p[k]);
       }
     } else if constexpr (t == B_AXIS) {
       constexpr int fa = Topo::bfa[b];
-      F[r0] = S(Fr[fa].R[2]);
-      F[r0 + 1] = S(Fr[fa].R[5]);
+      F[r0] = to_step<S>(Fr[fa].R[2]);
+      F[r0 + 1] = to_step<S>(Fr[fa].R[5]);
       n2 += Fr[fa].R[2] * Fr[fa].R[2] + Fr[fa].R[5] * Fr[fa].R[5];
-      sd.u[b][0] = S(Fr[fa].R[2]);
-      sd.u[b][1] = S(Fr[fa].R[5]);
-      sd.u[b][2] = S(Fr[fa].R[8]);
+      sd.u[b][0] = to_step<S>(Fr[fa].R[2]);
+      sd.u[b][1] = to_step<S>(Fr[fa].R[5]);
+      sd.u[b][2] = to_step<S>(Fr[fa].R[8]);
     }
   }
 
@@ -570,15 +571,19 @@ struct Kin {
   // dropped. Nearest point inside an edge: rows [n.(x - c), 0] in the edge's frame, the second
   // dropped, row map H = [n; 0]. Nearest point a vertex v: rows x - v, H = I.
   template <class S, int b>
-  static __device__ __forceinline__ void hull_rows(double x, double y, const Consts& P, S* F, double& n2, SD<S>& sd) {
+  // Each edge's constants are read after the previous edge's distance (scalar loads hoisted ahead
+  // of the kinematic walk would hold registers through it).
+  static __device__ __forceinline__ void hull_rows(double x, double y, const Consts& P0, S* F, double& n2, SD<S>& sd) {
     constexpr int r0 = KI::brow0(b);
+    const Consts& P = after_cp(P0, y);
     const int nv = P.hull_nv;
     bool inside = true, on_edge = false;
     double best = 1e300, bx = 0.0, by = 0.0, bnx = 0.0, bny = 0.0;
     for (int i = 0; i < MAXHV; ++i) {
       if (i < nv) {
-        const double* e = P.d.hull_e[i];
-        const double* nn = P.d.hull_n[i];
+        const TP<double>& Pd = after_cp(P.d, best);
+        const double* e = Pd.hull_e[i];
+        const double* nn = Pd.hull_n[i];
         const double dx = x - e[0], dy = y - e[1];
         inside = inside && (e[2] * dy - e[3] * dx >= 0.0);
         const double t = (dx * e[2] + dy * e[3]) * nn[2];
@@ -595,27 +600,22 @@ struct Kin {
         }
       }
     }
-    double f0, f1, h[4];
-    uint32_t dm;
-    if (inside) {
-      f0 = f1 = 0.0;
-      h[0] = h[1] = h[2] = h[3] = 0.0;
-      dm = 3u;
-    } else if (on_edge) {
-      f0 = bnx * (x - bx) + bny * (y - by);
-      f1 = 0.0;
-      h[0] = bnx; h[1] = bny; h[2] = 0.0; h[3] = 0.0;
-      dm = 2u;
-    } else {
-      f0 = x - bx;
-      f1 = y - by;
-      h[0] = 1.0; h[1] = 0.0; h[2] = 0.0; h[3] = 1.0;
-      dm = 0u;
-    }
-    F[r0] = S(f0);
-    F[r0 + 1] = S(f1);
+    // branch-free: inside, both rows dropped; edge region, [n.(x - c), 0] with the second dropped;
+    // vertex region, x - v
+    const bool vtx = !inside && !on_edge;
+    const double dx = x - bx, dy = y - by;
+    const double f0 = inside ? 0.0 : (on_edge ? bnx * dx + bny * dy : dx);
+    const double f1 = vtx ? dy : 0.0;
+    const double h0 = inside ? 0.0 : (on_edge ? bnx : 1.0);
+    const double h1 = on_edge ? bny : 0.0;
+    const double h3 = vtx ? 1.0 : 0.0;
+    const uint32_t dm = inside ? 3u : (on_edge ? 2u : 0u);
+    F[r0] = to_step<S>(f0);
+    F[r0 + 1] = to_step<S>(f1);
     n2 += f0 * f0 + f1 * f1;
-    for (int k = 0; k < 4; ++k) sd.H[b][k] = S(h[k]);
+    sd.H[b][0] = to_step<S>(h0);
+    sd.H[b][1] = to_step<S>(h1);
+    sd.H[b][2] = to_step<S>(h3);
     sd.drop = (sd.drop & ~(3u << r0)) | (dm << r0);
   }
 
@@ -642,7 +642,7 @@ struct Kin {
           for (int k = 0; k < 3; ++k) cm[k] = opaque(cm[k] + t[k] + jp.m * X.p[k]);
         }
         if constexpr (KI::end_needed(j + 1)) {
-          for (int k = 0; k < 3; ++k) sd.Qe[j + 1][k] = S(cm[k]);
+          for (int k = 0; k < 3; ++k) sd.Qe[j + 1][k] = to_step<S>(cm[k]);
         }
       }
       sfor<0, NB>([&](auto BI) {
@@ -657,8 +657,8 @@ struct Kin {
         const TP<double>& Pd = after_cp(P.d, cm[1]);
         const double e0 = cm[0] * Pd.inv_total_mass - Pd.target[b][0];
         const double e1 = cm[1] * Pd.inv_total_mass - Pd.target[b][1];
-        F[r0] = S(e0);
-        F[r0 + 1] = S(e1);
+        F[r0] = to_step<S>(e0);
+        F[r0 + 1] = to_step<S>(e1);
         n2 += e0 * e0 + e1 * e1;
       } else if constexpr (Topo::btype[b] == B_HULL && sel<RM>(b)) {
         const TP<double>& Pd = after_cp(P.d, cm[1]);
@@ -737,7 +737,7 @@ struct Kin {
           col[r0 + 1] = c1;
         } else {
           col[r0] = sd.H[b][0] * c0 + sd.H[b][1] * c1;
-          col[r0 + 1] = sd.H[b][2] * c0 + sd.H[b][3] * c1;
+          col[r0 + 1] = sd.H[b][2] * c1;
         }
       }
     });
