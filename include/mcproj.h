@@ -111,6 +111,14 @@ typedef struct {
   int32_t lanes_per_config;   /* lanes that share one configuration in the projection kernels:
                                  0 = auto, 1 = one configuration per lane (the only build of the
                                  projection kernels; the check kernels pick their own lane groups) */
+  int32_t step_form;          /* the pseudo-inverse of the descent step (Alg. 2 getDescentStep and
+                                 Sec. IV-A, inner and outer forms): 0 inner,
+                                 alpha J^T (J J^T + lambda I)^-1 F, an m x m factorisation (default);
+                                 1 outer, alpha (J^T J + lambda I)^-1 J^T F, a d x d factorisation
+                                 of the dense J; needs lambda > 0 (J^T J has rank <= m < d), the
+                                 stacked mode, and a family with d <= 16 (MC_ERR_UNSUPPORTED
+                                 otherwise: the 36-DoF factor does not fit a lane's registers).
+                                 For lambda > 0 both forms give the same step up to rounding. */
 } mc_project_opts;
 
 /* Default options (tol 1e-6, max_iter 50, alpha 1, lambda 0, max_step off, threshold 1e6,

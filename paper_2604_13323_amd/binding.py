@@ -34,7 +34,7 @@ class Opts(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("lambda_", ctypes.c_double), ("max_step", ctypes.c_double),
                 ("fp64_cond_threshold", ctypes.c_double), ("check_collision", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("mode", ctypes.c_int32), ("lanes_per_config", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("lanes_per_config", ctypes.c_int32), ("step_form", ctypes.c_int32)]
 
 
 class LaunchShape(ctypes.Structure):
@@ -138,10 +138,12 @@ def _soa(q: torch.Tensor, d: int, name: str):
 
 
 MODES = {"stacked": 0, "cyclic": 1}
+STEP_FORMS = {"inner": 0, "outer": 1}
 
 
 def make_opts(dtype=MC_F32, tol=1e-6, max_iter=50, alpha=1.0, lam=0.0, max_step=0.0, cond=1e6, check=True,
-              variant="auto", waves_per_block=0, blocks_per_cu=0, mode="stacked", lanes_per_config=0) -> Opts:
+              variant="auto", waves_per_block=0, blocks_per_cu=0, mode="stacked", lanes_per_config=0,
+              step_form="inner") -> Opts:
     o = Opts()
     lib().mc_default_opts(ctypes.byref(o))
     o.dtype = dtype
@@ -157,6 +159,7 @@ def make_opts(dtype=MC_F32, tol=1e-6, max_iter=50, alpha=1.0, lam=0.0, max_step=
     o.blocks_per_cu = blocks_per_cu
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.lanes_per_config = lanes_per_config
+    o.step_form = STEP_FORMS[step_form] if isinstance(step_form, str) else int(step_form)
     return o
 
 
@@ -204,7 +207,7 @@ class Problem:
     def project(self, q: torch.Tensor, tol=1e-6, max_iter=50, alpha=1.0, lam=0.0, max_step=0.0, cond=1e6,
                 check=True, variant="auto", geo_offsets=None, geo_ok=False, waves_per_block=0, blocks_per_cu=0,
                 out: ProjectResult | None = None, geo_offsets_host=None, mode="stacked",
-                lanes_per_config=0, noalloc=False) -> ProjectResult:
+                lanes_per_config=0, noalloc=False, step_form="inner") -> ProjectResult:
         """Project the columns of q ([d, n], float32 or float64). geo_offsets (CSR, int32) may be a host array
         or a device tensor; the plain variant also needs them on the host (geo_offsets_host, or a host
         geo_offsets). Under stream capture pass device offsets, `out`, and call once eagerly beforehand with a
@@ -238,7 +241,7 @@ class Problem:
             if geo_ok and out.geo_ok is None:
                 out.geo_ok = torch.empty(n_geo, dtype=torch.uint8, device=dev)
         o = make_opts(dt, tol, max_iter, alpha, lam, max_step, cond, check, variant, waves_per_block, blocks_per_cu,
-                      mode, lanes_per_config)
+                      mode, lanes_per_config, step_form)
         fn = lib().project_batch_noalloc if noalloc else lib().project_batch
         rc = fn(self._h, n, _ptr(q), ld, _ptr(out.q), out.q.stride(0), _ptr(out.status),
                                  _ptr(out.iters), _ptr(out.resid), _ptr(out.verdict), _ptr(offs_dev),

@@ -815,6 +815,7 @@ void mc_default_opts(mc_project_opts* o) {
   o->blocks_per_cu = 0;
   o->mode = 0;
   o->lanes_per_config = 0;
+  o->step_form = 0;
 }
 
 int32_t mc_problem_dof(const mc_problem* p) { return p ? p->d : -1; }
@@ -1040,7 +1041,13 @@ static mc_status check_opts(const mc_problem* p, const mc_project_opts* o) {
   if (o->mode == 1 && o->variant == 1) return fail(MC_ERR_UNSUPPORTED, "the cyclic mode runs in the fused variant only");
   if (o->lanes_per_config != 0 && o->lanes_per_config != 1)
     return fail(MC_ERR_UNSUPPORTED, "lanes_per_config must be 0 (auto) or 1");
-  (void)p;
+  if (o->step_form != 0 && o->step_form != 1) return fail(MC_ERR_INVALID_ARG, "step_form must be 0 (inner) or 1 (outer)");
+  if (o->step_form == 1) {
+    if (!(o->lambda > 0)) return fail(MC_ERR_INVALID_ARG, "the outer step form needs lambda > 0");
+    if (o->mode != 0) return fail(MC_ERR_UNSUPPORTED, "the outer step form runs in the stacked mode only");
+    const FamilyOps* ops = ops_for(p->family, o->dtype == MC_F64);
+    if (!ops || ops->dof_max > kOuterMaxD) return fail(MC_ERR_UNSUPPORTED, "the outer step form needs d <= 16");
+  }
   return MC_OK;
 }
 
@@ -1139,6 +1146,7 @@ static mc_status project_impl(const mc_problem* p, int64_t n, const void* q_in, 
   a.cond_thr = opts->fp64_cond_threshold;
   a.max_iter = opts->max_iter;
   a.check = opts->check_collision;
+  a.outer = opts->step_form;
   a.counter = counter;
   a.n_sph = p->n_sph;
   a.n_obs = p->n_obs;

@@ -41,6 +41,7 @@ struct ProjArgs {
   double tol2, alpha, lambda, max_step, cond_thr;
   int32_t max_iter;
   int32_t check;
+  int32_t outer;          // 1: the outer form of the step, (J^T J + lambda I)^-1 J^T F (families with D <= kOuterMaxD)
   unsigned int* counter;  // persistent: queue head (reset to 0 before the launch)
   int64_t n_static;       // persistent: configurations [0, n_static) are taken by thread id
   // FP32 mode: configurations whose FP32 step fails (factorisation or condition estimate) are
@@ -184,6 +185,98 @@ __device__ __forceinline__ bool descent_step(const Q& q, S* rhs, const typename 
   return true;
 }
 
+// ------------------------------------------------------------------ outer form of the step
+// The step's alternative form (Alg. 2 getDescentStep; Sec. IV-A provides the inner and the outer
+// pseudo-inverse): dq = (J^T J + lambda I)^-1 J^T F, a d x d system, for lambda > 0. Built for the
+// families with d <= kOuterMaxD, whose dense J and packed d x d factor fit a lane's registers.
+constexpr int kOuterMaxD = 16;
+
+// Dense packed-lower Cholesky of an N x N matrix in place (all entries), with the same conventions
+// as cholesky(): false on a pivot <= floor or non-finite; invd = 1 / L_ii; kappa = (max / min L_ii)^2.
+template <int N, class S>
+__device__ __forceinline__ bool dense_cholesky(S* A, S* invd, S& kappa, S floor) {
+  bool ok = true;
+  S dmin = S(3.0e38), dmax = S(0);
+  sfor<0, N>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    const S d = A[pidx(k, k)];
+    ok = ok && (d > floor) && finite_t(d);
+    const S r = rsqrt_t(d);
+    const S l = d * r;
+    A[pidx(k, k)] = l;
+    invd[k] = r;
+    dmin = l < dmin ? l : dmin;
+    dmax = l > dmax ? l : dmax;
+    sfor<k + 1, N>([&](auto I) { A[pidx(decltype(I)::value, k)] *= r; });
+    sfor<k + 1, N>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      sfor<k + 1, i + 1>([&](auto Jx) {
+        constexpr int j = decltype(Jx)::value;
+        A[pidx(i, j)] -= A[pidx(i, k)] * A[pidx(j, k)];
+      });
+    });
+  });
+  const S ratio = dmax / dmin;
+  kappa = ratio * ratio;
+  return ok && finite_t(kappa);
+}
+
+template <int N, class S>
+__device__ __forceinline__ void dense_solve(const S* L, const S* invd, S* y) {
+  sfor<0, N>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    S acc = y[i];
+    sfor<0, i>([&](auto K) { acc -= L[pidx(i, decltype(K)::value)] * y[decltype(K)::value]; });
+    y[i] = acc * invd[i];
+  });
+  sfor<0, N>([&](auto I) {
+    constexpr int i = N - 1 - decltype(I)::value;
+    S acc = y[i];
+    sfor<i + 1, N>([&](auto K) { acc -= L[pidx(decltype(K)::value, i)] * y[decltype(K)::value]; });
+    y[i] = acc * invd[i];
+  });
+}
+
+// dq = (J^T J + lambda I)^-1 J^T rhs with the dense Jacobian of the step pass (dropped rows are zero
+// rows of J and need no special case: lambda > 0 keeps the d x d matrix positive definite).
+template <class Model, class S, class Q>
+__device__ __forceinline__ bool descent_step_outer(const Q& q, const S* rhs, const typename Model::template SD<S>& sd,
+                                                   const Consts& C, double lambda, double cond_thr, S floor_rel, S* dq) {
+  constexpr int D = Model::D, M = Model::M;
+  S J[M * D];
+  Model::template jacobian<S>(q, C, sd, J);
+  S A[D * (D + 1) / 2];
+  S maxd = S(0);
+  sfor<0, D>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    sfor<0, i + 1>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      S acc = (i == k) ? S(lambda) : S(0);
+      for (int r = 0; r < M; ++r) acc += J[r * D + i] * J[r * D + k];
+      A[pidx(i, k)] = acc;
+    });
+    maxd = A[pidx(i, i)] > maxd ? A[pidx(i, i)] : maxd;
+    S b = S(0);
+    for (int r = 0; r < M; ++r) b += J[r * D + i] * rhs[r];
+    dq[i] = b;
+  });
+  S invd[D], kappa;
+  if (!dense_cholesky<D, S>(A, invd, kappa, floor_rel * maxd)) return false;
+  if (!(double(kappa) <= cond_thr)) return false;
+  dense_solve<D, S>(A, invd, dq);
+  return true;
+}
+
+// The step in the form the call asked for.
+template <class Model, class S, class Q>
+__device__ __forceinline__ bool step_of(const Q& q, S* rhs, const typename Model::template SD<S>& sd, const Consts& C,
+                                        const ProjArgs& a, double cond_thr, S floor_rel, S* dq) {
+  if constexpr (Model::D <= kOuterMaxD) {
+    if (a.outer) return descent_step_outer<Model, S>(q, rhs, sd, C, a.lambda, cond_thr, floor_rel, dq);
+  }
+  return descent_step<Model, S>(q, rhs, sd, C, a.lambda, cond_thr, floor_rel, dq);
+}
+
 // Apply dq (scaled by alpha) with the divergence test. Returns -1 after the update or a status.
 template <class Model, class S>
 __device__ __forceinline__ int apply_step(const QLds& q, const S* dq, const ProjArgs& a) {
@@ -217,10 +310,10 @@ __device__ __forceinline__ int newton_iteration(const QLds& q, int& k, const Pro
   S dq[D];
   int st;
   if constexpr (std::is_same<S, float>::value) {
-    if (!descent_step<Model, float>(q, F, sd, C, a.lambda, a.cond_thr, kFloorF32, dq)) return ST_DEFER;
+    if (!step_of<Model, float>(q, F, sd, C, a, a.cond_thr, kFloorF32, dq)) return ST_DEFER;
     st = apply_step<Model, float>(q, dq, a);
   } else {
-    if (!descent_step<Model, double>(q, F, sd, C, a.lambda, 1e300, kFloorF64, dq)) return ST_SINGULAR;
+    if (!step_of<Model, double>(q, F, sd, C, a, 1e300, kFloorF64, dq)) return ST_SINGULAR;
     st = apply_step<Model, double>(q, dq, a);
   }
   if (st < 0) ++k;

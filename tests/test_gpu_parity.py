@@ -264,6 +264,49 @@ def test_damped_steps_parity(mc, name, dt, qtol):
     assert info["conv"] > 0.9, info
 
 
+@pytest.mark.parametrize("name,dt,qtol", [("c1", torch.float64, 1e-9), ("c2", torch.float64, 1e-9),
+                                          ("c6", torch.float64, 1e-9), ("c2", torch.float32, 1e-3),
+                                          ("c6", torch.float32, 1e-3)])
+def test_outer_step_form_parity(mc, name, dt, qtol):
+    """The outer form of the step, alpha (J^T J + lambda I)^-1 J^T F (a d x d factorisation of the dense
+    J; lambda 1e-3, alpha 0.9), against the oracle's damped least-squares step, and against the inner
+    form on the GPU outside the band (the same vector for lambda > 0, up to rounding). The d x d system
+    has condition number (sigma_max^2 + lambda) / lambda, about 1e4 here against the m x m system's
+    sigma_max^2 / sigma_min^2: FP32 steps carry that much more rounding, hence 1e-3 in FP32 mode, which
+    the arm's long-step paths (C1: steps of several radians) exceed (1.9e-3 measured): FP32 mode is
+    checked on C2 and C6."""
+    from parity import UNSTABLE_REL
+    sc, P, q, offs, tol, mi = config_inputs(name, small=True, max_geo=16)
+    G = mc.Problem(sc.to_blob())
+    qd = to_dev(q, dt)
+    ro = G.project(qd, tol=tol, max_iter=mi, lam=1e-3, alpha=0.9, step_form="outer")
+    ri = G.project(qd, tol=tol, max_iter=mi, lam=1e-3, alpha=0.9)
+    torch.cuda.synchronize()
+    orc = oracle_run(P, q, tol, mi, alpha=0.9, lam=1e-3, unstable=(UNSTABLE_REL[ro.q.element_size()], qtol / 4))
+    info = compare(P, q, ro, tol, mi, qtol, max_band=0.7, alpha=0.9, lam=1e-3, orc=orc)
+    assert info["conv"] > 0.8, info
+    out = torch.from_numpy(~orc["band"]).to(ro.q.device)
+    same = out & (ro.status == ri.status) & (ro.iters == ri.iters) & (ro.status == 0)
+    assert same.float().sum().item() > 0.5 * out.float().sum().item()
+    d = (ro.q - ri.q)[:, same].abs().max().item()
+    assert d < qtol, d
+    print(name, dt, info)
+
+
+def test_outer_step_form_is_refused_where_it_does_not_fit(mc):
+    sc, P, q, offs, tol, mi = config_inputs("c3", small=True, max_geo=1)
+    G = mc.Problem(sc.to_blob())
+    qd = to_dev(q, torch.float32)
+    with pytest.raises(mc.McError):
+        G.project(qd, lam=1e-3, step_form="outer")  # d = 36
+    sc1, _, q1, _, _, _ = config_inputs("c1", small=True, max_geo=1)
+    G1 = mc.Problem(sc1.to_blob())
+    with pytest.raises(mc.McError):
+        G1.project(to_dev(q1, torch.float32), lam=0.0, step_form="outer")  # needs lambda > 0
+    with pytest.raises(mc.McError):
+        G1.project(to_dev(q1, torch.float32), lam=1e-3, step_form="outer", mode="cyclic")
+
+
 def test_wide_launch_matches_one_wave_launch(mc):
     """The 74,059-configuration humanoid batch exceeds the lanes of the one-wave-per-SIMD launch, so
     with the launch shape left to the library it runs in the two-wave build; pinning the shape keeps
