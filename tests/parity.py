@@ -85,10 +85,11 @@ def band_parts(path, iters, max_iter, max_step=0.0):
     return parts
 
 
-def unstable_mask(P, q, qo, st, longest, tol, max_iter, rel, limit, draws=2, **kw):
+def unstable_mask(P, q, qo, st, longest, tol, max_iter, rel, limit, draws=4, **kw):
     """Configurations whose oracle outcome moves when the input moves by a random vector of length
     rel * max(1, |q|_inf, longest step): a status change, or an output coordinate moving by more than
-    `limit` (angles compared modulo 2 pi)."""
+    `limit` (angles compared modulo 2 pi). Whether a draw reveals an unstable path depends on its
+    direction: on the full arm batch two draws missed three paths that four catch."""
     rng = np.random.default_rng(12345)
     size = rel * np.maximum(np.maximum(1.0, np.abs(q).max(axis=1)), longest)
     bad = np.zeros(len(q), bool)

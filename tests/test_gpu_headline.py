@@ -7,6 +7,8 @@ larger than the batch."""
 import numpy as np
 import pytest
 
+import oracle
+
 from parity import CONV, UNSTABLE_REL, compare, config_inputs, from_dev, oracle_run, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -231,3 +233,43 @@ def test_autotuner_result_is_used_by_the_auto_variant(mc):
         assert torch.equal(getattr(ra, f), getattr(rb, f)), f
     with pytest.raises(mc.McError):
         G.project(qd, lanes_per_config=3)
+
+
+class _Sub:
+    """The columns idx of a ProjectResult (what compare reads)."""
+
+    def __init__(self, r, idx):
+        ix = torch.as_tensor(idx, device=r.q.device)
+        self.q = r.q[:, ix]
+        self.status = r.status[ix]
+        self.iters = r.iters[ix]
+        self.resid = r.resid[ix]
+
+
+FULL = {"c1": (0.45, 131072), "c2": (0.25, 1078723), "c5": (0.30, 65536), "c6": (0.25, 131072)}
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c5", "c6"])
+def test_full_size_batches_sampled_against_oracle(mc, name):
+    """The other benchmark batches at full size through the path the benchmark times (fused variant,
+    the library's launch shape: lanes refill from the work queue, C1's and C2's uneven step counts
+    balance over it), compared with the oracle on 2,048 sampled configurations under the band rule."""
+    from paper_2604_13323_amd import scenes as S
+    import bench
+    cfg = S.make_config(name)
+    sc = cfg["scene"]
+    G = mc.Problem(sc.to_blob())
+    if "q" in cfg:
+        q = np.asarray(cfg["q"], np.float64)
+    else:
+        qd, _, _ = bench.build_batch(G, cfg, torch)
+        q = from_dev(qd).T
+    max_band, n_want = FULL[name]
+    assert len(q) == n_want
+    r = G.project(to_dev(q, torch.float32), tol=cfg["tol"], max_iter=cfg["max_iter"], variant="fused")
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng([len(q), 9]).choice(len(q), size=2048, replace=False))
+    P = oracle.Problem(sc.to_blob())
+    qs = from_dev(to_dev(q[idx], torch.float32)).T  # the inputs the GPU saw
+    stats = compare(P, qs, _Sub(r, idx), cfg["tol"], cfg["max_iter"], 1e-4, max_band=max_band)
+    print(name, len(q), stats)
