@@ -597,7 +597,9 @@ __global__ void __launch_bounds__(256) k_check_tail(ProjArgs a, int64_t small) {
 }
 
 // FP64 tail of the persistent variant: the configurations deferred by the FP32 kernel, one per
-// lane (grid-stride over the queue), continued from their stored FP64 iterate with FP64 steps.
+// lane (grid-stride over the queue), continued from their stored FP64 iterate with FP64 steps. Their
+// collision check joins the persistent kernel's: broad phase here, flagged ones queued for
+// k_check_tail (a one-lane exact check in-line cost C1's tail half a millisecond).
 // Dynamic LDS: D * blockDim doubles.
 template <class Model, class IO, bool CYC = false>
 __global__ void __launch_bounds__(64) k_project_tail(ProjArgs a) {
@@ -615,7 +617,20 @@ __global__ void __launch_bounds__(64) k_project_tail(ProjArgs a) {
     double resid;
     const int st = finish_fp64<Model, CYC>(q, q0, k, a, C, resid);
     store_result<Model, IO>(a, dof, i, q, st, k, resid);
-    if (a.verdict) a.verdict[i] = verdict_inline<Model>(q, C, a, st);
+    if (a.verdict) {
+      if constexpr (Model::broad_in_residual) {
+        // as in the persistent kernel: the broad phase here, the exact check of flagged
+        // configurations in k_check_tail (launched after this kernel), with its lane groups
+        if (a.check && st == ST_CONVERGED) {
+          a.verdict[i] = V_FREE;
+          if (Model::broad_flag(q, C)) a.chk_idx[queue_q<Model>(q, a.chk_count, a.chk_q, a.defer_cap)] = int32_t(i);
+        } else {
+          a.verdict[i] = V_UNCHECKED;
+        }
+      } else {
+        a.verdict[i] = verdict_inline<Model>(q, C, a, st);
+      }
+    }
   }
 }
 
