@@ -255,7 +255,8 @@ mc_status interpolate_geodesics(const mc_problem* p, int32_t n_geo, const int32_
 
 /* path_length_grad — path-length loss over geodesics and its gradient:
    L = sum_g sum_i ||q_{i+1} - q_i||, g_out[:, i] = u_{i-1} - u_i with u = delta / max(||delta||, 1e-12)
-   (u taken as 0 outside the geodesic). loss (nullable, device, one dtype scalar) receives L
+   (u taken as 0 outside the geodesic; geo_offsets non-decreasing, and a configuration before
+   geo_offsets[0] or from geo_offsets[n_geo] on gets g_out = 0). loss (nullable, device, one dtype scalar) receives L
    (accumulated atomically; it is zeroed by the call first). */
 mc_status path_length_grad(const mc_problem* p, int64_t n, const void* q, int64_t ld,
                            const int32_t* geo_offsets, int32_t n_geo, void* g_out, void* loss,

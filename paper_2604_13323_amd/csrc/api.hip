@@ -393,17 +393,17 @@ __global__ void k_interpolate(int n_geo, const int32_t* offs, const IO* e, int64
 // The geodesic holding configuration i, found by one wavefront: each round, the 64 lanes probe
 // 64 evenly spaced offsets and a ballot narrows the range 64-fold (2 rounds for 4,096 geodesics,
 // against 12 dependent loads of a binary search). Call with all 64 lanes of the wave active.
-__device__ __forceinline__ int wave_find_geo(const int32_t* offs, int n_geo, int64_t i) {
+__device__ __forceinline__ int half_wave_find_geo(const int32_t* offs, int n_geo, int64_t i) {
   int lo = 0, hi = n_geo;  // offs[lo] <= i < offs[hi] (or hi = n_geo)
-  const int lane = int(threadIdx.x & 63);
-  while (hi - lo > 1) {
+  const int lane = int(threadIdx.x & 31), half = int(threadIdx.x >> 5) & 1;
+  while (hi - lo > 1) {  // uniform within each half-wave
     const int64_t span = hi - lo;
-    const int probe = lo + int((span * lane) / 64);
+    const int probe = lo + int((span * lane) / 32);
     const bool le = lane == 0 || offs[probe] <= i;  // offs[probe] <= i (lane 0 probes lo)
-    const uint64_t m = uint64_t(__ballot(le));
-    const int last = 63 - __builtin_clzll(m);        // the highest probe still <= i
-    const int nlo = lo + int((span * last) / 64);
-    const int nhi = last == 63 ? hi : lo + int((span * (last + 1)) / 64);
+    const uint32_t m = uint32_t(uint64_t(__ballot(le)) >> (32 * half));
+    const int last = 31 - __builtin_clz(m);  // the highest probe still <= i
+    const int nlo = lo + int((span * last) / 32);
+    const int nhi = last == 31 ? hi : lo + int((span * (last + 1)) / 32);
     lo = nlo;
     hi = nhi > nlo ? nhi : nlo + 1;
   }
@@ -411,8 +411,8 @@ __device__ __forceinline__ int wave_find_geo(const int32_t* offs, int n_geo, int
 }
 
 // The geodesics a workgroup's configurations [i0, i1] belong to: the first wavefront finds the
-// first and last one, the workgroup stages the offsets between them in LDS (when they fit) and
-// searches there.
+// first (lanes 0-31) and the last one (lanes 32-63) in 32-ary searches side by side, the workgroup
+// stages the offsets between them in LDS (when they fit) and searches there.
 constexpr int kGeoWindow = 1024;
 constexpr int kMaxD = 36;  // largest configuration dimension of the compiled families
 
@@ -423,13 +423,15 @@ __global__ void __launch_bounds__(256) k_path_grad(int64_t n, const IO* q, int64
   __shared__ int s_g[2];
   const int64_t i0 = int64_t(blockIdx.x) * blockDim.x;
   const int64_t i1 = (i0 + blockDim.x < n ? i0 + blockDim.x : n) - 1;
+  const int64_t i = i0 + threadIdx.x;
+  const bool act = i < n;
+  // the configuration's own coordinates are requested first, so that their latency overlaps the
+  // geodesic search
+  IO x[kMaxD];
+  for (int c = 0; c < kMaxD; ++c) x[c] = (act && c < d) ? q[int64_t(c) * ld + i] : IO(0);
   if (threadIdx.x < 64) {
-    const int ga = wave_find_geo(offs, n_geo, i0);
-    const int gb = wave_find_geo(offs, n_geo, i1);
-    if (threadIdx.x == 0) {
-      s_g[0] = ga;
-      s_g[1] = gb;
-    }
+    const int gx = half_wave_find_geo(offs, n_geo, threadIdx.x < 32 ? i0 : i1);
+    if ((threadIdx.x & 31) == 0) s_g[threadIdx.x >> 5] = gx;
   }
   __syncthreads();
   const int g0 = s_g[0], w = s_g[1] - g0 + 2;  // offsets g0 .. g1 + 1
@@ -437,10 +439,8 @@ __global__ void __launch_bounds__(256) k_path_grad(int64_t n, const IO* q, int64
   if (win)
     for (int t = threadIdx.x; t < w; t += blockDim.x) s_offs[t] = offs[g0 + t];
   __syncthreads();
-  const int64_t i = i0 + threadIdx.x;
-  double seg = 0.0;
-  if (i < n) {
-    int64_t lo_off, hi_off;  // the configuration's geodesic is [lo_off, hi_off)
+  int64_t lo_off = 0, hi_off = 0;  // the configuration's geodesic is [lo_off, hi_off)
+  if (act) {
     if (win) {
       int lo = 0, hi = w - 1;  // s_offs[lo] <= i < s_offs[hi]
       while (hi - lo > 1) {
@@ -454,18 +454,31 @@ __global__ void __launch_bounds__(256) k_path_grad(int64_t n, const IO* q, int64
       lo_off = offs[gi];
       hi_off = offs[gi + 1];
     }
-    const bool has_prev = i > lo_off, has_next = i + 1 < hi_off && i + 1 < n;
-    // all loads first (one memory latency), then the arithmetic
-    IO x[kMaxD], xp[kMaxD], xn[kMaxD];
-    for (int c = 0; c < kMaxD; ++c) {
-      const int64_t k = int64_t(c) * ld + i;
-      x[c] = c < d ? q[k] : IO(0);
-      xp[c] = (c < d && has_prev) ? q[k - 1] : x[c];
-      xn[c] = (c < d && has_next) ? q[k + 1] : x[c];
-    }
+  }
+  // the searches clamp to the first and last geodesic: a configuration before geo_offsets[0] or
+  // from geo_offsets[n_geo] on lies on none
+  const bool inside = act && lo_off <= i && i < hi_off;
+  const bool has_prev = inside && i > lo_off, has_next = inside && i + 1 < hi_off && i + 1 < n;
+  // each coordinate is read once: the neighbours' come from the adjacent lanes, and only the
+  // wave's first and last lanes read the configuration outside the wave
+  const int lane = int(threadIdx.x & 63);
+  IO xp[kMaxD], xn[kMaxD];
+  for (int c = 0; c < kMaxD; ++c) {
+    xp[c] = __shfl_up(x[c], 1u);
+    xn[c] = __shfl_down(x[c], 1u);
+  }
+  if (lane == 0 && has_prev)
+    for (int c = 0; c < kMaxD; ++c)
+      if (c < d) xp[c] = q[int64_t(c) * ld + i - 1];
+  if (lane == 63 && has_next)
+    for (int c = 0; c < kMaxD; ++c)
+      if (c < d) xn[c] = q[int64_t(c) * ld + i + 1];
+  double seg = 0.0;
+  if (act) {
     double np = 0.0, nn = 0.0;
     for (int c = 0; c < kMaxD; ++c) {
-      const double tp = double(x[c]) - double(xp[c]), tn = double(xn[c]) - double(x[c]);
+      const double tp = has_prev ? double(x[c]) - double(xp[c]) : 0.0;
+      const double tn = has_next ? double(xn[c]) - double(x[c]) : 0.0;
       np += tp * tp;
       nn += tn * tn;
     }

@@ -493,6 +493,35 @@ def test_path_length_and_interpolation_match_oracle(mc):
     np.testing.assert_allclose(from_dev(qi).T, oracle.interpolate_interior(e, offs), atol=1e-14)
 
 
+@pytest.mark.parametrize("name", ["c0", "c3"])
+def test_path_length_gradient_ragged_geodesics(mc, name):
+    """Geodesics of 0 to 300 configurations: a run of 1,500 empty ones (more offsets than a
+    workgroup stages in LDS), lengths 1, 2, 63, 64 and 65 (boundaries on a wave's first and last
+    lane), configurations before the first and after the last geodesic (gradient 0), a leading
+    dimension above n; both dtypes against the oracle."""
+    import oracle
+    sc = config_inputs(name, small=True, max_geo=1)[0]
+    G = gpu_problem(mc, sc)
+    rng = np.random.default_rng(77)
+    lens = np.concatenate([rng.integers(0, 300, 40), np.zeros(1500, int), [1, 2, 63, 64, 65, 1, 1, 0, 2],
+                           rng.integers(0, 5, 200), rng.integers(60, 70, 30)])
+    offs = (5 + np.concatenate([[0], np.cumsum(lens)])).astype(np.int32)
+    n = int(offs[-1]) + 7
+    q = rng.uniform(-2.0, 2.0, (n, sc.d))
+    offs_d = torch.from_numpy(offs).cuda()
+    for dt in (torch.float64, torch.float32):
+        qd = torch.zeros((sc.d, n + 13), dtype=dt, device="cuda")
+        qd[:, :n] = torch.from_numpy(q.T).to(dt)
+        g, loss = G.path_length_grad(qd[:, :n], offs_d)
+        torch.cuda.synchronize()
+        L, go = oracle.path_length(from_dev(qd[:, :n]).T, offs)
+        tolg = 1e-12 if dt == torch.float64 else 1e-5
+        gg = from_dev(g).T
+        np.testing.assert_allclose(gg, go, atol=tolg)
+        assert (gg[:5] == 0).all() and (gg[-7:] == 0).all()
+        assert abs(float(loss[0]) - L) < (1e-9 if dt == torch.float64 else 1e-5) * max(1, L)
+
+
 # ---------------------------------------------------------------- edge cases
 def test_edge_cases(mc):
     from paper_2604_13323_amd import scenes as S
