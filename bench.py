@@ -298,9 +298,9 @@ def main():
     G.kernel_timing(False)
     ms_kernel = float(np.mean(kms))
     ms_check = timed(lambda: G.check(out.q), args.steps, args.warmup, torch)
-    # algorithmic work of one launch: the scope table's per-iteration figure x the batch's Newton
+    # algorithmic work of one launch: the nominal per-iteration figure x the batch's Newton
     # iterations + a final residual per configuration + the broad phase the kernel runs at convergence
-    flop = FL.survey_batch_flops(sc, iters, with_broad=True)
+    flop = FL.nominal_batch_flops(sc, iters, with_broad=True)
     flop_model = FL.batch_flops(sc, iters, with_broad=True)
     achieved_tflops = flop / (ms_kernel * 1e-3) / 1e12
     log(f"persistent kernel: {ms_kernel:.4f} ms per launch (min {min(kms):.4f}), {achieved_tflops:.2f} TFLOP/s "
@@ -361,7 +361,7 @@ def main():
 
         ms4 = timed(fwd_vjp, args.steps, args.warmup, torch, "fwd_vjp")
         # the VJP kernel alone (HIP events around its launch); ~14 kFLOP per converged configuration
-        # (one Newton iteration's work plus J g, the scope table's per-unit VJP figure)
+        # (one Newton iteration's work plus J g, the nominal per-unit VJP figure)
         g4, _ = G.path_length_grad(o4.q, offs4)
         G.kernel_timing(True)
         vms = []

@@ -164,13 +164,13 @@ def batch_flops(sc: S.Scene, iters: np.ndarray, with_broad: bool = True) -> floa
     return float(f["per_iter"] * iters.sum() + final * iters.size)
 
 
-# Per-unit figures of the scope table's measurement section: algorithmic FLOPs of one Newton
-# iteration (structural sparsity counted, FMA = 2), by family.
-SURVEY_PER_ITER = {S.FAMILY_SPHERE: 15, S.FAMILY_ARM7_AXIS: 800, S.FAMILY_DUAL14_REL: 3300,
+# Nominal per-unit figures: algorithmic FLOPs of one Newton iteration (structural sparsity
+# counted, FMA = 2), by family.
+NOMINAL_PER_ITER = {S.FAMILY_SPHERE: 15, S.FAMILY_ARM7_AXIS: 800, S.FAMILY_DUAL14_REL: 3300,
                    S.FAMILY_HUMANOID36: 13000}
 
 
-def survey_final_residual(sc: S.Scene) -> int:
+def nominal_final_residual(sc: S.Scene) -> int:
     """One residual evaluation with the same per-unit figures: forward kinematics at ~96 FLOP per
     joint plus a sine/cosine per revolute joint, ~150 per pose or relative-pose block."""
     if not sc.joints:
@@ -180,11 +180,11 @@ def survey_final_residual(sc: S.Scene) -> int:
     return 96 * len(sc.joints) + n_rev + 150 * n_pose
 
 
-def survey_batch_flops(sc: S.Scene, iters: np.ndarray, with_broad: bool = True) -> float:
-    """Algorithmic FLOPs of a batch with the scope table's per-unit figures: per-iteration FLOPs x the
+def nominal_batch_flops(sc: S.Scene, iters: np.ndarray, with_broad: bool = True) -> float:
+    """Algorithmic FLOPs of a batch with the nominal per-unit figures: per-iteration FLOPs x the
     batch's Newton iterations + one final residual per configuration (+ the broad phase of the
     collision check, from iteration_flops, when the launch runs it)."""
     iters = np.asarray(iters, np.int64)
-    per_iter = SURVEY_PER_ITER.get(sc.family, iteration_flops(sc)["per_iter"])
+    per_iter = NOMINAL_PER_ITER.get(sc.family, iteration_flops(sc)["per_iter"])
     broad = iteration_flops(sc)["parts"].get("broad_once", 0) if with_broad else 0
-    return float(per_iter * iters.sum() + (survey_final_residual(sc) + broad) * iters.size)
+    return float(per_iter * iters.sum() + (nominal_final_residual(sc) + broad) * iters.size)
