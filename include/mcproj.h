@@ -333,6 +333,15 @@ mc_status mc_eval_condition(const mc_problem* p, int64_t n, const void* q, int64
    queued for the exact collision check. */
 mc_status mc_queue_counts(const mc_problem* p, uint32_t counts[4]);
 
+/* mc_set_check_lanes — lanes per configuration of the exact collision check that project_batch
+   (fused variant), extend_batch and check_batch run on the configurations their broad phase flags
+   (Sec. IV-B, the collision test of every projected configuration). 0 (the default): by the length of
+   the queue, a wave per configuration while it is short (at most 4 per launch workgroup), else groups
+   of 4 lanes (or the size mc_autotune_project chose); 1, 2, 4, 8, 16 or 64: that many on every queue. Groups below 4 lanes exist for families
+   of at most 16 coordinates and run only where the scene's staged spheres leave LDS room for them
+   (else 4). Verdicts do not depend on it. MC_ERR_INVALID_ARG for other values. */
+mc_status mc_set_check_lanes(mc_problem* p, int32_t lanes);
+
 /* mc_set_kernel_timing — diagnostic: when on, project_batch brackets its main projection launch
    (the persistent kernel of the fused variant, all per-geodesic launches of the plain one) and
    project_vjp / project_vjp_exact their main VJP launch with HIP events on the call's stream; mc_last_kernel_ms waits for
@@ -347,6 +356,9 @@ typedef struct {
   int32_t waves_per_block;  /* 1, 2 or 4                                        */
   int32_t blocks_per_cu;    /* 0 = occupancy limit, else 1..64                  */
   int32_t lanes_per_config; /* 1                                                */
+  int32_t check_lanes;      /* lanes per configuration of the exact collision check on a long
+                               queue: 4, 8 or 16 as mc_autotune_project chose them for this
+                               batch (0 in the candidate list, and where the queue was short)   */
 } mc_launch_shape;
 
 /* mc_autotune_candidates — number of launch shapes mc_autotune_project tries; shapes (nullable)
@@ -359,8 +371,12 @@ int32_t mc_autotune_candidates(mc_launch_shape* shapes);
    gives bit-identical outputs (q_out, status, iters, resid, verdict; else MC_ERR_HIP with a message
    naming the shape), and stores the fastest shape in the problem for opts->dtype and opts->mode.
    best (nullable) receives it, ms (nullable, float[mc_autotune_candidates()]) the mean time per
-   call of every candidate. The batch itself is only read. Allocates temporary outputs and
-   synchronises the device (a set-up call, not for the hot loop). reps in 1..1000. */
+   call of every candidate. Where check_collision is on and the batch's exact-check queue is long (more
+   entries than 16 per CU), a second stage times the check's lane groups of 4, 8 and 16 lanes per
+   configuration in the fastest shape, checks the outputs again and keeps the fastest group size in
+   the problem for every later call's long queues (best->check_lanes; mc_set_check_lanes overrides it).
+   The batch itself is only read. Allocates temporary outputs and synchronises the device (a set-up
+   call, not for the hot loop). reps in 1..1000. */
 mc_status mc_autotune_project(mc_problem* p, int64_t n, const void* q_in, int64_t ld_in,
                               const mc_project_opts* opts, int32_t reps, void* stream,
                               mc_launch_shape* best, float* ms);

@@ -39,11 +39,11 @@ class Opts(ctypes.Structure):
 
 class LaunchShape(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("lanes_per_config", ctypes.c_int32)]
+                ("lanes_per_config", ctypes.c_int32), ("check_lanes", ctypes.c_int32)]
 
     def as_dict(self):
         return dict(waves_per_block=self.waves_per_block, blocks_per_cu=self.blocks_per_cu,
-                    lanes_per_config=self.lanes_per_config)
+                    lanes_per_config=self.lanes_per_config, check_lanes=self.check_lanes)
 
 
 class ExtendOpts(ctypes.Structure):
@@ -56,7 +56,8 @@ EXPORTS = ["mc_default_opts", "mc_problem_create", "mc_problem_destroy", "mc_pro
            "mc_problem_family", "mc_last_error", "project_batch", "check_batch", "project_vjp",
            "interpolate_geodesics", "path_length_grad", "mc_eval_residual_jacobian", "mc_fallback_count", "extend_batch",
            "mc_eval_condition", "mc_queue_counts", "mc_autotune_candidates", "mc_autotune_project", "mc_tuned_shape",
-           "mc_set_kernel_timing", "mc_last_kernel_ms", "project_batch_noalloc", "project_vjp_exact"]
+           "mc_set_kernel_timing", "mc_last_kernel_ms", "project_batch_noalloc", "project_vjp_exact",
+           "mc_set_check_lanes"]
 
 
 def lib():
@@ -97,6 +98,7 @@ def lib():
                                       ctypes.POINTER(ctypes.c_float)]
     L.mc_tuned_shape.argtypes = [P, ctypes.c_int, I32, ctypes.POINTER(LaunchShape)]
     L.mc_set_kernel_timing.argtypes = [P, I32]
+    L.mc_set_check_lanes.argtypes = [P, I32]
     L.mc_last_kernel_ms.argtypes = [P, I32, ctypes.POINTER(ctypes.c_float)]
     for f in EXPORTS:
         if f not in ("mc_default_opts", "mc_problem_destroy", "mc_problem_dof", "mc_problem_rows",
@@ -372,6 +374,10 @@ class Problem:
         out = LaunchShape()
         rc = lib().mc_tuned_shape(self._h, MC_F64 if dtype == torch.float64 else MC_F32, MODES[mode], ctypes.byref(out))
         return out.as_dict() if rc == 0 else None
+
+    def set_check_lanes(self, lanes=0):
+        """Lanes per configuration of the exact collision check (0: by queue length; 1, 2, 4, 8, 16, 64)."""
+        _check(lib().mc_set_check_lanes(self._h, int(lanes)), "mc_set_check_lanes")
 
     def kernel_timing(self, on=True):
         """Bracket the main projection and VJP launches with HIP events (see last_kernel_ms)."""

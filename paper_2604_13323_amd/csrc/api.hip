@@ -770,6 +770,11 @@ struct mc_problem {
   mutable int occ_wide = 0;  // resident 256-thread workgroups per CU of the two-wave launch
   // launch shape stored by mc_autotune_project, by (FP64 mode, cyclic mode); waves_per_block 0 = none
   mc_launch_shape tuned[2][2] = {{{0, 0, 0}, {0, 0, 0}}, {{0, 0, 0}, {0, 0, 0}}};
+  // mc_set_check_lanes: lanes per configuration of the exact-check tail (0: by queue length)
+  int32_t check_lanes = 0;
+  // lanes per configuration of the exact-check tail on long queues, as mc_autotune_project chose
+  // them (0: not tuned, kTailCheckLanesLong)
+  int32_t check_long = 0;
   // mc_set_kernel_timing: events around the main projection launch [0, 1] and the VJP launch [2, 3]
   bool timing = false;
   hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -1163,6 +1168,8 @@ static mc_status project_impl(const mc_problem* p, int64_t n, const void* q_in, 
   a.counter = counter;
   a.n_sph = p->n_sph;
   a.n_obs = p->n_obs;
+  a.chk_lanes = p->check_lanes;
+  a.chk_long = p->check_long;
   hipError_t e;
   if (variant == 1) {
     a.verdict = verdict;
@@ -1314,6 +1321,8 @@ mc_status check_batch(const mc_problem* p, int64_t n, const void* q, int64_t ld,
   a.defer_cap = p->defer_cap;
   a.n_sph = p->n_sph;
   a.n_obs = p->n_obs;
+  a.chk_lanes = p->check_lanes;
+  a.chk_long = p->check_long;
   hipLaunchKernelGGL(k_reset_u32, dim3(1), dim3(64), 0, s, p->counter + 3, 1);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "check_batch: reset");
   if ((e = ops->check_broad(c, a.chk_count, a.chk_idx, a.chk_q, a.defer_cap, s)) != hipSuccess)
@@ -1625,6 +1634,15 @@ mc_status mc_eval_condition(const mc_problem* p, int64_t n, const void* q, int64
   return MC_OK;
 }
 
+mc_status mc_set_check_lanes(mc_problem* p, int32_t lanes) {
+  g_err.clear();
+  if (!p) return fail(MC_ERR_INVALID_ARG, "mc_set_check_lanes: null problem");
+  if (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16 && lanes != 64)
+    return fail(MC_ERR_INVALID_ARG, "mc_set_check_lanes: lanes must be 0, 1, 2, 4, 8, 16 or 64");
+  p->check_lanes = lanes;
+  return MC_OK;
+}
+
 mc_status mc_set_kernel_timing(mc_problem* p, int32_t on) {
   g_err.clear();
   if (!p) return fail(MC_ERR_INVALID_ARG, "mc_set_kernel_timing: null problem");
@@ -1767,11 +1785,60 @@ mc_status mc_autotune_project(mc_problem* p, int64_t n, const void* q_in, int64_
       best_ms = t;
     }
   }
+  // second stage, where the batch's exact-check queue is long (more entries than the tail's
+  // wave-per-configuration path takes): the lane groups of that queue, in the best shape
+  mc_launch_shape chosen = kTuneCandidates[best_c >= 0 ? best_c : 0];
+  unsigned queued = 0;
+  if (rc == MC_OK && opts->check_collision &&
+      (e = hipMemcpy(&queued, p->counter + 3, sizeof queued, hipMemcpyDeviceToHost)) != hipSuccess)
+    rc = hip_fail(e, "mc_autotune_project: read the check queue length");
+  if (rc == MC_OK && opts->check_collision && int64_t(queued) > int64_t(4) * 4 * p->n_cu) {
+    const int32_t saved = p->check_long;
+    int32_t best_l = 0;
+    float best_l_ms = 0.f;
+    for (int32_t L : {4, 8, 16}) {
+      mc_project_opts o = *opts;
+      o.variant = 2;
+      o.waves_per_block = chosen.waves_per_block;
+      o.blocks_per_cu = chosen.blocks_per_cu;
+      o.lanes_per_config = chosen.lanes_per_config;
+      p->check_long = L;
+      auto call = [&]() {
+        return project_batch(p, n, q_in, ld_in, cand.q, n, cand.status, cand.iters, cand.resid, cand.verdict, nullptr,
+                             nullptr, 0, nullptr, &o, stream);
+      };
+      if ((rc = call()) != MC_OK) break;
+      if ((e = hipMemcpy(h_cand.data(), cand.base, cand.bytes, hipMemcpyDeviceToHost)) != hipSuccess) {
+        rc = hip_fail(e, "mc_autotune_project: read outputs");
+        break;
+      }
+      if (std::memcmp(h_ref.data(), h_cand.data(), cand.bytes) != 0) {
+        rc = fail(MC_ERR_HIP, "mc_autotune_project: exact-check lane groups of " + std::to_string(L) + " changed the results");
+        break;
+      }
+      if ((e = hipEventRecord(e0, s)) != hipSuccess) { rc = hip_fail(e, "mc_autotune_project: event"); break; }
+      for (int r = 0; r < reps && rc == MC_OK; ++r) rc = call();
+      if (rc != MC_OK) break;
+      float t = 0.f;
+      if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+          (e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) {
+        rc = hip_fail(e, "mc_autotune_project: timing");
+        break;
+      }
+      t /= float(reps);
+      if (best_l == 0 || t < best_l_ms) {
+        best_l = L;
+        best_l_ms = t;
+      }
+    }
+    p->check_long = rc == MC_OK ? best_l : saved;
+    chosen.check_lanes = best_l;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != MC_OK) return rc;
-  p->tuned[opts->dtype == MC_F64 ? 1 : 0][opts->mode == 1 ? 1 : 0] = kTuneCandidates[best_c];
-  if (best) *best = kTuneCandidates[best_c];
+  p->tuned[opts->dtype == MC_F64 ? 1 : 0][opts->mode == 1 ? 1 : 0] = chosen;
+  if (best) *best = chosen;
   return MC_OK;
 }
 

@@ -58,6 +58,9 @@ struct ProjArgs {
   int32_t* chk_idx;
   double* chk_q;
   int32_t n_sph, n_obs;   // robot and obstacle spheres (LDS size of the exact-check kernel)
+  int32_t chk_lanes;      // exact-check tail: lanes per queued configuration (0: by queue length; 1, 2, 4, 8, 16, 64)
+  int32_t chk_long;       // exact-check tail: lanes per configuration on a long queue with chk_lanes = 0
+                          // (4, 8 or 16; 0 = kTailCheckLanesLong)
 };
 
 constexpr int ST_DEFER = -2;  // internal: continue this configuration with FP64 steps
@@ -556,13 +559,20 @@ __global__ void __launch_bounds__(256, 2) k_project_persistent_wide(ProjArgs a) 
 }
 
 // Exact collision check of the configurations queued by k_project_persistent, L lanes per
-// configuration (grid-stride over the queue): a wave per configuration while the queue is short
-// (at most `small` entries: latency-bound, few waves; each configuration's links may be split over
-// up to 4 waves), 4 lanes per configuration when it is long (most configurations near the
-// obstacles). One launch serves both cases; the queue length picks the path.
-// Dynamic LDS: one configuration per lane group (D doubles each, 64 groups at most), then the
-// robot spheres and the obstacles (float4 each).
-constexpr int kTailCheckLanesLong = 4;  // lanes per configuration on a long queue
+// configuration (grid-stride over the queue). A short queue (at most `small` entries: latency-bound,
+// few waves) runs a wave per configuration, each configuration's links split over up to 4 waves; a
+// longer one runs groups of chk_long lanes (the autotuner's choice of 4, 8 or 16; 4 by default). Every lane of a group walks the tree and the
+// group splits the sphere-pair tests of the (link, cluster) pairs it finds overlapping; smaller groups
+// repeat fewer walks, but the lanes of a wave then run different pair lists and the wave runs their
+// union (measured on the 7- and 14-DoF batches: 1 and 2 lanes slower than 4, a wave per configuration
+// slower still on long queues). A caller may force 1, 2, 4, 8, 16 or 64 lanes (chk_lanes).
+// Dynamic LDS: one configuration per lane group (D doubles each), then the robot spheres and the
+// obstacles (float4 each); groups below 4 lanes exist for families of at most kTailCheckLowLanesMaxD
+// coordinates and run only where their staged configurations leave room for 4 workgroups per CU
+// (min_lanes, from the launcher).
+constexpr int kTailCheckLanesLong = 4;
+constexpr int kTailCheckLowLanesMaxD = 16;
+constexpr size_t kTailCheckLdsBudget = 40 * 1024;  // a quarter of a CU's LDS
 
 template <class Model, class IO, int L>
 __device__ __forceinline__ void check_tail_body(const ProjArgs& a, int64_t small, int64_t cnt, double* smem) {
@@ -589,11 +599,24 @@ __device__ __forceinline__ void check_tail_body(const ProjArgs& a, int64_t small
 }
 
 template <class Model, class IO>
-__global__ void __launch_bounds__(256) k_check_tail(ProjArgs a, int64_t small) {
+__global__ void __launch_bounds__(256) k_check_tail(ProjArgs a, int64_t small, int min_lanes) {
   extern __shared__ double smem[];
   const int64_t cnt = *a.chk_count;
-  if (cnt <= small) check_tail_body<Model, IO, 64>(a, small, cnt, smem);
-  else check_tail_body<Model, IO, kTailCheckLanesLong>(a, small, cnt, smem);
+  int L = a.chk_lanes != 0 ? a.chk_lanes : cnt <= small ? 64 : a.chk_long > 0 ? a.chk_long : kTailCheckLanesLong;
+  if (L < min_lanes) L = min_lanes;
+  if (L == 64) {
+    check_tail_body<Model, IO, 64>(a, small, cnt, smem);
+  } else if (L == 16) {
+    check_tail_body<Model, IO, 16>(a, small, cnt, smem);
+  } else if (L == 8) {
+    check_tail_body<Model, IO, 8>(a, small, cnt, smem);
+  } else if constexpr (Model::D <= kTailCheckLowLanesMaxD) {
+    if (L == 1) check_tail_body<Model, IO, 1>(a, small, cnt, smem);
+    else if (L == 2) check_tail_body<Model, IO, 2>(a, small, cnt, smem);
+    else check_tail_body<Model, IO, 4>(a, small, cnt, smem);
+  } else {
+    check_tail_body<Model, IO, 4>(a, small, cnt, smem);
+  }
 }
 
 // FP64 tail of the persistent variant: the configurations deferred by the FP32 kernel, one per

@@ -44,11 +44,20 @@ template <class Model, class IO, class S>
 hipError_t OpsImpl<Model, IO, S>::check_tail(const ProjArgs& a, int grid, hipStream_t s) {
   const size_t stage = size_t(a.n_sph + a.n_obs) * 16;
   // short queues: a wave (or part of one configuration's links) per work item, one pass of
-  // `small` work items over 4 waves per workgroup; the LDS covers the long-queue path's 64
-  // lane groups of 4
+  // `small` work items over 4 waves per workgroup
   const int64_t small = int64_t(grid) * 4;
-  const size_t cols = size_t(256 / kTailCheckLanesLong) * Model::D * sizeof(double);
-  hipLaunchKernelGGL((k_check_tail<Model, IO>), dim3(grid), dim3(256), cols + stage, s, a, small);
+  // the smallest lane group whose staged configurations fit beside the spheres in a quarter of the
+  // CU's LDS; the LDS covers 256 / min_lanes groups
+  int min_lanes = 4;
+  if constexpr (Model::D <= kTailCheckLowLanesMaxD) {
+    for (int L = 1; L < 4; L *= 2)
+      if (size_t(256 / L) * Model::D * sizeof(double) + stage <= kTailCheckLdsBudget) {
+        min_lanes = L;
+        break;
+      }
+  }
+  const size_t cols = size_t(256 / min_lanes) * Model::D * sizeof(double);
+  hipLaunchKernelGGL((k_check_tail<Model, IO>), dim3(grid), dim3(256), cols + stage, s, a, small, min_lanes);
   return hipGetLastError();
 }
 template <class Model, class IO, class S>

@@ -244,6 +244,7 @@ class _Sub:
         self.status = r.status[ix]
         self.iters = r.iters[ix]
         self.resid = r.resid[ix]
+        self.verdict = r.verdict[ix]
 
 
 FULL = {"c1": (0.45, 131072), "c2": (0.25, 1078723), "c5": (0.30, 65536), "c6": (0.25, 131072)}
@@ -271,5 +272,71 @@ def test_full_size_batches_sampled_against_oracle(mc, name):
     idx = np.sort(np.random.default_rng([len(q), 9]).choice(len(q), size=2048, replace=False))
     P = oracle.Problem(sc.to_blob())
     qs = from_dev(to_dev(q[idx], torch.float32)).T  # the inputs the GPU saw
-    stats = compare(P, qs, _Sub(r, idx), cfg["tol"], cfg["max_iter"], 1e-4, max_band=max_band)
-    print(name, len(q), stats)
+    sub = _Sub(r, idx)
+    stats = compare(P, qs, sub, cfg["tol"], cfg["max_iter"], 1e-4, max_band=max_band)
+    # collision verdicts of the sampled converged configurations (the long-queue path of the
+    # exact-check tail) against the oracle's brute force at the GPU's outputs, outside the 1e-5 m band
+    conv = from_dev(sub.status).astype(int) == CONV
+    vo, sdo = P.check(from_dev(sub.q).T[conv])
+    vg = from_dev(sub.verdict).astype(int)[conv]
+    out = np.abs(sdo) > 1e-5
+    assert (vg[out] == vo[out]).all(), f"{int((vg[out] != vo[out]).sum())} verdicts differ"
+    print(name, len(q), stats, "hits", int(vo.sum()), "queued", G.queue_counts()[3])
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+def test_exact_check_lane_groups_give_the_same_verdicts(mc, name):
+    """The exact-check tail with every lane-group size forced (a wave, 16, 8, 4, 2 and 1 lanes per
+    configuration; the 36-DoF family keeps at least 4) gives bit-identical verdicts, in check_batch
+    and in the fused projection, and they match the oracle outside the 1e-5 m band."""
+    sc, P, q, offs, tol, mi = config_inputs(name, small=True)
+    G = mc.Problem(sc.to_blob())
+    qd = to_dev(q, torch.float32)
+    ref = G.project(qd, tol=tol, max_iter=mi, variant="fused")
+    vref = G.check(ref.q)
+    torch.cuda.synchronize()
+    assert G.queue_counts()[3] > 0
+    for lanes in (64, 16, 8, 4, 2, 1):
+        G.set_check_lanes(lanes)
+        r = G.project(qd, tol=tol, max_iter=mi, variant="fused")
+        v = G.check(ref.q)
+        torch.cuda.synchronize()
+        assert torch.equal(r.verdict, ref.verdict), lanes
+        assert torch.equal(v, vref), lanes
+    G.set_check_lanes(0)
+    with pytest.raises(mc.McError):
+        G.set_check_lanes(3)
+    conv = from_dev(ref.status).astype(int) == CONV
+    vo, sdo = P.check(from_dev(ref.q).T[conv])
+    out = np.abs(sdo) > 1e-5
+    assert (from_dev(vref).astype(int)[conv][out] == vo[out]).all()
+
+
+def test_autotuner_picks_the_check_lane_groups_on_a_long_queue(mc):
+    """On the 7-DoF arm batch at full size almost every configuration reaches the exact check, so the
+    autotuner's second stage times lane groups of 4, 8 and 16 for it, keeps the fastest in the problem
+    and reports it; later calls give the same outputs as the untuned call. A short queue (the humanoid
+    batch) leaves the choice untuned."""
+    from paper_2604_13323_amd import scenes as S
+    import bench
+    cfg = S.make_config("c1")
+    G = mc.Problem(cfg["scene"].to_blob())
+    if "q" in cfg:
+        q = to_dev(np.asarray(cfg["q"], np.float64), torch.float32)
+    else:
+        q, _, _ = bench.build_batch(G, cfg, torch)
+    kw = dict(tol=cfg["tol"], max_iter=cfg["max_iter"])
+    ref = G.project(q, variant="fused", **kw)
+    torch.cuda.synchronize()
+    assert G.queue_counts()[3] > 16 * 256
+    best, table = G.autotune(q, reps=2, **kw)
+    assert best["check_lanes"] in (4, 8, 16), best
+    assert G.tuned_shape() == best
+    r = G.project(q, **kw)
+    torch.cuda.synchronize()
+    for f in ("q", "status", "iters", "resid", "verdict"):
+        assert torch.equal(getattr(r, f), getattr(ref, f)), f
+    sc3, P3, q3, offs3, tol3, mi3 = config_inputs("c3", small=True)
+    G3 = mc.Problem(sc3.to_blob())
+    best3, _ = G3.autotune(to_dev(q3, torch.float32), reps=1, tol=tol3, max_iter=mi3)
+    assert best3["check_lanes"] == 0
