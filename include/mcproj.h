@@ -357,8 +357,9 @@ typedef struct {
   int32_t blocks_per_cu;    /* 0 = occupancy limit, else 1..64                  */
   int32_t lanes_per_config; /* 1                                                */
   int32_t check_lanes;      /* lanes per configuration of the exact collision check on a long
-                               queue: 4, 8 or 16 as mc_autotune_project chose them for this
-                               batch (0 in the candidate list, and where the queue was short)   */
+                               queue: 1, 2, 4, 8 or 16 as mc_autotune_project chose them for
+                               this batch (0 in the candidate list, and where the queue was
+                               short)                                                           */
 } mc_launch_shape;
 
 /* mc_autotune_candidates — number of launch shapes mc_autotune_project tries; shapes (nullable)
@@ -372,8 +373,8 @@ int32_t mc_autotune_candidates(mc_launch_shape* shapes);
    naming the shape), and stores the fastest shape in the problem for opts->dtype and opts->mode.
    best (nullable) receives it, ms (nullable, float[mc_autotune_candidates()]) the mean time per
    call of every candidate. Where check_collision is on and the batch's exact-check queue is long (more
-   entries than 16 per CU), a second stage times the check's lane groups of 4, 8 and 16 lanes per
-   configuration in the fastest shape, checks the outputs again and keeps the fastest group size in
+   entries than 16 per CU), a second stage times the check's lane groups of 1, 2 (families of at most
+   16 coordinates), 4, 8 and 16 lanes per configuration in the fastest shape, checks the outputs again and keeps the fastest group size in
    the problem for every later call's long queues (best->check_lanes; mc_set_check_lanes overrides it).
    The batch itself is only read. Allocates temporary outputs and synchronises the device (a set-up
    call, not for the hot loop). reps in 1..1000. */

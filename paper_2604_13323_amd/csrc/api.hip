@@ -1786,7 +1786,9 @@ mc_status mc_autotune_project(mc_problem* p, int64_t n, const void* q_in, int64_
     }
   }
   // second stage, where the batch's exact-check queue is long (more entries than the tail's
-  // wave-per-configuration path takes): the lane groups of that queue, in the best shape
+  // wave-per-configuration path takes): the lane groups of that queue, in the best shape (groups of 1
+  // and 2 only for the families that have them; the kernel rounds them up to 4 where the scene's
+  // staged spheres leave no LDS room for them)
   mc_launch_shape chosen = kTuneCandidates[best_c >= 0 ? best_c : 0];
   unsigned queued = 0;
   if (rc == MC_OK && opts->check_collision &&
@@ -1796,7 +1798,8 @@ mc_status mc_autotune_project(mc_problem* p, int64_t n, const void* q_in, int64_
     const int32_t saved = p->check_long;
     int32_t best_l = 0;
     float best_l_ms = 0.f;
-    for (int32_t L : {4, 8, 16}) {
+    for (int32_t L : {1, 2, 4, 8, 16}) {
+      if (L < 4 && p->d > kTailCheckLowLanesMaxD) continue;  // such families run groups of at least 4
       mc_project_opts o = *opts;
       o.variant = 2;
       o.waves_per_block = chosen.waves_per_block;

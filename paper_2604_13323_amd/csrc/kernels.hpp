@@ -60,7 +60,7 @@ struct ProjArgs {
   int32_t n_sph, n_obs;   // robot and obstacle spheres (LDS size of the exact-check kernel)
   int32_t chk_lanes;      // exact-check tail: lanes per queued configuration (0: by queue length; 1, 2, 4, 8, 16, 64)
   int32_t chk_long;       // exact-check tail: lanes per configuration on a long queue with chk_lanes = 0
-                          // (4, 8 or 16; 0 = kTailCheckLanesLong)
+                          // (1, 2, 4, 8 or 16; 0 = kTailCheckLanesLong)
 };
 
 constexpr int ST_DEFER = -2;  // internal: continue this configuration with FP64 steps
@@ -561,13 +561,14 @@ __global__ void __launch_bounds__(256, 2) k_project_persistent_wide(ProjArgs a) 
 // Exact collision check of the configurations queued by k_project_persistent, L lanes per
 // configuration (grid-stride over the queue). A short queue (at most `small` entries: latency-bound,
 // few waves) runs a wave per configuration, each configuration's links split over up to 4 waves; a
-// longer one runs groups of chk_long lanes (the autotuner's choice of 4, 8 or 16; 4 by default). Every lane of a group walks the tree and the
-// group splits the sphere-pair tests of the (link, cluster) pairs it finds overlapping; smaller groups
-// repeat fewer walks, but the lanes of a wave then run different pair lists and the wave runs their
-// union (measured on the 7- and 14-DoF batches: 1 and 2 lanes slower than 4, a wave per configuration
-// slower still on long queues). A caller may force 1, 2, 4, 8, 16 or 64 lanes (chk_lanes).
-// Dynamic LDS: one configuration per lane group (D doubles each), then the robot spheres and the
-// obstacles (float4 each); groups below 4 lanes exist for families of at most kTailCheckLowLanesMaxD
+// longer one runs groups of chk_long lanes (the autotuner's choice among 1, 2, 4, 8 and 16; 4 by
+// default). Every lane of a group walks the tree, and the group splits the sphere-obstacle tests of
+// the (link, cluster) pairs it finds overlapping: smaller groups repeat fewer walks, but the lanes of
+// a wave then run different pair lists and the wave runs their union, so the best size depends on
+// the batch. A caller may force 1, 2, 4, 8, 16 or 64 lanes (chk_lanes).
+// Dynamic LDS: one configuration per lane group (D doubles each; a wave per configuration also
+// keeps 64 candidate-sphere slots per wave), then the robot spheres and the obstacles (float4
+// each); groups below 4 lanes exist for families of at most kTailCheckLowLanesMaxD
 // coordinates and run only where their staged configurations leave room for 4 workgroups per CU
 // (min_lanes, from the launcher).
 constexpr int kTailCheckLanesLong = 4;
@@ -583,7 +584,9 @@ __device__ __forceinline__ void check_tail_body(const ProjArgs& a, int64_t small
   if (L == 64 && cnt > 0) parts = small / cnt < 4 ? (small / cnt < 1 ? 1 : small / cnt) : 4;
   if (int64_t(blockIdx.x) * blockDim.x / L >= cnt * parts) return;  // no queued work for this block
   const QLdsU q{(QLdsU::LP)(smem + (threadIdx.x / L) * D)};
-  float4* sph = reinterpret_cast<float4*>(smem + D * (blockDim.x / L));
+  // a wave per configuration: 64 candidate-sphere slots per wave after the configurations
+  float4* slots = L == 64 ? reinterpret_cast<float4*>(smem + D * (blockDim.x / L)) + (threadIdx.x / 64) * 64 : nullptr;
+  float4* sph = reinterpret_cast<float4*>(smem + D * (blockDim.x / L)) + (L == 64 ? (blockDim.x / 64) * 64 : 0);
   float4* obs = sph + K.n_sph;
   block_copy16(sph, K.sph, K.n_sph * 16);
   block_copy16(obs, obs_of(a.P), K.n_obs * 16);
@@ -593,7 +596,7 @@ __device__ __forceinline__ void check_tail_body(const ProjArgs& a, int64_t small
     const int64_t slot = item / parts;
     const int part = int(item - slot * parts);
     load_queued<Model, IO>(a.chk_q, a.defer_cap, slot, q);
-    const bool hit = Model::template check_group<L>(q, C, K, sph, obs, part, int(parts));
+    const bool hit = Model::template check_group<L>(q, C, K, sph, obs, part, int(parts), slots);
     if ((gid & (L - 1)) == 0 && hit) a.verdict[a.chk_idx[slot]] = V_HIT;  // queued as V_FREE
   }
 }

@@ -47,7 +47,7 @@ hipError_t OpsImpl<Model, IO, S>::check_tail(const ProjArgs& a, int grid, hipStr
   // `small` work items over 4 waves per workgroup
   const int64_t small = int64_t(grid) * 4;
   // the smallest lane group whose staged configurations fit beside the spheres in a quarter of the
-  // CU's LDS; the LDS covers 256 / min_lanes groups
+  // CU's LDS; the LDS covers 256 / min_lanes groups (or the wave path's slots, if more)
   int min_lanes = 4;
   if constexpr (Model::D <= kTailCheckLowLanesMaxD) {
     for (int L = 1; L < 4; L *= 2)
@@ -56,7 +56,10 @@ hipError_t OpsImpl<Model, IO, S>::check_tail(const ProjArgs& a, int grid, hipStr
         break;
       }
   }
-  const size_t cols = size_t(256 / min_lanes) * Model::D * sizeof(double);
+  // the wave-per-configuration path: 4 configurations and 4 x 64 candidate slots (float4)
+  const size_t cols64 = size_t(4) * Model::D * sizeof(double) + size_t(4) * 64 * 16;
+  const size_t cols_l = size_t(256 / min_lanes) * Model::D * sizeof(double);
+  const size_t cols = cols_l > cols64 ? cols_l : cols64;
   hipLaunchKernelGGL((k_check_tail<Model, IO>), dim3(grid), dim3(256), cols + stage, s, a, small, min_lanes);
   return hipGetLastError();
 }

@@ -82,7 +82,7 @@ struct SphereModel {
   // Point robot: every lane of the group runs the whole (cheap) test.
   template <int L, class Q>
   static __device__ __forceinline__ bool check_group(const Q& q, const Consts&, const CollConsts& K, const float4*,
-                                                     const float4* obs, int part = 0, int = 1) {
+                                                     const float4* obs, int part = 0, int = 1, float4* = nullptr) {
     if (part != 0) return false;  // a point robot's check is not split
     bool hit = false;
     float minsd;
@@ -172,7 +172,7 @@ struct LinearModel {
   }
   template <int L, class Q>
   static __device__ __forceinline__ bool check_group(const Q&, const Consts&, const CollConsts&, const float4*,
-                                                     const float4*, int = 0, int = 1) {
+                                                     const float4*, int = 0, int = 1, float4* = nullptr) {
     return false;
   }
   template <class Q>

@@ -314,7 +314,7 @@ def test_exact_check_lane_groups_give_the_same_verdicts(mc, name):
 
 def test_autotuner_picks_the_check_lane_groups_on_a_long_queue(mc):
     """On the 7-DoF arm batch at full size almost every configuration reaches the exact check, so the
-    autotuner's second stage times lane groups of 4, 8 and 16 for it, keeps the fastest in the problem
+    autotuner's second stage times lane groups of 1, 2, 4, 8 and 16 for it, keeps the fastest in the problem
     and reports it; later calls give the same outputs as the untuned call. A short queue (the humanoid
     batch) leaves the choice untuned."""
     from paper_2604_13323_amd import scenes as S
@@ -330,7 +330,7 @@ def test_autotuner_picks_the_check_lane_groups_on_a_long_queue(mc):
     torch.cuda.synchronize()
     assert G.queue_counts()[3] > 16 * 256
     best, table = G.autotune(q, reps=2, **kw)
-    assert best["check_lanes"] in (4, 8, 16), best
+    assert best["check_lanes"] in (1, 2, 4, 8, 16), best
     assert G.tuned_shape() == best
     r = G.project(q, **kw)
     torch.cuda.synchronize()
