@@ -84,6 +84,18 @@ struct alignas(16) CollConsts {
 };
 
 // Squared distance from point c to the box [lo, hi] (0 inside).
+// Resident waves per SIMD a model's FP32 stacked projection kernel is built for: a model (or its
+// topology) may ask for 2 where the kernel fits in 256 registers per lane, so that twice the lanes
+// run at once; 1 otherwise.
+template <class M, class = void>
+struct PersistWaves {
+  static constexpr int value = 1;
+};
+template <class M>
+struct PersistWaves<M, std::void_t<decltype(M::persist_waves)>> {
+  static constexpr int value = M::persist_waves;
+};
+
 __device__ __forceinline__ float box_dist2(const float* c, const float4& lo, const float4& hi) {
   const float dx = fmaxf(fmaxf(lo.x - c[0], c[0] - hi.x), 0.f);
   const float dy = fmaxf(fmaxf(lo.y - c[1], c[1] - hi.y), 0.f);

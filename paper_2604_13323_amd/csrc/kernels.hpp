@@ -543,8 +543,12 @@ __device__ __forceinline__ void persistent_body(const ProjArgs& a, double* smem)
 }
 
 
+template <class Model, class S, bool CYC>
+constexpr int persist_waves_v = std::is_same<S, float>::value && !CYC ? PersistWaves<Model>::value : 1;
+
 template <class Model, class IO, class S, bool CYC = false>
-__global__ void __launch_bounds__(256) k_project_persistent(ProjArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(persist_waves_v<Model, S, CYC>)))
+k_project_persistent(ProjArgs a) {
   extern __shared__ double smem[];
   persistent_body<Model, IO, S, CYC>(a, smem);
 }

@@ -83,6 +83,7 @@ struct TopoArm7Axis {
 
 struct TopoDual14Rel {
   static constexpr int family = 4;
+  static constexpr int persist_waves = 2;  // the FP32 stacked projection fits 256 registers per lane
   static constexpr int NJ = 14, NF = 2, NB = 1, M = 6;
   static constexpr int parent[NJ] = {-1, 0, 1, 2, 3, 4, 5, -1, 7, 8, 9, 10, 11, 12};
   static constexpr int jtype[NJ] = {REV, REV, REV, REV, REV, REV, REV, REV, REV, REV, REV, REV, REV, REV};
@@ -334,6 +335,7 @@ struct Kin {
   static constexpr int family = Topo::family;
   static constexpr bool broad_in_residual = true;  // broad_flag() tests the link bounds against the obstacle box
   static constexpr int NBLK = NB;                  // constraint blocks (the cyclic mode steps them in order)
+  static constexpr int persist_waves = PersistWaves<Topo>::value;
   static constexpr uint32_t ALL = ~uint32_t(0);
   static constexpr uint32_t block_rows_mask(int b) { return KI::brmask(b); }
   static constexpr uint32_t DROPPABLE = KI::drop_rows();  // rows a lane may drop (see the header)
