@@ -925,7 +925,73 @@ struct Kin {
           for (int k = 0; k < 3; ++k) cb[k] += X.p[k];
           const float r2 = bs.w * bs.w;
           const int s0 = K.sph_begin[l], ns = K.sph_begin[l + 1] - s0;
-          // exact tests of the link against the clusters of slot b that some lane found overlapping
+          // exact tests of the link against cluster cc (obstacles rg), in all L lanes of the group
+          auto pairs = [&](int cc, int2 rg) {
+            const int no = rg.y - rg.x;
+            if constexpr (L <= 16) {
+              // each sphere's centre once, tested against the cluster's box first (the box bounds
+              // the obstacle spheres with a margin far above FP32 rounding, so a sphere farther
+              // than its radius from it overlaps none of them); the group's lanes split the
+              // obstacles of the spheres that pass
+              const float4 clo = K.clus_lo[cc], chi = K.clus_hi[cc];
+              for (int si = 0; si < ns; ++si) {
+                const float4 sp = sph[s0 + si];
+                const float lp[3] = {sp.x, sp.y, sp.z};
+                float w[3];
+                matvec3(X.R, lp, w);
+                const float c[3] = {w[0] + X.p[0], w[1] + X.p[1], w[2] + X.p[2]};
+                if (box_dist2(c, clo, chi) > sp.w * sp.w) continue;
+                for (int oi = t; oi < no; oi += L) {
+                  const float4 ob = obs[rg.x + oi];
+                  const float dx = c[0] - ob.x, dy = c[1] - ob.y, dz = c[2] - ob.z;
+                  const float rr = sp.w + ob.w;
+                  hit = hit || (dx * dx + dy * dy + dz * dz < rr * rr);
+                }
+              }
+            } else if (slots != nullptr && ns <= L) {
+              // a wave per configuration: lane t transforms sphere t and tests it against the
+              // cluster's box; the candidates' centres go to the wave's LDS slots in rank order
+              // and the lanes split the (candidate, obstacle) pairs
+              const float4 clo = K.clus_lo[cc], chi = K.clus_hi[cc];
+              bool cand = false;
+              float4 cs = make_float4(0.f, 0.f, 0.f, 0.f);
+              if (t < ns) {
+                const float4 sp = sph[s0 + t];
+                const float lp[3] = {sp.x, sp.y, sp.z};
+                float w[3];
+                matvec3(X.R, lp, w);
+                const float c[3] = {w[0] + X.p[0], w[1] + X.p[1], w[2] + X.p[2]};
+                cand = box_dist2(c, clo, chi) <= sp.w * sp.w;
+                cs = make_float4(c[0], c[1], c[2], sp.w);
+              }
+              const uint64_t cm = (uint64_t(__ballot(cand)) >> shift) & gmask;
+              if (cand) slots[__popcll(cm & ((uint64_t(1) << t) - 1))] = cs;
+              const int np = __popcll(cm) * no;
+              for (int pi = t; pi < np; pi += L) {
+                const int k = pi / no, oi = pi - k * no;
+                const float4 c = slots[k];
+                const float4 ob = obs[rg.x + oi];
+                const float dx = c.x - ob.x, dy = c.y - ob.y, dz = c.z - ob.z;
+                const float rr = c.w + ob.w;
+                hit = hit || (dx * dx + dy * dy + dz * dz < rr * rr);
+              }
+            } else {
+              // a wave per configuration: the link's sphere-obstacle pairs flattened over the lanes
+              const int np = ns * no;
+              for (int pi = t; pi < np; pi += L) {
+                const int si = pi / no, oi = pi - si * no;
+                const float4 sp = sph[s0 + si];
+                const float4 ob = obs[rg.x + oi];
+                const float lp[3] = {sp.x, sp.y, sp.z};
+                float w[3];
+                matvec3(X.R, lp, w);
+                const float dx = w[0] + X.p[0] - ob.x, dy = w[1] + X.p[1] - ob.y, dz = w[2] + X.p[2] - ob.z;
+                const float rr = sp.w + ob.w;
+                hit = hit || (dx * dx + dy * dy + dz * dz < rr * rr);
+              }
+            }
+          };
+          // the clusters of slot b that some lane of the group found overlapping
           auto process = [&](int b, bool ov) {
             uint64_t m = (uint64_t(__ballot(ov)) >> shift) & gmask;
             while (m) {  // the same list in all L lanes
@@ -938,71 +1004,21 @@ struct Kin {
               } else {
                 rg = K.clus_range[cc];
               }
-              const int no = rg.y - rg.x;
-              if constexpr (L <= 16) {
-                // each sphere's centre once, tested against the cluster's box first (the box bounds
-                // the obstacle spheres with a margin far above FP32 rounding, so a sphere farther
-                // than its radius from it overlaps none of them); the group's lanes split the
-                // obstacles of the spheres that pass
-                const float4 clo = K.clus_lo[cc], chi = K.clus_hi[cc];
-                for (int si = 0; si < ns; ++si) {
-                  const float4 sp = sph[s0 + si];
-                  const float lp[3] = {sp.x, sp.y, sp.z};
-                  float w[3];
-                  matvec3(X.R, lp, w);
-                  const float c[3] = {w[0] + X.p[0], w[1] + X.p[1], w[2] + X.p[2]};
-                  if (box_dist2(c, clo, chi) > sp.w * sp.w) continue;
-                  for (int oi = t; oi < no; oi += L) {
-                    const float4 ob = obs[rg.x + oi];
-                    const float dx = c[0] - ob.x, dy = c[1] - ob.y, dz = c[2] - ob.z;
-                    const float rr = sp.w + ob.w;
-                    hit = hit || (dx * dx + dy * dy + dz * dz < rr * rr);
-                  }
-                }
-              } else if (slots != nullptr && ns <= L) {
-                // a wave per configuration: lane t transforms sphere t and tests it against the
-                // cluster's box; the candidates' centres go to the wave's LDS slots in rank order
-                // and the lanes split the (candidate, obstacle) pairs
-                const float4 clo = K.clus_lo[cc], chi = K.clus_hi[cc];
-                bool cand = false;
-                float4 cs = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (t < ns) {
-                  const float4 sp = sph[s0 + t];
-                  const float lp[3] = {sp.x, sp.y, sp.z};
-                  float w[3];
-                  matvec3(X.R, lp, w);
-                  const float c[3] = {w[0] + X.p[0], w[1] + X.p[1], w[2] + X.p[2]};
-                  cand = box_dist2(c, clo, chi) <= sp.w * sp.w;
-                  cs = make_float4(c[0], c[1], c[2], sp.w);
-                }
-                const uint64_t cm = (uint64_t(__ballot(cand)) >> shift) & gmask;
-                if (cand) slots[__popcll(cm & ((uint64_t(1) << t) - 1))] = cs;
-                const int np = __popcll(cm) * no;
-                for (int pi = t; pi < np; pi += L) {
-                  const int k = pi / no, oi = pi - k * no;
-                  const float4 c = slots[k];
-                  const float4 ob = obs[rg.x + oi];
-                  const float dx = c.x - ob.x, dy = c.y - ob.y, dz = c.z - ob.z;
-                  const float rr = c.w + ob.w;
-                  hit = hit || (dx * dx + dy * dy + dz * dz < rr * rr);
-                }
-              } else {
-                // a wave per configuration: the link's sphere-obstacle pairs flattened over the lanes
-                const int np = ns * no;
-                for (int pi = t; pi < np; pi += L) {
-                  const int si = pi / no, oi = pi - si * no;
-                  const float4 sp = sph[s0 + si];
-                  const float4 ob = obs[rg.x + oi];
-                  const float lp[3] = {sp.x, sp.y, sp.z};
-                  float w[3];
-                  matvec3(X.R, lp, w);
-                  const float dx = w[0] + X.p[0] - ob.x, dy = w[1] + X.p[1] - ob.y, dz = w[2] + X.p[2] - ob.z;
-                  const float rr = sp.w + ob.w;
-                  hit = hit || (dx * dx + dy * dy + dz * dz < rr * rr);
-                }
-              }
+              pairs(cc, rg);
             }
           };
+          if constexpr (L == 1) {
+            // one lane per configuration: the link's bound against the boxes of the cluster groups
+            // first, then against the clusters of the groups it reaches (a group's box contains its
+            // clusters' boxes, in FP32 too, so no overlapping cluster is skipped)
+            for (int g = 0; g < K.n_sup; ++g) {
+              if (box_dist2(cb, K.sup_lo[g], K.sup_hi[g]) > r2) continue;
+              const int2 gr = K.sup_range[g];
+              for (int c = gr.x; c < gr.y; ++c)
+                if (box_dist2(cb, K.clus_lo[c], K.clus_hi[c]) <= r2) pairs(c, K.clus_range[c]);
+            }
+            return;
+          }
           uint32_t own = 0;  // bit b: this lane's cluster of slot b overlaps the link's bound
           sfor<0, PB>([&](auto BI) {
             constexpr int bi = decltype(BI)::value;
