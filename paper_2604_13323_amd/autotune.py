@@ -6,7 +6,10 @@ the occupancy limit) and lanes per configuration. The best shape depends on the 
 LDS footprint), the precision mode and the batch. `mc_autotune_project` times every candidate on a
 real batch with HIP events, checks that all candidates give bit-identical outputs (the launch shape
 must not change results) and keeps the fastest in the problem, where `project_batch` with the
-variant and shape left at auto picks it up.
+variant and shape left at auto picks it up. Where the batch's exact-check queue is long (most
+configurations near the obstacles), a second stage times the lane groups of the exact check (1, 2,
+4, 8 or 16 lanes per configuration) in that shape and keeps the fastest for the problem's later
+calls; the chosen size is the shape's `check_lanes` (0 when the queue was short).
 """
 from __future__ import annotations
 
