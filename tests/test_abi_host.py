@@ -62,7 +62,7 @@ def test_autotune_candidates_and_host_errors(L):
     n = L.mc_autotune_candidates(None)
     shapes = (binding.LaunchShape * n)()
     assert L.mc_autotune_candidates(shapes) == n and n >= 7
-    assert all(s.waves_per_block in (1, 2, 4) and s.lanes_per_config == 1 for s in shapes)
+    assert all(s.waves_per_block in (1, 2, 4) and s.lanes_per_config == 1 and s.check_lanes == 0 for s in shapes)
     out = binding.LaunchShape()
     assert L.mc_tuned_shape(None, 0, 0, ctypes.byref(out)) == MC_ERR_INVALID_ARG
     assert L.mc_queue_counts(None, (ctypes.c_uint32 * 4)()) == MC_ERR_INVALID_ARG
@@ -70,6 +70,7 @@ def test_autotune_candidates_and_host_errors(L):
     o = binding.Opts()
     L.mc_default_opts(ctypes.byref(o))
     assert L.mc_autotune_project(None, 1, None, 1, ctypes.byref(o), 1, None, None, None) == MC_ERR_INVALID_ARG
+    assert L.mc_set_check_lanes(None, 4) == MC_ERR_INVALID_ARG
 
 
 def test_create_rejects_malformed_blobs_on_the_host(L):
