@@ -263,6 +263,9 @@ bool validate_family(const HScene& s, std::string& err) {
 // ---- obstacle clusters: recursive median split on the widest axis, <= kClusterSize each
 constexpr int kClusterSize = 16;
 constexpr double kBoundMargin = 1e-4;  // metres added to every bound (covers FP32 rounding)
+// exact-check tail grid: workgroups of 256 per CU (its short-queue path takes up to 4 waves' work
+// items per workgroup)
+constexpr int kCheckTailBlocksPerCu = 4;
 constexpr int kGroupSize = 8;          // clusters per group (the second level of boxes)
 static_assert((MAXC + kGroupSize - 1) / kGroupSize <= MAXSUP, "group table too small");
 
@@ -1257,7 +1260,7 @@ static mc_status project_impl(const mc_problem* p, int64_t n, const void* q_in, 
     if (tail && (e = (cyc ? ops->project_tail_cyclic : ops->project_tail)(a, p->n_cu, s)) != hipSuccess)
       return hip_fail(e, "project_batch: FP64 tail launch");
     // 4 workgroups of 4 waves per CU: 4,096 work items per round (blocks without work leave at once)
-    if (ctail && (e = ops->check_tail(a, 4 * p->n_cu, s)) != hipSuccess) return hip_fail(e, "project_batch: check tail launch");
+    if (ctail && (e = ops->check_tail(a, kCheckTailBlocksPerCu * p->n_cu, s)) != hipSuccess) return hip_fail(e, "project_batch: check tail launch");
   }
   if (geo_ok) {
     hipLaunchKernelGGL(k_geo_ok, dim3((n_geo + 255) / 256), dim3(256), 0, s, n_geo, geo_offsets, n, status, verdict, geo_ok);
@@ -1327,7 +1330,7 @@ mc_status check_batch(const mc_problem* p, int64_t n, const void* q, int64_t ld,
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "check_batch: reset");
   if ((e = ops->check_broad(c, a.chk_count, a.chk_idx, a.chk_q, a.defer_cap, s)) != hipSuccess)
     return hip_fail(e, "check_batch: broad-phase launch");
-  if ((e = ops->check_tail(a, 4 * p->n_cu, s)) != hipSuccess) return hip_fail(e, "check_batch: exact-check launch");
+  if ((e = ops->check_tail(a, kCheckTailBlocksPerCu * p->n_cu, s)) != hipSuccess) return hip_fail(e, "check_batch: exact-check launch");
   return MC_OK;
 }
 
@@ -1794,7 +1797,7 @@ mc_status mc_autotune_project(mc_problem* p, int64_t n, const void* q_in, int64_
   if (rc == MC_OK && opts->check_collision &&
       (e = hipMemcpy(&queued, p->counter + 3, sizeof queued, hipMemcpyDeviceToHost)) != hipSuccess)
     rc = hip_fail(e, "mc_autotune_project: read the check queue length");
-  if (rc == MC_OK && opts->check_collision && int64_t(queued) > int64_t(4) * 4 * p->n_cu) {
+  if (rc == MC_OK && opts->check_collision && int64_t(queued) > int64_t(4) * kCheckTailBlocksPerCu * p->n_cu) {
     const int32_t saved = p->check_long;
     int32_t best_l = 0;
     float best_l_ms = 0.f;
